@@ -1,0 +1,148 @@
+/*
+ * sssp.h -- C ABI of the MI355X (gfx950) delta-stepping single-source
+ * shortest-path library.
+ *
+ * The method is the linear-algebra delta-stepping of Sridhar et al.,
+ * "Delta-stepping SSSP: from Vertices and Edges to GraphBLAS Implementations"
+ * (IPDPSW 2019): the adjacency matrix is split into light and heavy parts
+ * (Sec. IV-A), buckets are selected by the mask i*delta <= t < (i+1)*delta
+ * (Sec. IV-B), and each processing phase is a masked min-plus product
+ * t_Req = A_L^T (t o t_Bi) or A_H^T (t o S) merged into t by an element-wise
+ * min (Sec. IV-C, IV-D; Fig. 1 left).
+ *
+ * Conventions for every entry point
+ *   - Return value: an sssp_status. Nothing throws across this boundary.
+ *   - Pointers documented as "device" are HIP device pointers on the device
+ *     that is current when sssp_create is called; "host" pointers are ordinary
+ *     host memory. The caller owns every pointer it passes; the library never
+ *     frees caller memory and keeps no caller pointer after a call returns.
+ *   - stream: a hipStream_t passed as void* (NULL = the null stream). Work is
+ *     enqueued on it; calls documented as synchronising wait for it.
+ *   - On error, outputs are unspecified and a handle stays valid (except that
+ *     sssp_create stores NULL into *out).
+ *   - A handle is not thread-safe: calls on one handle must not overlap.
+ */
+#ifndef SSSP_MI355X_H
+#define SSSP_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SSSP_OK = 0,
+  SSSP_ERR_INVALID_ARGUMENT = 1, /* null pointer, bad sizes, malformed CSR, bad delta or source */
+  SSSP_ERR_INVALID_WEIGHT = 2,   /* a weight that is zero, negative, NaN or infinite */
+  SSSP_ERR_OUT_OF_MEMORY = 3,    /* device allocation failed */
+  SSSP_ERR_DEVICE = 4,           /* a HIP runtime error or an aborted device schedule */
+  SSSP_ERR_OVERFLOW = 5,         /* a reachable vertex's distance is not representable */
+  SSSP_ERR_NO_FORWARD = 6,       /* sssp_backward before any successful sssp_solve */
+  SSSP_ERR_UNSUPPORTED = 7,      /* a size or type outside what this build handles */
+} sssp_status;
+
+typedef enum {
+  SSSP_WEIGHT_U32 = 0, /* uint32 weights >= 1; distances uint32, UINT32_MAX = unreachable */
+  SSSP_WEIGHT_F32 = 1, /* float weights, finite and > 0; distances float, +inf = unreachable */
+} sssp_weight_type;
+
+/*
+ * Directed weighted graph as the CSR of its adjacency matrix A: row u holds the
+ * out-edges of vertex u, A(u, v) = weight of u -> v (Sec. II, graph as a matrix).
+ * All arrays are DEVICE memory, caller-owned, read only, and only borrowed for
+ * the duration of sssp_create (the handle keeps its own copy).
+ *   n        number of vertices, 1 <= n < 2^31
+ *   m        number of edges, 0 <= m < 2^32
+ *   row_ptr  int64 [n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = m
+ *   col_idx  int32 [m], 0 <= col_idx[e] < n; parallel edges and self-loops are
+ *            accepted (parallel edges act as their minimum, self-loops never
+ *            improve a distance because weights are positive)
+ *   weights  [m] of wtype
+ */
+typedef struct {
+  int64_t n;
+  int64_t m;
+  const int64_t *row_ptr;
+  const int32_t *col_idx;
+  const void *weights;
+  int32_t wtype; /* sssp_weight_type */
+} sssp_graph;
+
+/* Counters of the last sssp_solve, summed over its sources. */
+typedef struct {
+  uint64_t sources;      /* solves performed */
+  uint64_t buckets;      /* bucket rounds (non-empty buckets processed) */
+  uint64_t light_phases; /* light relaxation phases (inner-loop iterations) */
+  uint64_t heavy_phases; /* heavy relaxation phases */
+  uint64_t far_phases;   /* redistributions of far-future buckets */
+  uint64_t light_edges;  /* light edges scanned */
+  uint64_t heavy_edges;  /* heavy edges scanned */
+  uint64_t improvements; /* relaxations that lowered a tentative distance */
+  uint64_t barriers;     /* device-wide synchronisations */
+} sssp_stats;
+
+/* Schedule parameters (every field 0 = library default). */
+typedef struct {
+  int32_t workgroups_per_cu; /* resident workgroups per compute unit for the solver (default 2) */
+  int32_t ring_buckets;      /* buckets held in the near ring, power of two in [2, 64] (default: fit max weight) */
+} sssp_tuning;
+
+typedef struct sssp_handle sssp_handle;
+
+/*
+ * sssp_create -- prepare a graph and delta for repeated solves.
+ *   Validates the CSR and the weights, then splits A into its light and heavy
+ *   parts, A_L = A o (0 < A <= delta) and A_H = A o (A > delta) (Sec. IV-A;
+ *   Fig. 1 left, first two lines; light(v) and heavy(v) of Sec. III-A), stored as
+ *   one row-partitioned copy: each row holds its light edges, then its heavy ones.
+ *   delta: for SSSP_WEIGHT_U32 an integer in [1, 2^32-1]; for SSSP_WEIGHT_F32 the
+ *   threshold is (float)delta, which must be finite and > 0, and the total weight
+ *   divided by delta must stay below 2^30 (bucket indices are 32-bit).
+ *   stream: enqueue work here; the call synchronises it before returning.
+ *   out: host pointer receiving the new handle (library-owned; free with
+ *   sssp_destroy), NULL on error.
+ *   Errors: INVALID_ARGUMENT (null pointers, n/m/CSR, delta), INVALID_WEIGHT,
+ *   UNSUPPORTED (sizes), OUT_OF_MEMORY, DEVICE.
+ */
+sssp_status sssp_create(const sssp_graph *g, double delta, void *stream, sssp_handle **out);
+
+/*
+ * sssp_solve -- shortest-path distances from k sources, one after another.
+ *   For source s = sources[r], row r of dist receives d_s(v) = the minimum over
+ *   directed paths from s to v of the path weight (Sec. III, problem statement),
+ *   computed by delta-stepping (Fig. 1): buckets B_i selected by
+ *   i*delta <= t < (i+1)*delta, light phases t_Req = A_L^T (t o t_Bi) repeated
+ *   while vertices re-enter B_i, then one heavy phase t_Req = A_H^T (t o S).
+ *   Path weights add left to right in the weight type: exact integers for u32
+ *   (a distance above 2^32-2 is SSSP_ERR_OVERFLOW), binary32 round-to-nearest-even
+ *   for f32 (a sum that rounds to +inf is SSSP_ERR_OVERFLOW). The result does not
+ *   depend on the order of relaxations.
+ *   sources: HOST int32 [k], each in [0, n).  k >= 1.
+ *   dist: DEVICE, caller-owned, [k][n] of the weight type (uint32 or float),
+ *   row-major; fully overwritten. d(s) = 0; unreachable = UINT32_MAX / +inf.
+ *   stream: the call synchronises it before returning (to report overflow).
+ *   Errors: INVALID_ARGUMENT, OVERFLOW, DEVICE.
+ */
+sssp_status sssp_solve(sssp_handle *h, const int32_t *sources, int32_t k, void *dist, void *stream);
+
+/* Counters of the last successful sssp_solve (host struct, caller-owned). */
+sssp_status sssp_last_stats(const sssp_handle *h, sssp_stats *out);
+
+/* Replace the schedule parameters of a handle (host struct; copied). */
+sssp_status sssp_set_tuning(sssp_handle *h, const sssp_tuning *t);
+
+/* Vertex and edge counts and the weight type of a handle (host out-pointers, any may be NULL). */
+sssp_status sssp_graph_info(const sssp_handle *h, int64_t *n, int64_t *m, int32_t *wtype);
+
+/* Release a handle and all device memory it owns. NULL is a no-op. */
+void sssp_destroy(sssp_handle *h);
+
+/* Static, human-readable name of a status. */
+const char *sssp_status_string(sssp_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSSP_MI355X_H */

@@ -1,0 +1,311 @@
+// Host side of the C ABI declared in include/sssp.h: argument checks, device
+// memory of a handle, the create-time validation and split, and the solve
+// launch with its status read-back.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "sssp.h"
+#include "sssp_internal.h"
+
+struct sssp_handle {
+  int device = 0;
+  int64_t n = 0, m = 0;
+  int32_t wtype = 0;
+  double delta = 0;
+  uint32_t delta_u = 0;
+  float delta_f = 0;
+  uint32_t wmax_bits = 0;
+  int grid = 0;
+  int cus = 0;
+  int occupancy = 0;
+  sssp_tuning tuning{};
+  sssp::Params p{};
+  uint32_t* perm = nullptr;
+  int32_t* src_dev = nullptr;
+  int32_t src_cap = 0;
+  int32_t* src_host = nullptr;   // pinned staging for sources
+  sssp::Ctl* ctl_host = nullptr;  // pinned copy of the control block
+  sssp_stats last{};
+  bool solved = false;
+  bool stamps_dirty = false;
+};
+
+namespace {
+
+constexpr uint32_t kEpochLimit = 1u << 30;
+
+sssp_status from_hip(hipError_t e) {
+  if (e == hipSuccess) return SSSP_OK;
+  if (e == hipErrorOutOfMemory) return SSSP_ERR_OUT_OF_MEMORY;
+  return SSSP_ERR_DEVICE;
+}
+
+#define SSSP_TRY(expr)                           \
+  do {                                           \
+    sssp_status _st = from_hip(expr);            \
+    if (_st != SSSP_OK) return _st;              \
+  } while (0)
+
+template <class T>
+hipError_t dalloc(T** p, size_t count) {
+  if (count == 0) count = 1;
+  return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+void free_handle(sssp_handle* h) {
+  if (!h) return;
+  sssp::Params& p = h->p;
+  void* dev[] = {const_cast<uint32_t*>(p.off), const_cast<uint32_t*>(p.split), const_cast<uint64_t*>(p.edges),
+                 p.qstamp, p.sstamp, p.bstamp, p.fstamp, p.ovf_at, p.front[0], p.front[1], p.slist, p.bins,
+                 p.far[0], p.far[1], p.ctl, h->perm, h->src_dev};
+  for (void* q : dev)
+    if (q) (void)hipFree(q);
+  if (h->src_host) (void)hipHostFree(h->src_host);
+  if (h->ctl_host) (void)hipHostFree(h->ctl_host);
+  delete h;
+}
+
+uint32_t pow2_at_least(uint32_t x) {
+  uint32_t r = 1;
+  while (r < x) r <<= 1;
+  return r;
+}
+
+sssp_status configure_grid(sssp_handle* h) {
+  int per_cu = h->tuning.workgroups_per_cu > 0 ? h->tuning.workgroups_per_cu : 2;
+  if (per_cu > h->occupancy) per_cu = h->occupancy;
+  if (per_cu < 1) return SSSP_ERR_UNSUPPORTED;
+  h->grid = per_cu * h->cus;
+  return SSSP_OK;
+}
+
+sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, sssp_handle* h) {
+  SSSP_TRY(hipGetDevice(&h->device));
+  hipDeviceProp_t prop;
+  SSSP_TRY(hipGetDeviceProperties(&prop, h->device));
+  if (!prop.cooperativeLaunch) return SSSP_ERR_UNSUPPORTED;
+  h->cus = prop.multiProcessorCount;
+  SSSP_TRY(sssp::solver_occupancy(g->wtype, &h->occupancy));
+
+  const int64_t n = g->n, m = g->m;
+  h->n = n;
+  h->m = m;
+  h->wtype = g->wtype;
+  h->delta = delta;
+  if (g->wtype == SSSP_WEIGHT_U32) h->delta_u = static_cast<uint32_t>(delta);
+  else h->delta_f = static_cast<float>(delta);
+
+  // 1. validate the CSR and the weights on the device
+  uint32_t* scratch = nullptr;  // [0] status, [1] max weight bits, [2..3] fp64 weight total
+  SSSP_TRY(dalloc(&scratch, 4));
+  hipError_t e = hipMemsetAsync(scratch, 0, 4 * sizeof(uint32_t), stream);
+  if (e == hipSuccess)
+    e = sssp::launch_validate(g->row_ptr, g->col_idx, g->weights, g->wtype, n, m, scratch, scratch + 1,
+                              reinterpret_cast<double*>(scratch + 2), stream);
+  uint32_t res[4] = {0, 0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(res, scratch, sizeof(res), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  (void)hipFree(scratch);
+  SSSP_TRY(e);
+  if (res[0] & (sssp::kBadRowPtr | sssp::kBadCol)) return SSSP_ERR_INVALID_ARGUMENT;
+  if (res[0] & sssp::kBadWeight) return SSSP_ERR_INVALID_WEIGHT;
+  h->wmax_bits = res[1];
+  double wsum;
+  std::memcpy(&wsum, res + 2, sizeof(double));
+
+  // 2. bucket geometry: ring large enough that one relaxation never jumps past it
+  double span;  // max weight / delta
+  if (g->wtype == SSSP_WEIGHT_U32) {
+    span = static_cast<double>(h->wmax_bits) / static_cast<double>(h->delta_u);
+  } else {
+    float wmax;
+    std::memcpy(&wmax, &h->wmax_bits, sizeof(float));
+    const double dd = static_cast<double>(h->delta_f);
+    span = static_cast<double>(wmax) / dd;
+    // every finite fp32 path sum is at most the total weight (times a rounding
+    // factor well below 2): bucket indices then stay below 2^29
+    if (wsum * 2.0 / dd >= static_cast<double>(1u << 29)) return SSSP_ERR_UNSUPPORTED;
+  }
+  uint32_t ring = h->tuning.ring_buckets > 0 ? static_cast<uint32_t>(h->tuning.ring_buckets)
+                                              : pow2_at_least(static_cast<uint32_t>(std::min(span + 2.0, 64.0)));
+  if (ring < 2) ring = 2;
+  if (ring > sssp::kRingMax || (ring & (ring - 1))) return SSSP_ERR_INVALID_ARGUMENT;
+
+  // 3. device memory
+  sssp::Params& p = h->p;
+  p.n = static_cast<uint32_t>(n);
+  p.ring = ring;
+  p.ring_mask = ring - 1;
+  p.wtype = static_cast<uint32_t>(g->wtype);
+  p.delta_u = h->delta_u;
+  p.delta_d = static_cast<double>(h->delta_f);
+  p.inv_delta_d = h->delta_f > 0 ? 1.0 / static_cast<double>(h->delta_f) : 0.0;
+  const size_t un = static_cast<size_t>(n), um = static_cast<size_t>(m);
+  uint32_t *off = nullptr, *split = nullptr;
+  uint64_t* edges = nullptr;
+  SSSP_TRY(dalloc(&off, un + 1));
+  p.off = off;
+  SSSP_TRY(dalloc(&split, un));
+  p.split = split;
+  SSSP_TRY(dalloc(&edges, um));
+  p.edges = edges;
+  SSSP_TRY(dalloc(&h->perm, um));
+  SSSP_TRY(dalloc(&p.qstamp, un));
+  SSSP_TRY(dalloc(&p.sstamp, un));
+  SSSP_TRY(dalloc(&p.bstamp, un));
+  SSSP_TRY(dalloc(&p.fstamp, un));
+  SSSP_TRY(dalloc(&p.ovf_at, un));
+  SSSP_TRY(dalloc(&p.front[0], un));
+  SSSP_TRY(dalloc(&p.front[1], un));
+  SSSP_TRY(dalloc(&p.slist, un));
+  SSSP_TRY(dalloc(&p.bins, un * ring));
+  SSSP_TRY(dalloc(&p.far[0], un));
+  SSSP_TRY(dalloc(&p.far[1], un));
+  SSSP_TRY(dalloc(&p.ctl, 1));
+  SSSP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->ctl_host), sizeof(sssp::Ctl), hipHostMallocDefault));
+  SSSP_TRY(hipMemsetAsync(p.qstamp, 0, un * sizeof(uint32_t), stream));
+  SSSP_TRY(hipMemsetAsync(p.sstamp, 0, un * sizeof(uint32_t), stream));
+  SSSP_TRY(hipMemsetAsync(p.fstamp, 0, un * sizeof(uint32_t), stream));
+  SSSP_TRY(hipMemsetAsync(p.ovf_at, 0, un, stream));
+  SSSP_TRY(hipMemsetAsync(p.ctl, 0, sizeof(sssp::Ctl), stream));
+  SSSP_TRY(sssp::launch_ctl_reset(p.ctl, 1, stream));
+
+  // 4. light/heavy split (A_L, A_H)
+  SSSP_TRY(sssp::launch_split(g->row_ptr, g->col_idx, g->weights, g->wtype, n, h->delta_u, h->delta_f, off, split,
+                              edges, h->perm, stream));
+  SSSP_TRY(hipStreamSynchronize(stream));
+  return configure_grid(h);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sssp_status_string(sssp_status s) {
+  switch (s) {
+    case SSSP_OK: return "ok";
+    case SSSP_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case SSSP_ERR_INVALID_WEIGHT: return "invalid weight";
+    case SSSP_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case SSSP_ERR_DEVICE: return "device error";
+    case SSSP_ERR_OVERFLOW: return "distance overflow";
+    case SSSP_ERR_NO_FORWARD: return "no forward solve";
+    case SSSP_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+sssp_status sssp_create(const sssp_graph* g, double delta, void* stream, sssp_handle** out) {
+  if (!out) return SSSP_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  if (!g || !g->row_ptr) return SSSP_ERR_INVALID_ARGUMENT;
+  if (g->wtype != SSSP_WEIGHT_U32 && g->wtype != SSSP_WEIGHT_F32) return SSSP_ERR_INVALID_ARGUMENT;
+  if (g->n < 1 || g->m < 0) return SSSP_ERR_INVALID_ARGUMENT;
+  if (g->n >= (int64_t(1) << 31) || g->m >= (int64_t(1) << 32) - 1) return SSSP_ERR_UNSUPPORTED;
+  if (g->m > 0 && (!g->col_idx || !g->weights)) return SSSP_ERR_INVALID_ARGUMENT;
+  if (!std::isfinite(delta) || !(delta > 0)) return SSSP_ERR_INVALID_ARGUMENT;
+  if (g->wtype == SSSP_WEIGHT_U32) {
+    if (delta != std::floor(delta) || delta < 1.0 || delta > 4294967295.0) return SSSP_ERR_INVALID_ARGUMENT;
+  } else {
+    const float df = static_cast<float>(delta);
+    if (!std::isfinite(df) || !(df > 0.0f)) return SSSP_ERR_INVALID_ARGUMENT;
+  }
+  sssp_handle* h = new (std::nothrow) sssp_handle();
+  if (!h) return SSSP_ERR_OUT_OF_MEMORY;
+  const sssp_status st = create_impl(g, delta, static_cast<hipStream_t>(stream), h);
+  if (st != SSSP_OK) {
+    (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    free_handle(h);
+    return st;
+  }
+  *out = h;
+  return SSSP_OK;
+}
+
+sssp_status sssp_solve(sssp_handle* h, const int32_t* sources, int32_t k, void* dist, void* stream) {
+  if (!h || !sources || k < 1 || !dist) return SSSP_ERR_INVALID_ARGUMENT;
+  for (int32_t r = 0; r < k; ++r)
+    if (sources[r] < 0 || sources[r] >= h->n) return SSSP_ERR_INVALID_ARGUMENT;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SSSP_TRY(hipSetDevice(h->device));
+  if (k > h->src_cap) {
+    if (h->src_dev) (void)hipFree(h->src_dev);
+    if (h->src_host) (void)hipHostFree(h->src_host);
+    h->src_dev = nullptr;
+    h->src_host = nullptr;
+    h->src_cap = 0;
+    SSSP_TRY(dalloc(&h->src_dev, static_cast<size_t>(k)));
+    SSSP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->src_host), sizeof(int32_t) * k, hipHostMallocDefault));
+    h->src_cap = k;
+  }
+  std::memcpy(h->src_host, sources, sizeof(int32_t) * k);
+  SSSP_TRY(hipMemcpyAsync(h->src_dev, h->src_host, sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
+  int reset_epochs = 0;
+  if (h->stamps_dirty) {
+    const size_t un = static_cast<size_t>(h->n);
+    SSSP_TRY(hipMemsetAsync(h->p.qstamp, 0, un * sizeof(uint32_t), s));
+    SSSP_TRY(hipMemsetAsync(h->p.sstamp, 0, un * sizeof(uint32_t), s));
+    SSSP_TRY(hipMemsetAsync(h->p.fstamp, 0, un * sizeof(uint32_t), s));
+    SSSP_TRY(hipMemsetAsync(h->p.ovf_at, 0, un, s));
+    reset_epochs = 1;
+  }
+  SSSP_TRY(sssp::launch_ctl_reset(h->p.ctl, reset_epochs, s));
+  SSSP_TRY(sssp::launch_solver(h->p, h->src_dev, k, static_cast<uint32_t*>(dist), h->grid, s));
+  SSSP_TRY(hipMemcpyAsync(h->ctl_host, h->p.ctl, sizeof(sssp::Ctl), hipMemcpyDeviceToHost, s));
+  SSSP_TRY(hipStreamSynchronize(s));
+  const sssp::Ctl& c = *h->ctl_host;
+  // tags grow by one per step; clear the stamps long before they could wrap
+  h->stamps_dirty = c.abort || c.step > kEpochLimit || c.round > kEpochLimit || c.far_epoch > kEpochLimit;
+  if (c.abort) return SSSP_ERR_DEVICE;
+  h->last.sources = c.sources;
+  h->last.buckets = c.buckets;
+  h->last.light_phases = c.light_phases;
+  h->last.heavy_phases = c.heavy_phases;
+  h->last.far_phases = c.far_phases;
+  h->last.light_edges = c.light_edges;
+  h->last.heavy_edges = c.heavy_edges;
+  h->last.improvements = c.improvements;
+  h->last.barriers = c.barriers;
+  if (c.ovf_real) return SSSP_ERR_OVERFLOW;
+  h->solved = true;
+  return SSSP_OK;
+}
+
+sssp_status sssp_last_stats(const sssp_handle* h, sssp_stats* out) {
+  if (!h || !out) return SSSP_ERR_INVALID_ARGUMENT;
+  *out = h->last;
+  return SSSP_OK;
+}
+
+sssp_status sssp_set_tuning(sssp_handle* h, const sssp_tuning* t) {
+  if (!h || !t) return SSSP_ERR_INVALID_ARGUMENT;
+  if (t->workgroups_per_cu < 0 || t->ring_buckets < 0) return SSSP_ERR_INVALID_ARGUMENT;
+  if (t->ring_buckets != 0 && t->ring_buckets != static_cast<int32_t>(h->p.ring))
+    return SSSP_ERR_UNSUPPORTED;  // the ring is sized at create time
+  const sssp_tuning old = h->tuning;
+  h->tuning = *t;
+  const sssp_status st = configure_grid(h);
+  if (st != SSSP_OK) {
+    h->tuning = old;
+    (void)configure_grid(h);
+  }
+  return st;
+}
+
+sssp_status sssp_graph_info(const sssp_handle* h, int64_t* n, int64_t* m, int32_t* wtype) {
+  if (!h) return SSSP_ERR_INVALID_ARGUMENT;
+  if (n) *n = h->n;
+  if (m) *m = h->m;
+  if (wtype) *wtype = h->wtype;
+  return SSSP_OK;
+}
+
+void sssp_destroy(sssp_handle* h) {
+  if (!h) return;
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  free_handle(h);
+}
+
+}  // extern "C"

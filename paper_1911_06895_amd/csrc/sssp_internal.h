@@ -1,0 +1,109 @@
+// Internal declarations shared by the kernels and the host library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sssp {
+
+constexpr int kWG = 256;               // threads per workgroup: 4 wave64s
+constexpr uint32_t kRingMax = 64;      // near-bucket ring capacity
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// Tentative distances are kept as 32-bit patterns: uint32 values for integer
+// weights, and for fp32 weights the IEEE bits of non-negative floats, which
+// order exactly like the floats themselves (+0.0 = 0, +inf = 0x7F800000).
+constexpr uint32_t kInfU32 = 0xFFFFFFFFu;
+constexpr uint32_t kInfF32 = 0x7F800000u;
+
+enum Action : uint32_t {
+  kActLight = 1,  // light phase over the current frontier
+  kActHeavy = 2,  // heavy phase over S
+  kActFar = 3,    // move far-future vertices into the ring
+  kActDone = 4,
+  kActOverflowCheck = 5,
+};
+
+enum InKind : uint32_t { kInF0 = 0, kInF1 = 1, kInBin = 2 };
+
+// Device control block of the persistent solver. The barrier words and the
+// epoch counters persist across launches; the schedule fields are set by the
+// barrier leader (the last workgroup to arrive) before it releases the others,
+// so every workgroup reads the same schedule.
+struct Ctl {
+  // grid barrier
+  uint32_t bar_arrive;
+  uint32_t bar_gen;
+  uint32_t abort;
+  uint32_t source_index;
+  // schedule
+  uint32_t action;
+  uint32_t bucket;       // current bucket i
+  uint32_t in_kind;      // InKind of the current input list
+  uint32_t in_count;     // entries in the current input list
+  uint32_t out_buf;      // frontier buffer receiving re-inserted vertices (0/1)
+  uint32_t far_base;     // ring base used by a far redistribution
+  uint32_t step;         // frontier de-duplication tag (monotone across solves)
+  uint32_t round;        // S de-duplication tag (monotone across solves)
+  uint32_t far_epoch;    // far-list de-duplication tag (monotone across solves)
+  uint32_t far_cur;      // which far list is current (0/1)
+  uint32_t far_min;      // lower bound on the bucket of any far vertex
+  uint32_t far_min_next;
+  // bucket bounds of the current bucket: [lo, hi) as integers or doubles
+  uint64_t lo_u, hi_u;
+  double lo_d, hi_d;
+  // counters
+  uint32_t fcount[2];
+  uint32_t scount;
+  uint32_t farcount[2];
+  uint32_t ovf_seen;     // some candidate did not fit the distance type
+  uint32_t ovf_real;     // a reachable vertex has an unrepresentable distance
+  uint32_t pad;
+  uint32_t bincount[kRingMax];
+  // statistics (summed over sources)
+  unsigned long long sources, buckets, light_phases, heavy_phases, far_phases;
+  unsigned long long light_edges, heavy_edges, improvements, barriers;
+};
+
+struct Params {
+  uint32_t n;
+  uint32_t ring;        // ring size, power of two
+  uint32_t ring_mask;
+  uint32_t wtype;       // 0 = u32, 1 = f32
+  uint32_t delta_u;     // u32 delta
+  double delta_d;       // f32: (double)(float)delta
+  double inv_delta_d;   // f32: 1 / delta_d (an estimate; bucket indices are corrected exactly)
+  const uint32_t* off;    // [n+1] row starts of the split copy
+  const uint32_t* split;  // [n] end of the light range of each row
+  const uint64_t* edges;  // [m] (destination | weight bits << 32)
+  uint32_t* qstamp;       // [n] frontier tag of the last push
+  uint32_t* sstamp;       // [n] round tag of the last S insertion
+  uint32_t* bstamp;       // [n] lowest bucket a vertex was filed under (this solve)
+  uint32_t* fstamp;       // [n] far epoch of the last far insertion
+  uint8_t* ovf_at;        // [n] a candidate for this vertex did not fit
+  uint32_t* front[2];     // [n] frontier buffers
+  uint32_t* slist;        // [n] S
+  uint32_t* bins;         // [ring][n]
+  uint32_t* far[2];       // [n] far lists
+  Ctl* ctl;
+};
+
+// launchers (sssp_kernels.hip)
+hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, const void* w, int wtype, int64_t n,
+                           int64_t m, uint32_t* status, uint32_t* wmax_bits, double* wsum, hipStream_t s);
+hipError_t launch_split(const int64_t* row_ptr, const int32_t* col, const void* w, int wtype, int64_t n,
+                        uint32_t delta_u, float delta_f, uint32_t* off, uint32_t* split, uint64_t* edges,
+                        uint32_t* perm, hipStream_t s);
+hipError_t solver_occupancy(int wtype, int* blocks_per_cu);
+hipError_t launch_ctl_reset(Ctl* c, int reset_epochs, hipStream_t s);
+hipError_t launch_solver(const Params& p, const int32_t* sources, int k, uint32_t* dist, int grid,
+                         hipStream_t s);
+
+// validation status bits
+enum : uint32_t {
+  kBadRowPtr = 1u,
+  kBadCol = 2u,
+  kBadWeight = 4u,
+};
+
+}  // namespace sssp

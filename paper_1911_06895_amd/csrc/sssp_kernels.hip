@@ -1,0 +1,733 @@
+// HIP kernels for gfx950 (CDNA4, wave64): graph validation, the light/heavy
+// split of the adjacency matrix, and the persistent delta-stepping solver.
+//
+// The solver is one cooperative launch per call. Every step of the method
+// (a light phase, a heavy phase, a far-bucket redistribution) is processed by
+// all resident workgroups, and steps are separated by a device-wide barrier
+// whose last arriving workgroup (the leader) computes the next step -- the
+// loop tests of Fig. 1 ("while t_Bi != 0", "while (t >= i*delta) != 0") -- and
+// publishes it before releasing the others. No host round trip is needed
+// between steps.
+#include "sssp_internal.h"
+
+namespace sssp {
+namespace {
+
+// ------------------------------------------------------------------ helpers
+
+template <typename T>
+__device__ inline T ld_agent(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ inline void st_agent(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// number of set bits of `mask` in lanes below this one
+__device__ inline uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+__device__ inline uint32_t lane() { return __lane_id(); }
+
+// Append `v` to list[*count] for every lane with `pred`; one atomic per wave.
+__device__ inline void push_wave(uint32_t* list, uint32_t* count, bool pred, uint32_t v) {
+  const uint64_t mask = __ballot(pred);
+  if (mask == 0) return;
+  const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
+  uint32_t base = 0;
+  if (static_cast<int>(lane()) == leader) base = atomicAdd(count, static_cast<uint32_t>(__popcll(mask)));
+  base = __shfl(base, leader);
+  if (pred) list[base + lanes_below(mask)] = v;
+}
+
+// Inclusive prefix sum across a wave64.
+__device__ inline uint32_t wave_scan(uint32_t x) {
+  const uint32_t l = lane();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d);
+    if (l >= static_cast<uint32_t>(d)) x += y;
+  }
+  return x;
+}
+
+// Exclusive prefix sum across the workgroup; returns the total in *total.
+__device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t* total, uint32_t* s_wsum) {
+  const uint32_t inc = wave_scan(x);
+  const uint32_t w = threadIdx.x >> 6;
+  if (lane() == 63) s_wsum[w] = inc;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kWG / 64; ++k) {
+    const uint32_t s = s_wsum[k];
+    before += (k < w) ? s : 0u;
+    all += s;
+  }
+  *total = all;
+  return before + inc - x;
+}
+
+// ------------------------------------------------------------------ weights
+
+// x (+) w in the weight type, and the bucket index floor(x / delta).
+struct WeightU32 {
+  static constexpr uint32_t kInf = kInfU32;
+  __device__ static bool add(uint32_t t, uint32_t w, uint32_t* out) {
+    const uint64_t s = static_cast<uint64_t>(t) + static_cast<uint64_t>(w);
+    *out = static_cast<uint32_t>(s);
+    return s <= 0xFFFFFFFEull;  // 2^32-1 is reserved for "unreachable"
+  }
+  __device__ static uint32_t bucket(uint32_t x, const Params& p) { return x / p.delta_u; }
+};
+
+struct WeightF32 {
+  static constexpr uint32_t kInf = kInfF32;
+  __device__ static bool add(uint32_t t, uint32_t w, uint32_t* out) {
+    const float s = __fadd_rn(__uint_as_float(t), __uint_as_float(w));
+    *out = __float_as_uint(s);
+    return *out < kInfF32;  // non-negative operands: the sum is finite or +inf
+  }
+  // floor(x / delta) exactly: the estimate from one rounded product is off by
+  // at most one, and j * delta is exact in double for j < 2^29.
+  __device__ static uint32_t bucket(uint32_t x, const Params& p) {
+    const double d = static_cast<double>(__uint_as_float(x));
+    double j = floor(d * p.inv_delta_d);
+    if (j * p.delta_d > d) j -= 1.0;
+    else if ((j + 1.0) * p.delta_d <= d) j += 1.0;
+    return static_cast<uint32_t>(j);
+  }
+};
+
+// ------------------------------------------------------------------ schedule
+
+struct Sched {
+  uint32_t action, bucket, in_kind, in_count, out_buf, step, round, far_epoch, far_cur, far_base;
+  uint64_t lo_u, hi_u;
+  double lo_d, hi_d;
+};
+
+template <class W>
+__device__ inline bool in_bucket(uint32_t x, const Sched& s);
+template <>
+__device__ inline bool in_bucket<WeightU32>(uint32_t x, const Sched& s) {
+  return x >= s.lo_u && x < s.hi_u;
+}
+template <>
+__device__ inline bool in_bucket<WeightF32>(uint32_t x, const Sched& s) {
+  const double d = static_cast<double>(__uint_as_float(x));
+  return d >= s.lo_d && d < s.hi_d;
+}
+
+__device__ inline void load_sched(Ctl* c, Sched* s) {
+  if (threadIdx.x == 0) {
+    s->action = ld_agent(&c->action);
+    s->bucket = ld_agent(&c->bucket);
+    s->in_kind = ld_agent(&c->in_kind);
+    s->in_count = ld_agent(&c->in_count);
+    s->out_buf = ld_agent(&c->out_buf);
+    s->step = ld_agent(&c->step);
+    s->round = ld_agent(&c->round);
+    s->far_epoch = ld_agent(&c->far_epoch);
+    s->far_cur = ld_agent(&c->far_cur);
+    s->far_base = ld_agent(&c->far_base);
+    s->lo_u = ld_agent(&c->lo_u);
+    s->hi_u = ld_agent(&c->hi_u);
+    s->lo_d = ld_agent(&c->lo_d);
+    s->hi_d = ld_agent(&c->hi_d);
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ barrier
+
+constexpr uint32_t kSpinLimit = 1u << 22;  // several seconds of waiting: only a broken schedule gets there
+
+// Device-wide barrier over all (co-resident) workgroups. The last workgroup to
+// arrive runs `leader` (every thread of it) before releasing the others.
+// Returns false when the schedule was aborted (a wait exceeded kSpinLimit).
+template <class F>
+__device__ bool grid_sync(Ctl* c, F&& leader) {
+  __shared__ uint32_t s_is_leader;
+  __shared__ uint32_t s_ok;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  uint32_t gen = 0;
+  if (threadIdx.x == 0) {
+    gen = ld_agent(&c->bar_gen);
+    const uint32_t prev = __hip_atomic_fetch_add(&c->bar_arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    const bool last = prev == gridDim.x - 1;
+    s_is_leader = last ? 1u : 0u;
+    uint32_t ok = 1;
+    if (!last) {
+      uint32_t it = 0;
+      while (__hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        if (++it > kSpinLimit || ld_agent(&c->abort) != 0u) {
+          st_agent(&c->abort, 1u);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (s_is_leader) {
+    leader();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      atomicAdd(&c->barriers, 1ull);
+      st_agent(&c->bar_arrive, 0u);
+      __hip_atomic_store(&c->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  const bool ok = s_ok != 0u;
+  __syncthreads();
+  return ok;
+}
+
+// ------------------------------------------------------------------ leader decisions
+
+template <class W>
+__device__ void set_bucket(const Params& p, uint32_t i) {
+  Ctl* c = p.ctl;
+  st_agent(&c->bucket, i);
+  if (p.wtype == 0) {
+    st_agent(&c->lo_u, static_cast<uint64_t>(i) * p.delta_u);
+    st_agent(&c->hi_u, static_cast<uint64_t>(i + 1ull) * p.delta_u);
+  } else {
+    st_agent(&c->lo_d, static_cast<double>(i) * p.delta_d);
+    st_agent(&c->hi_d, static_cast<double>(i) * p.delta_d + p.delta_d);
+  }
+}
+
+// Next bucket to process: the first non-empty ring slot among the `len`
+// buckets starting at `from`, unless far-future vertices may come first.
+template <class W>
+__device__ void choose_next(const Params& p, uint32_t from, uint32_t len) {
+  Ctl* c = p.ctl;
+  __shared__ uint32_t s_jn;
+  if (threadIdx.x < 64) {
+    const uint32_t l = threadIdx.x;
+    bool nonempty = false;
+    if (l < len) nonempty = ld_agent(&c->bincount[(from + l) & p.ring_mask]) != 0u;
+    const uint64_t m = __ballot(nonempty);
+    if (l == 0) s_jn = m ? from + static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(m)) - 1) : kNone;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t jn = s_jn;
+    const uint32_t fc = ld_agent(&c->farcount[ld_agent(&c->far_cur)]);
+    const uint32_t fmin = ld_agent(&c->far_min);
+    if (fc > 0 && (jn == kNone || fmin <= jn)) {
+      st_agent(&c->action, static_cast<uint32_t>(kActFar));
+      st_agent(&c->far_base, jn == kNone ? fmin : min(jn, fmin));
+      st_agent(&c->in_count, fc);
+    } else if (jn == kNone) {
+      st_agent(&c->action, static_cast<uint32_t>(ld_agent(&c->ovf_seen) ? kActOverflowCheck : kActDone));
+    } else {
+      set_bucket<W>(p, jn);
+      st_agent(&c->action, static_cast<uint32_t>(kActLight));
+      st_agent(&c->in_kind, static_cast<uint32_t>(kInBin));
+      st_agent(&c->in_count, ld_agent(&c->bincount[jn & p.ring_mask]));
+      st_agent(&c->out_buf, 0u);
+      atomicAdd(&c->buckets, 1ull);
+    }
+  }
+}
+
+template <class W>
+__device__ void leader_start(const Params& p, uint32_t* t, uint32_t src) {
+  Ctl* c = p.ctl;
+  if (threadIdx.x < kRingMax) st_agent(&c->bincount[threadIdx.x], 0u);
+  if (threadIdx.x == 0) {
+    atomicAdd(&c->sources, 1ull);
+    st_agent(&c->fcount[0], 0u);
+    st_agent(&c->fcount[1], 0u);
+    st_agent(&c->scount, 0u);
+    st_agent(&c->farcount[0], 0u);
+    st_agent(&c->farcount[1], 0u);
+    st_agent(&c->far_cur, 0u);
+    st_agent(&c->far_min, kNone);
+    st_agent(&c->far_min_next, kNone);
+    st_agent(&c->ovf_seen, 0u);
+    st_agent(&c->step, ld_agent(&c->step) + 1u);
+    st_agent(&c->round, ld_agent(&c->round) + 1u);
+    // t = inf, t[s] = 0 (Fig. 1 left); the source is the only member of B_0
+    st_agent(&t[src], 0u);
+    st_agent(&p.bstamp[src], 0u);
+    st_agent(&p.bins[0], src);  // ring slot of bucket 0, first entry
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st_agent(&c->bincount[0], 1u);
+    set_bucket<W>(p, 0u);
+    st_agent(&c->action, static_cast<uint32_t>(kActLight));
+    st_agent(&c->in_kind, static_cast<uint32_t>(kInBin));
+    st_agent(&c->in_count, 1u);
+    st_agent(&c->out_buf, 0u);
+    atomicAdd(&c->buckets, 1ull);
+  }
+}
+
+template <class W>
+__device__ void leader_after_light(const Params& p, const Sched& s) {
+  Ctl* c = p.ctl;
+  if (threadIdx.x == 0) {
+    atomicAdd(&c->light_phases, 1ull);
+    st_agent(&c->step, s.step + 1u);
+    const uint32_t n_next = ld_agent(&c->fcount[s.out_buf]);
+    if (s.in_kind == kInBin) st_agent(&c->bincount[s.bucket & p.ring_mask], 0u);
+    else st_agent(&c->fcount[s.in_kind], 0u);
+    if (n_next > 0) {  // while t_Bi != 0: another light phase on the re-inserted vertices
+      st_agent(&c->action, static_cast<uint32_t>(kActLight));
+      st_agent(&c->in_kind, s.out_buf);
+      st_agent(&c->in_count, n_next);
+      st_agent(&c->out_buf, 1u - s.out_buf);
+    } else {  // B_i is empty: one heavy phase over S
+      st_agent(&c->action, static_cast<uint32_t>(kActHeavy));
+      st_agent(&c->in_count, ld_agent(&c->scount));
+    }
+  }
+}
+
+template <class W>
+__device__ void leader_after_heavy(const Params& p, const Sched& s) {
+  Ctl* c = p.ctl;
+  __shared__ uint32_t s_redo;
+  if (threadIdx.x == 0) {
+    atomicAdd(&c->heavy_phases, 1ull);
+    st_agent(&c->step, s.step + 1u);
+    st_agent(&c->round, s.round + 1u);
+    st_agent(&c->scount, 0u);
+    // A heavy request can only fall back into bucket i through fp32 rounding
+    // (t(u) + w > (i+1)*delta in exact arithmetic); such vertices restart bucket i.
+    const uint32_t n_redo = ld_agent(&c->fcount[s.out_buf]);
+    s_redo = n_redo;
+    if (n_redo > 0) {
+      st_agent(&c->action, static_cast<uint32_t>(kActLight));
+      st_agent(&c->in_kind, s.out_buf);
+      st_agent(&c->in_count, n_redo);
+      st_agent(&c->out_buf, 1u - s.out_buf);
+    }
+  }
+  __syncthreads();
+  if (s_redo == 0) choose_next<W>(p, s.bucket + 1u, p.ring - 1u);
+}
+
+template <class W>
+__device__ void leader_after_far(const Params& p, const Sched& s) {
+  Ctl* c = p.ctl;
+  if (threadIdx.x == 0) {
+    atomicAdd(&c->far_phases, 1ull);
+    st_agent(&c->step, s.step + 1u);
+    st_agent(&c->farcount[s.far_cur], 0u);
+    st_agent(&c->far_cur, 1u - s.far_cur);
+    st_agent(&c->far_min, ld_agent(&c->far_min_next));
+    st_agent(&c->far_min_next, kNone);
+    st_agent(&c->far_epoch, s.far_epoch + 1u);
+  }
+  __syncthreads();
+  choose_next<W>(p, s.far_base, p.ring);
+}
+
+// ------------------------------------------------------------------ relaxation
+
+struct WgStats {
+  unsigned long long light_edges, heavy_edges, improvements;
+};
+
+// Append winners to the ring slot of their bucket: one atomic per distinct
+// bucket present in the wave.
+__device__ inline void push_ring(const Params& p, bool pred, uint32_t j, uint32_t v) {
+  bool pending = pred;
+  uint64_t mask = __ballot(pending);
+  while (mask) {
+    const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
+    const uint32_t jl = __shfl(j, leader);
+    const bool mine = pending && j == jl;
+    const uint64_t same = __ballot(mine);
+    uint32_t base = 0;
+    if (static_cast<int>(lane()) == leader) base = atomicAdd(&p.ctl->bincount[jl & p.ring_mask], static_cast<uint32_t>(__popcll(same)));
+    base = __shfl(base, leader);
+    if (mine) {
+      p.bins[static_cast<size_t>(jl & p.ring_mask) * p.n + base + lanes_below(same)] = v;
+      pending = false;
+    }
+    mask = __ballot(pending);
+  }
+}
+
+// One request (v, t(u) (+) w): t(v) = min(t(v), request) (Sec. III-C relax;
+// Sec. IV-C/IV-D t = min(t, t_Req)), then file v by the bucket of its new
+// tentative distance: back into the current bucket's frontier (the re-insertion
+// mask (i*delta <= t_Req < (i+1)*delta) o (t_Req < t) of Sec. IV-C), into the
+// ring of near buckets, or into the far list.
+template <class W>
+__device__ inline void relax(const Params& p, uint32_t* t, const Sched& s, bool active, uint32_t tu, uint32_t v,
+                             uint32_t w, uint32_t near_end, WgStats& st) {
+  bool win = false;
+  uint32_t cand = 0;
+  if (active) {
+    if (!W::add(tu, w, &cand)) {
+      p.ovf_at[v] = 1;
+      st_agent(&p.ctl->ovf_seen, 1u);
+    } else {
+      const uint32_t tv = t[v];  // may be stale, but never below the current value
+      if (cand < tv) win = cand < atomicMin(&t[v], cand);
+    }
+  }
+  uint32_t j = 0;
+  bool to_front = false, to_ring = false, to_far = false;
+  if (win) {
+    j = W::bucket(cand, p);
+    if (j <= s.bucket) to_front = atomicExch(&p.qstamp[v], s.step + 1u) != s.step + 1u;
+    else if (j < near_end) to_ring = atomicMin(&p.bstamp[v], j) > j;
+    else {
+      atomicMin(&p.ctl->far_min, j);
+      to_far = atomicExch(&p.fstamp[v], s.far_epoch) != s.far_epoch;
+    }
+  }
+  const uint64_t wins = __ballot(win);
+  if (lane() == 0) st.improvements += __popcll(wins);
+  push_wave(p.front[s.out_buf], &p.ctl->fcount[s.out_buf], to_front, v);
+  push_ring(p, to_ring, j, v);
+  push_wave(p.far[s.far_cur], &p.ctl->farcount[s.far_cur], to_far, v);
+}
+
+// One relaxation phase: every vertex u of the input list sends t(u) (+) w along
+// its light (kLight) or heavy out-edges -- the masked min-plus product
+// t_Req = A_L^T (t o t_Bi) or A_H^T (t o S) of Sec. IV-C/IV-D, fused with the
+// min-merge into t (the paper's fusion of the Hadamard product into vxm).
+// Edges are balanced over the workgroup: the degrees of up to 256 list entries
+// are prefix-summed in LDS and the lanes walk the concatenated edge ranges, so
+// consecutive lanes read consecutive edges of a row.
+template <class W, bool kLight>
+__device__ void phase(const Params& p, uint32_t* t, const Sched& s, WgStats& st) {
+  __shared__ uint32_t s_pref[kWG];
+  __shared__ uint32_t s_beg[kWG];
+  __shared__ uint32_t s_tu[kWG];
+  __shared__ uint32_t s_wsum[kWG / 64];
+
+  const bool from_bin = kLight && s.in_kind == kInBin;
+  const uint32_t* list = !kLight ? p.slist
+                         : from_bin ? p.bins + static_cast<size_t>(s.bucket & p.ring_mask) * p.n
+                                    : p.front[s.in_kind];
+  const uint32_t count = s.in_count;
+  const uint32_t near_end = s.bucket + p.ring;
+
+  for (uint32_t base = blockIdx.x * kWG; base < count; base += gridDim.x * kWG) {
+    const uint32_t k = base + threadIdx.x;
+    uint32_t beg = 0, deg = 0, tu = W::kInf, u = 0;
+    bool take = false;
+    if (k < count) {
+      u = list[k];
+      tu = ld_agent(&t[u]);
+      // a ring slot may hold vertices that have since moved to a lower bucket
+      take = !from_bin || in_bucket<W>(tu, s);
+      if (take) {
+        if (kLight) {
+          beg = p.off[u];
+          deg = p.split[u] - beg;
+        } else {
+          beg = p.split[u];
+          deg = p.off[u + 1] - beg;
+        }
+      }
+    }
+    if (kLight) {  // S = (S + t_Bi) > 0: each expanded vertex joins S once per round
+      bool to_s = false;
+      if (take && ld_agent(&p.sstamp[u]) != s.round) to_s = atomicExch(&p.sstamp[u], s.round) != s.round;
+      push_wave(p.slist, &p.ctl->scount, to_s, u);
+    }
+    uint32_t total;
+    const uint32_t excl = block_exclusive_scan(deg, &total, s_wsum);
+    s_pref[threadIdx.x] = excl;
+    s_beg[threadIdx.x] = beg;
+    s_tu[threadIdx.x] = tu;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (kLight) st.light_edges += total;
+      else st.heavy_edges += total;
+    }
+    const uint32_t rounds = (total + kWG - 1) / kWG;
+    for (uint32_t r = 0; r < rounds; ++r) {
+      const uint32_t e = r * kWG + threadIdx.x;
+      const bool active = e < total;
+      uint32_t owner = 0, v = 0, w = 0, tw = W::kInf;
+      if (active) {
+        uint32_t lo = 0, hi = kWG - 1;  // last entry whose range starts at or before e
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi + 1) >> 1;
+          if (s_pref[mid] <= e) lo = mid;
+          else hi = mid - 1;
+        }
+        owner = lo;
+        const uint64_t ed = p.edges[s_beg[owner] + (e - s_pref[owner])];
+        v = static_cast<uint32_t>(ed);
+        w = static_cast<uint32_t>(ed >> 32);
+        tw = s_tu[owner];
+      }
+      relax<W>(p, t, s, active, tw, v, w, near_end, st);
+    }
+    __syncthreads();
+  }
+}
+
+// Far-list redistribution: far vertices whose bucket is now within the ring
+// move into it; the rest move to the other far list.
+template <class W>
+__device__ void far_step(const Params& p, uint32_t* t, const Sched& s) {
+  const uint32_t count = s.in_count;
+  const uint32_t* list = p.far[s.far_cur];
+  const uint32_t nxt = 1u - s.far_cur;
+  const uint32_t near_end = s.far_base + p.ring;
+  const uint32_t iters = (count + gridDim.x * kWG - 1) / (gridDim.x * kWG);
+  for (uint32_t it = 0; it < iters; ++it) {
+    const uint32_t k = (it * gridDim.x + blockIdx.x) * kWG + threadIdx.x;
+    bool to_ring = false, to_far = false;
+    uint32_t v = 0, j = 0;
+    if (k < count) {
+      v = list[k];
+      // still only filed far (never moved into the ring since)?
+      if (ld_agent(&p.bstamp[v]) == kNone) {
+        j = W::bucket(ld_agent(&t[v]), p);
+        if (j < near_end) {
+          to_ring = atomicMin(&p.bstamp[v], j) > j;
+        } else {
+          atomicMin(&p.ctl->far_min_next, j);
+          to_far = atomicExch(&p.fstamp[v], s.far_epoch + 1u) != s.far_epoch + 1u;
+        }
+      }
+    }
+    push_ring(p, to_ring, j, v);
+    push_wave(p.far[nxt], &p.ctl->farcount[nxt], to_far, v);
+  }
+}
+
+// A candidate that did not fit marked its target; the distance of that target
+// is unrepresentable exactly when no other path reached it.
+template <class W>
+__device__ void overflow_step(const Params& p, uint32_t* t) {
+  for (uint32_t v = blockIdx.x * kWG + threadIdx.x; v < p.n; v += gridDim.x * kWG) {
+    if (p.ovf_at[v]) {
+      if (ld_agent(&t[v]) == W::kInf) st_agent(&p.ctl->ovf_real, 1u);
+      p.ovf_at[v] = 0;
+    }
+  }
+}
+
+template <class W>
+__global__ __launch_bounds__(kWG) void solver_kernel(Params p, const int32_t* sources, int k, uint32_t* dist) {
+  __shared__ Sched s;
+  WgStats st{0, 0, 0};
+  bool alive = true;
+  for (int r = 0; r < k && alive; ++r) {
+    uint32_t* t = dist + static_cast<size_t>(r) * p.n;
+    for (uint32_t v = blockIdx.x * kWG + threadIdx.x; v < p.n; v += gridDim.x * kWG) {
+      t[v] = W::kInf;
+      p.bstamp[v] = kNone;
+    }
+    const uint32_t src = static_cast<uint32_t>(sources[r]);
+    if (!grid_sync(p.ctl, [&] { leader_start<W>(p, t, src); })) { alive = false; break; }
+    for (;;) {
+      load_sched(p.ctl, &s);
+      const uint32_t a = s.action;
+      if (a == kActDone) break;
+      if (a == kActLight) {
+        phase<W, true>(p, t, s, st);
+        alive = grid_sync(p.ctl, [&] { leader_after_light<W>(p, s); });
+      } else if (a == kActHeavy) {
+        phase<W, false>(p, t, s, st);
+        alive = grid_sync(p.ctl, [&] { leader_after_heavy<W>(p, s); });
+      } else if (a == kActFar) {
+        far_step<W>(p, t, s);
+        alive = grid_sync(p.ctl, [&] { leader_after_far<W>(p, s); });
+      } else if (a == kActOverflowCheck) {
+        overflow_step<W>(p, t);
+        alive = grid_sync(p.ctl, [&] {
+          if (threadIdx.x == 0) st_agent(&p.ctl->action, static_cast<uint32_t>(kActDone));
+        });
+      } else {
+        alive = false;
+        if (threadIdx.x == 0) st_agent(&p.ctl->abort, 1u);
+      }
+      if (!alive) break;
+    }
+  }
+  // fold per-lane counters into the control block
+  unsigned long long le = st.light_edges, he = st.heavy_edges, im = st.improvements;
+  for (int d = 32; d > 0; d >>= 1) {
+    le += __shfl_down(le, d);
+    he += __shfl_down(he, d);
+    im += __shfl_down(im, d);
+  }
+  if (lane() == 0) {
+    if (le) atomicAdd(&p.ctl->light_edges, le);
+    if (he) atomicAdd(&p.ctl->heavy_edges, he);
+    if (im) atomicAdd(&p.ctl->improvements, im);
+  }
+}
+
+// ------------------------------------------------------------------ create-time kernels
+
+// CSR and weight validation; max weight (as bits: positive floats order like
+// their bit patterns) and the fp32 weight total for the bucket-range check.
+__global__ __launch_bounds__(kWG) void validate_kernel(const int64_t* rp, const int32_t* col, const uint32_t* wbits,
+                                                       int wtype, int64_t n, int64_t m, uint32_t* status,
+                                                       uint32_t* wmax_bits, double* wsum) {
+  uint32_t bad = 0, wmax = 0;
+  double sum = 0.0;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kWG;
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  for (int64_t u = i0; u <= n; u += stride) {
+    const int64_t a = rp[u];
+    if (u == 0 && a != 0) bad |= kBadRowPtr;
+    if (u == n && a != m) bad |= kBadRowPtr;
+    if (u < n && rp[u + 1] < a) bad |= kBadRowPtr;
+  }
+  for (int64_t e = i0; e < m; e += stride) {
+    const int32_t c = col[e];
+    if (c < 0 || c >= n) bad |= kBadCol;
+    const uint32_t wb = wbits[e];
+    if (wtype == 0) {
+      if (wb == 0) bad |= kBadWeight;
+    } else {
+      // reject -0.0 and negatives (sign bit), +0.0, and inf/NaN (exponent all ones)
+      if ((wb & 0x80000000u) || wb == 0 || (wb & 0x7F800000u) == 0x7F800000u) bad |= kBadWeight;
+      else sum += static_cast<double>(__uint_as_float(wb));
+    }
+    wmax = max(wmax, wb);
+  }
+  for (int d = 32; d > 0; d >>= 1) {
+    bad |= __shfl_down(bad, d);
+    wmax = max(wmax, __shfl_down(wmax, d));
+    sum += __shfl_down(sum, d);
+  }
+  if (lane() == 0) {
+    if (bad) atomicOr(status, bad);
+    if (wmax) atomicMax(wmax_bits, wmax);
+    if (sum != 0.0) atomicAdd(wsum, sum);
+  }
+}
+
+// Light/heavy split (Sec. IV-A): one wave per row writes the row's light edges
+// (w <= delta) first and its heavy edges (w > delta) after, each group in its
+// original order, as packed (destination | weight << 32) records; perm maps a
+// position back to the caller's edge index.
+__global__ __launch_bounds__(kWG) void split_kernel(const int64_t* rp, const int32_t* col, const uint32_t* wbits,
+                                                    int wtype, int64_t n, uint32_t delta_u, float delta_f,
+                                                    uint32_t* off, uint32_t* split, uint64_t* edges, uint32_t* perm) {
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x) >> 6;
+  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * kWG) >> 6;
+  const uint32_t l = lane();
+  for (int64_t u = wave; u < n; u += nwaves) {
+    const int64_t b = rp[u], e = rp[u + 1];
+    uint32_t nlight = 0;
+    for (int64_t x = b; x < e; x += 64) {
+      bool light = false;
+      if (x + l < e) {
+        const uint32_t wb = wbits[x + l];
+        light = wtype == 0 ? wb <= delta_u : __uint_as_float(wb) <= delta_f;
+      }
+      nlight += static_cast<uint32_t>(__popcll(__ballot(light)));
+    }
+    if (l == 0) {
+      off[u] = static_cast<uint32_t>(b);
+      split[u] = static_cast<uint32_t>(b) + nlight;
+      if (u == n - 1) off[n] = static_cast<uint32_t>(e);
+    }
+    uint32_t lpos = static_cast<uint32_t>(b), hpos = static_cast<uint32_t>(b) + nlight;
+    for (int64_t x = b; x < e; x += 64) {
+      const bool in = x + l < e;
+      bool light = false;
+      uint32_t wb = 0;
+      int32_t c = 0;
+      if (in) {
+        wb = wbits[x + l];
+        c = col[x + l];
+        light = wtype == 0 ? wb <= delta_u : __uint_as_float(wb) <= delta_f;
+      }
+      const uint64_t ml = __ballot(in && light);
+      const uint64_t mh = __ballot(in && !light);
+      if (in) {
+        const uint32_t pos = light ? lpos + lanes_below(ml) : hpos + lanes_below(mh);
+        edges[pos] = static_cast<uint64_t>(static_cast<uint32_t>(c)) | (static_cast<uint64_t>(wb) << 32);
+        perm[pos] = static_cast<uint32_t>(x + l);
+      }
+      lpos += static_cast<uint32_t>(__popcll(ml));
+      hpos += static_cast<uint32_t>(__popcll(mh));
+    }
+  }
+}
+
+// Prepare the control block for a launch: clear the counters and the abort
+// flag (and the epochs when the de-duplication stamps were just cleared).
+__global__ void ctl_reset_kernel(Ctl* c, int reset_epochs) {
+  if (threadIdx.x != 0) return;
+  c->bar_arrive = 0;
+  c->abort = 0;
+  c->ovf_real = 0;
+  c->sources = c->buckets = c->light_phases = c->heavy_phases = c->far_phases = 0;
+  c->light_edges = c->heavy_edges = c->improvements = c->barriers = 0;
+  if (reset_epochs) {
+    c->step = 0;
+    c->round = 0;
+    c->far_epoch = 1;  // stamps are zero: every tag starts above 0
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_ctl_reset(Ctl* c, int reset_epochs, hipStream_t s) {
+  hipLaunchKernelGGL(ctl_reset_kernel, dim3(1), dim3(64), 0, s, c, reset_epochs);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, const void* w, int wtype, int64_t n,
+                           int64_t m, uint32_t* status, uint32_t* wmax_bits, double* wsum, hipStream_t s) {
+  const int64_t work = m > n + 1 ? m : n + 1;
+  int64_t blocks = (work + kWG - 1) / kWG;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(validate_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kWG), 0, s, row_ptr, col,
+                     static_cast<const uint32_t*>(w), wtype, n, m, status, wmax_bits, wsum);
+  return hipGetLastError();
+}
+
+hipError_t launch_split(const int64_t* row_ptr, const int32_t* col, const void* w, int wtype, int64_t n,
+                        uint32_t delta_u, float delta_f, uint32_t* off, uint32_t* split, uint64_t* edges,
+                        uint32_t* perm, hipStream_t s) {
+  int64_t blocks = (n * 64 + kWG - 1) / kWG;
+  if (blocks > 16384) blocks = 16384;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(split_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kWG), 0, s, row_ptr, col,
+                     static_cast<const uint32_t*>(w), wtype, n, delta_u, delta_f, off, split, edges, perm);
+  return hipGetLastError();
+}
+
+hipError_t solver_occupancy(int wtype, int* blocks_per_cu) {
+  return wtype == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solver_kernel<WeightU32>, kWG, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solver_kernel<WeightF32>, kWG, 0);
+}
+
+hipError_t launch_solver(const Params& p, const int32_t* sources, int k, uint32_t* dist, int grid, hipStream_t s) {
+  Params pp = p;
+  const int32_t* src = sources;
+  int kk = k;
+  uint32_t* d = dist;
+  void* args[] = {&pp, &src, &kk, &d};
+  const void* fn = p.wtype == 0 ? reinterpret_cast<const void*>(solver_kernel<WeightU32>)
+                                : reinterpret_cast<const void*>(solver_kernel<WeightF32>);
+  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kWG), args, 0, s);
+}
+
+}  // namespace sssp

@@ -1,0 +1,212 @@
+"""Python binding of the C ABI in include/sssp.h (argument marshalling only).
+
+Every computation runs in libsssp.so (HIP kernels for gfx950); torch supplies
+device memory and the current HIP stream. There is no CPU fallback: if the
+library is missing, the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIBRARY = os.path.join(_PKG, "libsssp.so")
+
+SSSP_OK = 0
+SSSP_ERR_INVALID_ARGUMENT = 1
+SSSP_ERR_INVALID_WEIGHT = 2
+SSSP_ERR_OUT_OF_MEMORY = 3
+SSSP_ERR_DEVICE = 4
+SSSP_ERR_OVERFLOW = 5
+SSSP_ERR_NO_FORWARD = 6
+SSSP_ERR_UNSUPPORTED = 7
+
+SSSP_WEIGHT_U32 = 0
+SSSP_WEIGHT_F32 = 1
+
+EXPORTS = ("sssp_create", "sssp_solve", "sssp_last_stats", "sssp_set_tuning", "sssp_graph_info", "sssp_destroy",
+           "sssp_status_string")
+
+
+class SsspGraph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("weights", ctypes.c_void_p), ("wtype", ctypes.c_int32)]
+
+
+class SsspStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_uint64) for name in
+                ("sources", "buckets", "light_phases", "heavy_phases", "far_phases", "light_edges", "heavy_edges",
+                 "improvements", "barriers")]
+
+
+class SsspTuning(ctypes.Structure):
+    _fields_ = [("workgroups_per_cu", ctypes.c_int32), ("ring_buckets", ctypes.c_int32)]
+
+
+class SsspError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {sssp_status_string(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIBRARY) -> ctypes.CDLL:
+    """Load libsssp.so (built by paper_1911_06895_amd.build). Raises if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.sssp_create.argtypes = [ctypes.POINTER(SsspGraph), ctypes.c_double, P, ctypes.POINTER(P)]
+    lib.sssp_create.restype = ctypes.c_int
+    lib.sssp_solve.argtypes = [P, P, ctypes.c_int32, P, P]
+    lib.sssp_solve.restype = ctypes.c_int
+    lib.sssp_last_stats.argtypes = [P, ctypes.POINTER(SsspStats)]
+    lib.sssp_last_stats.restype = ctypes.c_int
+    lib.sssp_set_tuning.argtypes = [P, ctypes.POINTER(SsspTuning)]
+    lib.sssp_set_tuning.restype = ctypes.c_int
+    lib.sssp_graph_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_int32)]
+    lib.sssp_graph_info.restype = ctypes.c_int
+    lib.sssp_destroy.argtypes = [P]
+    lib.sssp_destroy.restype = None
+    lib.sssp_status_string.argtypes = [ctypes.c_int]
+    lib.sssp_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check(status: int, what: str):
+    if status != SSSP_OK:
+        raise SsspError(status, what)
+
+
+def sssp_status_string(status: int) -> str:
+    return load_library().sssp_status_string(int(status)).decode()
+
+
+def sssp_create(row_ptr, col_idx, weights, delta: float, stream=None) -> ctypes.c_void_p:
+    """row_ptr int64 [n+1], col_idx int32 [m], weights uint32|float32 [m]: torch tensors on the GPU."""
+    import torch
+
+    if weights.dtype == torch.int32 or weights.dtype == torch.uint32:
+        wtype = SSSP_WEIGHT_U32
+    elif weights.dtype == torch.float32:
+        wtype = SSSP_WEIGHT_F32
+    else:
+        raise TypeError(f"weights must be uint32 (or int32 bit patterns) or float32, got {weights.dtype}")
+    if row_ptr.dtype != torch.int64 or col_idx.dtype != torch.int32:
+        raise TypeError("row_ptr must be int64 and col_idx int32")
+    for t in (row_ptr, col_idx, weights):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("graph arrays must be contiguous GPU tensors")
+    n = row_ptr.numel() - 1
+    m = col_idx.numel()
+    if weights.numel() != m:
+        raise ValueError("weights and col_idx differ in length")
+    g = SsspGraph(n=n, m=m, row_ptr=row_ptr.data_ptr(), col_idx=col_idx.data_ptr() if m else None,
+                  weights=weights.data_ptr() if m else None, wtype=wtype)
+    h = ctypes.c_void_p()
+    _check(load_library().sssp_create(ctypes.byref(g), float(delta), _stream(stream), ctypes.byref(h)),
+           "sssp_create")
+    return h
+
+
+def sssp_solve(handle, sources, dist, stream=None) -> None:
+    """sources: host ints [k]; dist: GPU tensor [k, n] (uint32/int32 or float32), overwritten."""
+    src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32).reshape(-1))
+    if not dist.is_cuda or not dist.is_contiguous():
+        raise ValueError("dist must be a contiguous GPU tensor")
+    _check(load_library().sssp_solve(handle, src.ctypes.data_as(ctypes.c_void_p), int(src.size),
+                                     ctypes.c_void_p(dist.data_ptr()), _stream(stream)), "sssp_solve")
+
+
+def sssp_last_stats(handle) -> dict:
+    st = SsspStats()
+    _check(load_library().sssp_last_stats(handle, ctypes.byref(st)), "sssp_last_stats")
+    return {name: int(getattr(st, name)) for name, _ in SsspStats._fields_}
+
+
+def sssp_set_tuning(handle, workgroups_per_cu: int = 0, ring_buckets: int = 0) -> None:
+    t = SsspTuning(workgroups_per_cu=workgroups_per_cu, ring_buckets=ring_buckets)
+    _check(load_library().sssp_set_tuning(handle, ctypes.byref(t)), "sssp_set_tuning")
+
+
+def sssp_graph_info(handle) -> tuple[int, int, int]:
+    n, m, w = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+    _check(load_library().sssp_graph_info(handle, ctypes.byref(n), ctypes.byref(m), ctypes.byref(w)),
+           "sssp_graph_info")
+    return n.value, m.value, w.value
+
+
+def sssp_destroy(handle) -> None:
+    if handle:
+        load_library().sssp_destroy(handle)
+
+
+class DeltaStepping:
+    """Owns a handle for one graph and delta; graph given as numpy CSR arrays."""
+
+    def __init__(self, row_ptr: np.ndarray, col: np.ndarray, w: np.ndarray, delta: float, device="cuda"):
+        import torch
+
+        self.torch = torch
+        if w.dtype == np.uint32:
+            wt = torch.from_numpy(w.view(np.int32)).to(device)
+            self.out_dtype = torch.int32  # uint32 bit patterns
+        elif w.dtype == np.float32:
+            wt = torch.from_numpy(w).to(device)
+            self.out_dtype = torch.float32
+        else:
+            raise TypeError(f"unsupported weight dtype {w.dtype}")
+        rp = torch.from_numpy(np.ascontiguousarray(row_ptr, dtype=np.int64)).to(device)
+        ci = torch.from_numpy(np.ascontiguousarray(col, dtype=np.int32)).to(device)
+        self.n = int(row_ptr.shape[0] - 1)
+        self.m = int(col.shape[0])
+        self.device = device
+        self.handle = sssp_create(rp, ci, wt, delta)
+        torch.cuda.synchronize()
+
+    def solve(self, sources, out=None):
+        src = np.asarray(sources, dtype=np.int32).reshape(-1)
+        if out is None:
+            out = self.torch.empty((src.size, self.n), dtype=self.out_dtype, device=self.device)
+        sssp_solve(self.handle, src, out)
+        return out
+
+    def solve_numpy(self, sources) -> np.ndarray:
+        d = self.solve(sources).cpu().numpy()
+        return d.view(np.uint32) if self.out_dtype == self.torch.int32 else d
+
+    def stats(self) -> dict:
+        return sssp_last_stats(self.handle)
+
+    def set_tuning(self, **kw):
+        sssp_set_tuning(self.handle, **kw)
+
+    def close(self):
+        if self.handle:
+            sssp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Distances are unique (the minimum over paths of a fold that is monotone and
+non-decreasing), so every comparison is bit-exact: uint32 for integer weights
+and 0 ulp for fp32 weights. A nonzero fp32 difference would be reported with
+its size; the allowed relative tolerance 1e-6 is never used because none is seen.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_1911_06895_amd import graphs as G  # noqa: E402
+from paper_1911_06895_amd import sssp  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU-only hosts
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def _bits(a):
+    return a.view(np.uint32) if a.dtype == np.float32 else a
+
+
+def gpu_solve(g, delta, sources, tuning=None):
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, delta)
+    try:
+        if tuning:
+            solver.set_tuning(**tuning)
+        d = solver.solve_numpy(sources)
+        return d, solver.stats()
+    finally:
+        solver.close()
+
+
+def assert_exact(g, got, src, label=""):
+    want, rc = oracle.dijkstra(g, int(src))
+    assert rc == oracle.OK
+    if not np.array_equal(_bits(got), _bits(want)):
+        bad = np.nonzero(_bits(got) != _bits(want))[0]
+        detail = ""
+        if got.dtype == np.float32:
+            fin = np.isfinite(want[bad]) & np.isfinite(got[bad])
+            rel = np.abs(got[bad][fin].astype(np.float64) - want[bad][fin]) / np.maximum(want[bad][fin], 1e-30)
+            detail = f" max rel diff {rel.max() if rel.size else 'n/a'}"
+        raise AssertionError(f"{label} source {src}: {bad.size} vertices differ, first {bad[:5]}: "
+                             f"got {got[bad[:5]]} want {want[bad[:5]]}{detail}")
+
+
+def test_er_1024_all_deltas():
+    g = G.workload("er_n1024_m8192")
+    for delta in (1, 8, 32, 100, 1000, 100000):
+        got, st = gpu_solve(g, delta, [0])
+        assert_exact(g, got[0], 0, f"delta={delta}")
+        assert st["sources"] == 1
+
+
+def test_multi_source_rows():
+    g = G.workload("er_n1024_m8192")
+    srcs = [0, 5, 1023, 512, 5]
+    got, st = gpu_solve(g, 32, srcs)
+    for r, s in enumerate(srcs):
+        assert_exact(g, got[r], s)
+    assert st["sources"] == len(srcs)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_graphs_ragged(seed):
+    """Sizes that span several 256-entry tiles with a ragged tail, raw CSR (parallel
+    edges and self-loops kept), both weight types."""
+    r = G.rng_for(9000 + seed, G.S_STRUCT)
+    n = int(r.integers(300, 5000))
+    m = int(r.integers(n, 12 * n))
+    src = r.integers(0, n, size=m)
+    dst = r.integers(0, n, size=m)
+    if seed % 2 == 0:
+        w = r.integers(1, 1000, size=m).astype(np.uint32)
+        deltas = [1, 37, 256, 5000]
+    else:
+        w = np.exp(r.uniform(np.log(1e-2), np.log(1e2), size=m)).astype(np.float32)
+        deltas = [0.25, 1.0, 3.3, 0.07]  # two dyadic, two not (fp32 re-insertion path)
+    g = G.csr_from_edges(n, src, dst, w, dedup=seed % 3 != 0, drop_self_loops=seed % 3 != 0)
+    s = int(G.sources_with_outedges(g, 1, cfg=9000 + seed)[0])
+    for delta in deltas:
+        got, _ = gpu_solve(g, delta, [s])
+        assert_exact(g, got[0], s, f"seed={seed} delta={delta}")
+
+
+@pytest.mark.parametrize("delta", [8, 32, 128])
+def test_rmat_s14(delta):
+    g = G.rmat_graph(14, 16, cfg=2)
+    srcs = G.sources_with_outedges(g, 3, cfg=2)
+    got, st = gpu_solve(g, delta, srcs)
+    for r, s in enumerate(srcs):
+        assert_exact(g, got[r], s, f"rmat14 delta={delta}")
+    # each reached heavy edge is relaxed exactly once per solve (schedule invariant)
+    heavy = 0
+    light = 0
+    for r, s in enumerate(srcs):
+        reached = got[r] != 0xFFFFFFFF
+        src_of_edge = g.edge_src()
+        mask = reached[src_of_edge]
+        heavy += int((mask & (g.w > delta)).sum())
+        light += int((mask & (g.w <= delta)).sum())
+    assert st["heavy_edges"] == heavy
+    assert st["light_edges"] >= light
+
+
+def test_grid_many_buckets():
+    g = G.grid_graph(96, 96, cfg=3)
+    for delta in (50, 400):
+        got, st = gpu_solve(g, delta, [0])
+        assert_exact(g, got[0], 0, f"grid delta={delta}")
+        assert st["buckets"] >= len(np.unique(got[0] // delta))
+
+
+def test_far_list_path():
+    """Weights far larger than delta: the near ring (64 buckets) overflows into the far list."""
+    r = G.rng_for(9100, G.S_STRUCT)
+    n, m = 3000, 24000
+    g = G.csr_from_edges(n, r.integers(0, n, m), r.integers(0, n, m), r.integers(1, 10**6, m).astype(np.uint32))
+    got, st = gpu_solve(g, 1000, [7])
+    assert_exact(g, got[0], 7, "far")
+    assert st["far_phases"] > 0
+
+
+def test_fp32_loguniform_rmat():
+    g = G.rmat_graph(13, 16, cfg=41, weights="f32_loguniform", wlo=1e-2, whi=1e2)
+    srcs = G.sources_with_outedges(g, 2, cfg=41)
+    for delta in (0.5, 2.0, 0.3):
+        got, _ = gpu_solve(g, delta, srcs)
+        for r, s in enumerate(srcs):
+            assert_exact(g, got[r], s, f"f32 delta={delta}")
+
+
+def test_fp32_absorption_golden():
+    """The fp32 worked example: 2^24 + 1 rounds to 2^24 along the two-hop path."""
+    g = G.csr_from_edges(4, np.array([0, 1, 0, 2]), np.array([1, 2, 2, 3]),
+                         np.array([16777216.0, 1.0, 16777218.0, 2.0], dtype=np.float32), dedup=False)
+    got, _ = gpu_solve(g, 4.0, [0])
+    assert np.array_equal(got[0], np.array([0.0, 16777216.0, 16777216.0, 16777218.0], dtype=np.float32))
+
+
+def test_edge_cases():
+    # single vertex, no edges
+    g = G.Graph(n=1, row_ptr=np.zeros(2, dtype=np.int64), col=np.zeros(0, dtype=np.int32),
+                w=np.zeros(0, dtype=np.uint32))
+    got, st = gpu_solve(g, 5, [0])
+    assert got[0].tolist() == [0]
+    # source without out-edges: everything else unreachable
+    g = G.path_graph(50, np.arange(1, 50, dtype=np.uint32))
+    got, _ = gpu_solve(g, 3, [49])
+    assert got[0][49] == 0 and np.all(got[0][:49] == 0xFFFFFFFF)
+    got, _ = gpu_solve(g, 3, [0])
+    assert np.array_equal(got[0], np.concatenate([[0], np.cumsum(np.arange(1, 50))]).astype(np.uint32))
+    # largest representable distance 2^32 - 2
+    g = G.path_graph(3, np.array([2**31 - 1, 2**31 - 1], dtype=np.uint32))
+    got, _ = gpu_solve(g, 2**31, [0])
+    assert got[0].tolist() == [0, 2**31 - 1, 2**32 - 2]
+
+
+def test_overflow_is_reported():
+    g = G.path_graph(3, np.array([2**31, 2**31], dtype=np.uint32))
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, 2**31)
+    try:
+        with pytest.raises(sssp.SsspError) as e:
+            solver.solve([0])
+        assert e.value.status == sssp.SSSP_ERR_OVERFLOW
+        # an overflowing detour beside a representable path is fine
+    finally:
+        solver.close()
+    g = G.csr_from_edges(3, np.array([0, 0, 1]), np.array([1, 2, 2]),
+                         np.array([4_000_000_000, 5, 1_000_000_000], dtype=np.uint32))
+    got, _ = gpu_solve(g, 10, [0])
+    assert got[0].tolist() == [0, 4_000_000_000, 5]
+    g = G.path_graph(3, np.array([3e38, 3e38], dtype=np.float32))
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, 1e37)
+    try:
+        with pytest.raises(sssp.SsspError) as e:
+            solver.solve([0])
+        assert e.value.status == sssp.SSSP_ERR_OVERFLOW
+    finally:
+        solver.close()
+
+
+def _create_status(row_ptr, col, w, delta):
+    try:
+        h = sssp.sssp_create(torch.from_numpy(row_ptr).cuda(), torch.from_numpy(col).cuda(),
+                             torch.from_numpy(w).cuda(), delta)
+    except sssp.SsspError as e:
+        return e.status
+    sssp.sssp_destroy(h)
+    return sssp.SSSP_OK
+
+
+def test_invalid_inputs_rejected():
+    rp = np.array([0, 2, 3, 3], dtype=np.int64)
+    col = np.array([1, 2, 0], dtype=np.int32)
+    ok_w = np.array([1, 2, 3], dtype=np.int32)
+    assert _create_status(rp, col, ok_w, 2) == sssp.SSSP_OK
+    assert _create_status(rp, col, np.array([1, 0, 3], dtype=np.int32), 2) == sssp.SSSP_ERR_INVALID_WEIGHT
+    for bad in (0.0, -1.0, np.nan, np.inf, -0.0):
+        w = np.array([1.0, bad, 2.0], dtype=np.float32)
+        assert _create_status(rp, col, w, 2.0) == sssp.SSSP_ERR_INVALID_WEIGHT, bad
+    assert _create_status(rp, np.array([1, 3, 0], dtype=np.int32), ok_w, 2) == sssp.SSSP_ERR_INVALID_ARGUMENT
+    assert _create_status(rp, np.array([1, -1, 0], dtype=np.int32), ok_w, 2) == sssp.SSSP_ERR_INVALID_ARGUMENT
+    assert _create_status(np.array([0, 2, 1, 3], dtype=np.int64), col, ok_w, 2) == sssp.SSSP_ERR_INVALID_ARGUMENT
+    assert _create_status(np.array([1, 2, 3, 3], dtype=np.int64), col, ok_w, 2) == sssp.SSSP_ERR_INVALID_ARGUMENT
+    assert _create_status(np.array([0, 2, 3, 2], dtype=np.int64), col, ok_w, 2) == sssp.SSSP_ERR_INVALID_ARGUMENT
+    assert _create_status(rp, col, ok_w, 2.5) == sssp.SSSP_ERR_INVALID_ARGUMENT
+    assert _create_status(rp, col, ok_w, 0) == sssp.SSSP_ERR_INVALID_ARGUMENT
+    # fp32: total weight / delta must keep bucket indices below 2^29
+    assert _create_status(rp, col, np.array([1e20, 1.0, 1.0], dtype=np.float32), 1e-3) == sssp.SSSP_ERR_UNSUPPORTED
+    g = G.workload("er_n1024_m8192")
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, 32)
+    try:
+        for bad_src in ([-1], [1024], [0, 5000]):
+            with pytest.raises(sssp.SsspError) as e:
+                solver.solve(bad_src)
+            assert e.value.status == sssp.SSSP_ERR_INVALID_ARGUMENT
+        got = solver.solve_numpy([3])  # the handle stays usable after errors
+        assert_exact(g, got[0], 3)
+    finally:
+        solver.close()
+
+
+def test_tuning_variants_agree():
+    g = G.rmat_graph(12, 16, cfg=2)
+    s = int(G.sources_with_outedges(g, 1, cfg=3)[0])
+    for wpc in (1, 2, 4):
+        got, _ = gpu_solve(g, 16, [s], tuning={"workgroups_per_cu": wpc})
+        assert_exact(g, got[0], s, f"wg/cu={wpc}")
