@@ -80,12 +80,15 @@ typedef struct {
   uint64_t heavy_edges;  /* heavy edges scanned */
   uint64_t improvements; /* relaxations that lowered a tentative distance */
   uint64_t barriers;     /* device-wide synchronisations */
+  uint64_t trace_records; /* step records produced (see sssp_set_trace) */
 } sssp_stats;
 
 /* Schedule parameters (every field 0 = library default). */
 typedef struct {
-  int32_t workgroups_per_cu; /* resident workgroups per compute unit for the solver (default 2) */
+  int32_t workgroups_per_cu; /* resident 1024-thread workgroups per compute unit (default 1) */
   int32_t ring_buckets;      /* buckets held in the near ring, power of two in [2, 64] (default: fit max weight) */
+  int32_t inline_edges;      /* phases scanning at most this many edges (and at most 512 list entries)
+                                run on one workgroup without a device-wide barrier (default 4096) */
 } sssp_tuning;
 
 typedef struct sssp_handle sssp_handle;
@@ -98,7 +101,7 @@ typedef struct sssp_handle sssp_handle;
  *   one row-partitioned copy: each row holds its light edges, then its heavy ones.
  *   delta: for SSSP_WEIGHT_U32 an integer in [1, 2^32-1]; for SSSP_WEIGHT_F32 the
  *   threshold is (float)delta, which must be finite and > 0, and the total weight
- *   divided by delta must stay below 2^30 (bucket indices are 32-bit).
+ *   divided by delta must stay below 2^29 (bucket indices stay exact in fp64 products).
  *   stream: enqueue work here; the call synchronises it before returning.
  *   out: host pointer receiving the new handle (library-owned; free with
  *   sssp_destroy), NULL on error.
@@ -131,6 +134,19 @@ sssp_status sssp_last_stats(const sssp_handle *h, sssp_stats *out);
 
 /* Replace the schedule parameters of a handle (host struct; copied). */
 sssp_status sssp_set_tuning(sssp_handle *h, const sssp_tuning *t);
+
+/*
+ * sssp_set_trace -- attach a step trace (profiling aid; NULL/0 detaches).
+ *   device_buffer: DEVICE uint64 [2 * capacity], caller-owned, must stay valid
+ *   while attached. Every later sssp_solve writes one record per device-wide
+ *   step, from its start: word 0 = device wall clock (hipDeviceAttributeWallClockRate
+ *   ticks) when the step began; word 1 = (input entries << 32) | (bucket & 0xFFFFFF) << 8
+ *   | action (1 light phase, 2 heavy phase, 3 far redistribution, 4 done,
+ *   5 overflow check, 6 high-degree pieces of the previous phase; bit 0x80 set
+ *   when one workgroup ran the phase alone). Records past capacity are counted
+ *   in trace_records but not written.
+ */
+sssp_status sssp_set_trace(sssp_handle *h, uint64_t *device_buffer, int64_t capacity);
 
 /* Vertex and edge counts and the weight type of a handle (host out-pointers, any may be NULL). */
 sssp_status sssp_graph_info(const sssp_handle *h, int64_t *n, int64_t *m, int32_t *wtype);

@@ -29,11 +29,14 @@ struct sssp_handle {
   sssp_stats last{};
   bool solved = false;
   bool stamps_dirty = false;
+  unsigned long long* trace = nullptr;  // caller-owned device buffer (optional)
+  uint32_t trace_cap = 0;
 };
 
 namespace {
 
 constexpr uint32_t kEpochLimit = 1u << 30;
+constexpr uint32_t kDefaultInlineEdges = 4096;
 
 sssp_status from_hip(hipError_t e) {
   if (e == hipSuccess) return SSSP_OK;
@@ -58,7 +61,7 @@ void free_handle(sssp_handle* h) {
   sssp::Params& p = h->p;
   void* dev[] = {const_cast<uint32_t*>(p.off), const_cast<uint32_t*>(p.split), const_cast<uint64_t*>(p.edges),
                  p.qstamp, p.sstamp, p.bstamp, p.fstamp, p.ovf_at, p.front[0], p.front[1], p.slist, p.bins,
-                 p.far[0], p.far[1], p.ctl, h->perm, h->src_dev};
+                 p.far[0], p.far[1], p.hub, p.ctl, h->perm, h->src_dev};
   for (void* q : dev)
     if (q) (void)hipFree(q);
   if (h->src_host) (void)hipHostFree(h->src_host);
@@ -73,7 +76,7 @@ uint32_t pow2_at_least(uint32_t x) {
 }
 
 sssp_status configure_grid(sssp_handle* h) {
-  int per_cu = h->tuning.workgroups_per_cu > 0 ? h->tuning.workgroups_per_cu : 2;
+  int per_cu = h->tuning.workgroups_per_cu > 0 ? h->tuning.workgroups_per_cu : 1;
   if (per_cu > h->occupancy) per_cu = h->occupancy;
   if (per_cu < 1) return SSSP_ERR_UNSUPPORTED;
   h->grid = per_cu * h->cus;
@@ -156,6 +159,11 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   SSSP_TRY(dalloc(&p.bstamp, un));
   SSSP_TRY(dalloc(&p.fstamp, un));
   SSSP_TRY(dalloc(&p.ovf_at, un));
+  // each vertex appears at most once in a phase's list, so the pieces of its
+  // high-degree vertices number at most m / kPiece + m / kHub
+  p.hub_cap = static_cast<uint32_t>(um / sssp::kPiece + um / sssp::kHub + 16);
+  SSSP_TRY(dalloc(&p.hub, p.hub_cap));
+  p.inline_edges = h->tuning.inline_edges > 0 ? static_cast<uint32_t>(h->tuning.inline_edges) : kDefaultInlineEdges;
   SSSP_TRY(dalloc(&p.front[0], un));
   SSSP_TRY(dalloc(&p.front[1], un));
   SSSP_TRY(dalloc(&p.slist, un));
@@ -167,9 +175,9 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   SSSP_TRY(hipMemsetAsync(p.qstamp, 0, un * sizeof(uint32_t), stream));
   SSSP_TRY(hipMemsetAsync(p.sstamp, 0, un * sizeof(uint32_t), stream));
   SSSP_TRY(hipMemsetAsync(p.fstamp, 0, un * sizeof(uint32_t), stream));
-  SSSP_TRY(hipMemsetAsync(p.ovf_at, 0, un, stream));
+  SSSP_TRY(hipMemsetAsync(p.ovf_at, 0, un * sizeof(uint32_t), stream));
   SSSP_TRY(hipMemsetAsync(p.ctl, 0, sizeof(sssp::Ctl), stream));
-  SSSP_TRY(sssp::launch_ctl_reset(p.ctl, 1, stream));
+  SSSP_TRY(sssp::launch_ctl_reset(p.ctl, 1, nullptr, 0, stream));
 
   // 4. light/heavy split (A_L, A_H)
   SSSP_TRY(sssp::launch_split(g->row_ptr, g->col_idx, g->weights, g->wtype, n, h->delta_u, h->delta_f, off, split,
@@ -247,10 +255,10 @@ sssp_status sssp_solve(sssp_handle* h, const int32_t* sources, int32_t k, void* 
     SSSP_TRY(hipMemsetAsync(h->p.qstamp, 0, un * sizeof(uint32_t), s));
     SSSP_TRY(hipMemsetAsync(h->p.sstamp, 0, un * sizeof(uint32_t), s));
     SSSP_TRY(hipMemsetAsync(h->p.fstamp, 0, un * sizeof(uint32_t), s));
-    SSSP_TRY(hipMemsetAsync(h->p.ovf_at, 0, un, s));
+    SSSP_TRY(hipMemsetAsync(h->p.ovf_at, 0, un * sizeof(uint32_t), s));
     reset_epochs = 1;
   }
-  SSSP_TRY(sssp::launch_ctl_reset(h->p.ctl, reset_epochs, s));
+  SSSP_TRY(sssp::launch_ctl_reset(h->p.ctl, reset_epochs, h->trace, h->trace_cap, s));
   SSSP_TRY(sssp::launch_solver(h->p, h->src_dev, k, static_cast<uint32_t*>(dist), h->grid, s));
   SSSP_TRY(hipMemcpyAsync(h->ctl_host, h->p.ctl, sizeof(sssp::Ctl), hipMemcpyDeviceToHost, s));
   SSSP_TRY(hipStreamSynchronize(s));
@@ -267,6 +275,7 @@ sssp_status sssp_solve(sssp_handle* h, const int32_t* sources, int32_t k, void* 
   h->last.heavy_edges = c.heavy_edges;
   h->last.improvements = c.improvements;
   h->last.barriers = c.barriers;
+  h->last.trace_records = c.trace_len;
   if (c.ovf_real) return SSSP_ERR_OVERFLOW;
   h->solved = true;
   return SSSP_OK;
@@ -280,7 +289,7 @@ sssp_status sssp_last_stats(const sssp_handle* h, sssp_stats* out) {
 
 sssp_status sssp_set_tuning(sssp_handle* h, const sssp_tuning* t) {
   if (!h || !t) return SSSP_ERR_INVALID_ARGUMENT;
-  if (t->workgroups_per_cu < 0 || t->ring_buckets < 0) return SSSP_ERR_INVALID_ARGUMENT;
+  if (t->workgroups_per_cu < 0 || t->ring_buckets < 0 || t->inline_edges < 0) return SSSP_ERR_INVALID_ARGUMENT;
   if (t->ring_buckets != 0 && t->ring_buckets != static_cast<int32_t>(h->p.ring))
     return SSSP_ERR_UNSUPPORTED;  // the ring is sized at create time
   const sssp_tuning old = h->tuning;
@@ -289,8 +298,18 @@ sssp_status sssp_set_tuning(sssp_handle* h, const sssp_tuning* t) {
   if (st != SSSP_OK) {
     h->tuning = old;
     (void)configure_grid(h);
+    return st;
   }
-  return st;
+  h->p.inline_edges = t->inline_edges > 0 ? static_cast<uint32_t>(t->inline_edges) : kDefaultInlineEdges;
+  return SSSP_OK;
+}
+
+sssp_status sssp_set_trace(sssp_handle* h, uint64_t* device_buffer, int64_t capacity) {
+  if (!h || capacity < 0 || (capacity > 0 && !device_buffer)) return SSSP_ERR_INVALID_ARGUMENT;
+  if (capacity > 0xFFFFFFFFll) capacity = 0xFFFFFFFFll;
+  h->trace = capacity > 0 ? reinterpret_cast<unsigned long long*>(device_buffer) : nullptr;
+  h->trace_cap = static_cast<uint32_t>(capacity);
+  return SSSP_OK;
 }
 
 sssp_status sssp_graph_info(const sssp_handle* h, int64_t* n, int64_t* m, int32_t* wtype) {

@@ -6,7 +6,15 @@
 
 namespace sssp {
 
-constexpr int kWG = 256;               // threads per workgroup: 4 wave64s
+constexpr int kWG = 1024;              // solver workgroup: 16 wave64s, one per compute unit
+constexpr int kAuxWG = 256;            // workgroup of the create-time kernels
+constexpr uint32_t kChunk = 512;       // most list entries a workgroup expands at a time
+constexpr uint32_t kMinChunk = 32;     // fewest list entries per claimed chunk
+constexpr uint32_t kILP = 4;           // edges per lane in flight
+constexpr uint32_t kPiece = kWG * kILP;  // edges of one hub piece (one round of a workgroup)
+constexpr uint32_t kHub = 1024;        // a vertex with at least this many edges in a phase goes to the hub step
+constexpr uint32_t kStage = 2 * kWG * kILP;  // LDS staging capacity for list appends (entries)
+constexpr uint32_t kBarGroups = 8;     // arrival sub-counters of the grid barrier
 constexpr uint32_t kRingMax = 64;      // near-bucket ring capacity
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
@@ -22,6 +30,7 @@ enum Action : uint32_t {
   kActFar = 3,    // move far-future vertices into the ring
   kActDone = 4,
   kActOverflowCheck = 5,
+  kActHub = 6,    // pieces of high-degree vertices left over by the previous phase
 };
 
 enum InKind : uint32_t { kInF0 = 0, kInF1 = 1, kInBin = 2 };
@@ -31,11 +40,16 @@ enum InKind : uint32_t { kInF0 = 0, kInF1 = 1, kInBin = 2 };
 // barrier leader (the last workgroup to arrive) before it releases the others,
 // so every workgroup reads the same schedule.
 struct Ctl {
-  // grid barrier
+  // grid barrier: arrival sub-counters on separate 128-byte lines, then the top counter
+  uint32_t bar_sub[kBarGroups][32];
   uint32_t bar_arrive;
   uint32_t bar_gen;
   uint32_t abort;
   uint32_t source_index;
+  uint32_t chunk_next;   // dynamic chunk counter of the current step
+  uint32_t hub_count;    // hub pieces queued by the current phase
+  uint32_t hub_parent;   // action of the phase that queued them
+  uint32_t pad0;
   // schedule
   uint32_t action;
   uint32_t bucket;       // current bucket i
@@ -58,6 +72,9 @@ struct Ctl {
   uint32_t farcount[2];
   uint32_t ovf_seen;     // some candidate did not fit the distance type
   uint32_t ovf_real;     // a reachable vertex has an unrepresentable distance
+  uint32_t trace_len;    // step records written (may exceed trace_cap)
+  unsigned long long* trace;  // optional step trace: 2 words per record
+  uint32_t trace_cap;
   uint32_t pad;
   uint32_t bincount[kRingMax];
   // statistics (summed over sources)
@@ -80,11 +97,14 @@ struct Params {
   uint32_t* sstamp;       // [n] round tag of the last S insertion
   uint32_t* bstamp;       // [n] lowest bucket a vertex was filed under (this solve)
   uint32_t* fstamp;       // [n] far epoch of the last far insertion
-  uint8_t* ovf_at;        // [n] a candidate for this vertex did not fit
+  uint32_t* ovf_at;       // [n] a candidate for this vertex did not fit
   uint32_t* front[2];     // [n] frontier buffers
   uint32_t* slist;        // [n] S
   uint32_t* bins;         // [ring][n]
   uint32_t* far[2];       // [n] far lists
+  uint64_t* hub;          // [hub_cap] pieces (vertex | piece index << 32)
+  uint32_t hub_cap;
+  uint32_t inline_edges;  // steps with at most this many edges run on the leader workgroup alone
   Ctl* ctl;
 };
 
@@ -95,7 +115,7 @@ hipError_t launch_split(const int64_t* row_ptr, const int32_t* col, const void* 
                         uint32_t delta_u, float delta_f, uint32_t* off, uint32_t* split, uint64_t* edges,
                         uint32_t* perm, hipStream_t s);
 hipError_t solver_occupancy(int wtype, int* blocks_per_cu);
-hipError_t launch_ctl_reset(Ctl* c, int reset_epochs, hipStream_t s);
+hipError_t launch_ctl_reset(Ctl* c, int reset_epochs, unsigned long long* trace, uint32_t trace_cap, hipStream_t s);
 hipError_t launch_solver(const Params& p, const int32_t* sources, int k, uint32_t* dist, int grid,
                          hipStream_t s);
 

@@ -1,13 +1,21 @@
 // HIP kernels for gfx950 (CDNA4, wave64): graph validation, the light/heavy
 // split of the adjacency matrix, and the persistent delta-stepping solver.
 //
-// The solver is one cooperative launch per call. Every step of the method
-// (a light phase, a heavy phase, a far-bucket redistribution) is processed by
-// all resident workgroups, and steps are separated by a device-wide barrier
-// whose last arriving workgroup (the leader) computes the next step -- the
-// loop tests of Fig. 1 ("while t_Bi != 0", "while (t >= i*delta) != 0") -- and
-// publishes it before releasing the others. No host round trip is needed
-// between steps.
+// The solver is one cooperative launch per call, one 1024-thread workgroup per
+// compute unit. Every step of the method (a light phase, a heavy phase, a
+// far-bucket redistribution) is processed by all workgroups; steps are
+// separated by a device-wide barrier whose last arriving workgroup (the
+// leader) evaluates the loop tests of Fig. 1 ("while t_Bi != 0",
+// "while (t >= i*delta) != 0") and publishes the next step before releasing
+// the others. Steps too small to be worth a device-wide barrier run on the
+// leader workgroup alone, inside the barrier.
+//
+// Memory model: every datum one workgroup writes and another reads (distances,
+// stamps, lists, counters, the schedule) is written with device-scope stores
+// or atomics and read with device-scope loads, which are coherent across the
+// XCDs' L2 caches. The barrier therefore only needs each wave's outstanding
+// stores to complete, not an L2 write-back or invalidation. Only the split
+// graph (written by an earlier kernel) is read through the caches.
 #include "sssp_internal.h"
 
 namespace sssp {
@@ -32,15 +40,17 @@ __device__ inline uint32_t lanes_below(uint64_t mask) {
 
 __device__ inline uint32_t lane() { return __lane_id(); }
 
+__device__ inline int first_lane(uint64_t mask) { return __ffsll(static_cast<unsigned long long>(mask)) - 1; }
+
 // Append `v` to list[*count] for every lane with `pred`; one atomic per wave.
 __device__ inline void push_wave(uint32_t* list, uint32_t* count, bool pred, uint32_t v) {
   const uint64_t mask = __ballot(pred);
   if (mask == 0) return;
-  const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
+  const int leader = first_lane(mask);
   uint32_t base = 0;
   if (static_cast<int>(lane()) == leader) base = atomicAdd(count, static_cast<uint32_t>(__popcll(mask)));
   base = __shfl(base, leader);
-  if (pred) list[base + lanes_below(mask)] = v;
+  if (pred) st_agent(&list[base + lanes_below(mask)], v);
 }
 
 // Inclusive prefix sum across a wave64.
@@ -68,6 +78,7 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t* total, uin
     all += s;
   }
   *total = all;
+  __syncthreads();  // s_wsum is reused by the next scan
   return before + inc - x;
 }
 
@@ -106,6 +117,7 @@ struct WeightF32 {
 
 struct Sched {
   uint32_t action, bucket, in_kind, in_count, out_buf, step, round, far_epoch, far_cur, far_base;
+  uint32_t hub_count, hub_parent;
   uint64_t lo_u, hi_u;
   double lo_d, hi_d;
 };
@@ -134,6 +146,8 @@ __device__ inline void load_sched(Ctl* c, Sched* s) {
     s->far_epoch = ld_agent(&c->far_epoch);
     s->far_cur = ld_agent(&c->far_cur);
     s->far_base = ld_agent(&c->far_base);
+    s->hub_count = ld_agent(&c->hub_count);
+    s->hub_parent = ld_agent(&c->hub_parent);
     s->lo_u = ld_agent(&c->lo_u);
     s->hi_u = ld_agent(&c->hi_u);
     s->lo_d = ld_agent(&c->lo_d);
@@ -142,54 +156,463 @@ __device__ inline void load_sched(Ctl* c, Sched* s) {
   __syncthreads();
 }
 
+// the input list of a light or heavy phase
+__device__ inline const uint32_t* phase_list(const Params& p, const Sched& s, bool light) {
+  if (!light) return p.slist;
+  if (s.in_kind == kInBin) return p.bins + static_cast<size_t>(s.bucket & p.ring_mask) * p.n;
+  return p.front[s.in_kind];
+}
+
 // ------------------------------------------------------------------ barrier
 
-constexpr uint32_t kSpinLimit = 1u << 22;  // several seconds of waiting: only a broken schedule gets there
+constexpr unsigned long long kWaitLimitTicks = 3000000000ull;  // 30 s of the 100 MHz wall clock
 
-// Device-wide barrier over all (co-resident) workgroups. The last workgroup to
-// arrive runs `leader` (every thread of it) before releasing the others.
-// Returns false when the schedule was aborted (a wait exceeded kSpinLimit).
+// Every wave's device-scope stores and atomics complete (are acknowledged by
+// the device-coherent level) before its workgroup arrives: s_waitcnt with all
+// counters zero.
+__device__ inline void drain_stores() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
+__device__ inline void record_trace(Ctl* c, uint32_t flags) {
+  if (!c->trace) return;
+  const uint32_t idx = atomicAdd(&c->trace_len, 1u);
+  if (idx < c->trace_cap) {
+    const unsigned long long what = static_cast<unsigned long long>(ld_agent(&c->in_count)) << 32 |
+                                    static_cast<unsigned long long>(ld_agent(&c->bucket) & 0xFFFFFFu) << 8 |
+                                    (ld_agent(&c->action) | flags);
+    st_agent(&c->trace[2 * idx], static_cast<unsigned long long>(wall_clock64()));
+    st_agent(&c->trace[2 * idx + 1], what);
+  }
+}
+
+// Device-wide barrier over all (co-resident) workgroups. Arrivals are counted
+// first per group of workgroups (blockIdx % 8), then once per group, which
+// keeps same-address atomics short. The last workgroup to arrive runs `leader`
+// (all its threads) before releasing the others. Returns false when the
+// schedule was aborted (a wait ran past kWaitLimitTicks).
 template <class F>
 __device__ bool grid_sync(Ctl* c, F&& leader) {
   __shared__ uint32_t s_is_leader;
   __shared__ uint32_t s_ok;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  drain_stores();
   __syncthreads();
   uint32_t gen = 0;
   if (threadIdx.x == 0) {
+    const uint32_t groups = gridDim.x < kBarGroups ? gridDim.x : kBarGroups;
+    const uint32_t g = blockIdx.x % groups;
+    const uint32_t gsize = (gridDim.x - g + groups - 1) / groups;
     gen = ld_agent(&c->bar_gen);
-    const uint32_t prev = __hip_atomic_fetch_add(&c->bar_arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    const bool last = prev == gridDim.x - 1;
+    bool last = false;
+    const uint32_t prev = atomicAdd(&c->bar_sub[g][0], 1u);
+    if (prev == gsize - 1) {
+      st_agent(&c->bar_sub[g][0], 0u);  // the whole group has arrived; nobody re-arrives before the release
+      last = atomicAdd(&c->bar_arrive, 1u) == groups - 1;
+      if (last) st_agent(&c->bar_arrive, 0u);
+    }
     s_is_leader = last ? 1u : 0u;
     uint32_t ok = 1;
     if (!last) {
-      uint32_t it = 0;
-      while (__hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        if (++it > kSpinLimit || ld_agent(&c->abort) != 0u) {
+      const unsigned long long t0 = wall_clock64();
+      while (ld_agent(&c->bar_gen) == gen) {
+        if (ld_agent(&c->abort) != 0u || wall_clock64() - t0 > kWaitLimitTicks) {
           st_agent(&c->abort, 1u);
           ok = 0;
           break;
         }
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(1);
       }
     }
     s_ok = ok;
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   if (s_is_leader) {
     leader();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    drain_stores();
     __syncthreads();
     if (threadIdx.x == 0) {
       atomicAdd(&c->barriers, 1ull);
-      st_agent(&c->bar_arrive, 0u);
-      __hip_atomic_store(&c->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      record_trace(c, 0u);
+      drain_stores();
+      st_agent(&c->bar_gen, gen + 1u);
     }
   }
   const bool ok = s_ok != 0u;
   __syncthreads();
   return ok;
+}
+
+// ------------------------------------------------------------------ relaxation
+
+struct WgStats {
+  unsigned long long light_edges, heavy_edges, improvements;
+};
+
+// Append winners to the ring slot of their bucket. Lanes are grouped by
+// bucket with ballots only; then every group leader issues its atomic at the
+// same time, so a wave waits for one atomic round trip whatever the number of
+// distinct buckets.
+__device__ inline void push_ring(const Params& p, bool pred, uint32_t j, uint32_t v) {
+  uint64_t rest = __ballot(pred);
+  if (rest == 0) return;
+  uint32_t my_leader = 0;
+  uint64_t my_group = 0;
+  while (rest) {
+    const int l = first_lane(rest);
+    const uint32_t jl = __builtin_amdgcn_readlane(j, l);
+    const bool same = pred && j == jl;
+    const uint64_t grp = __ballot(same);
+    if (same) {
+      my_leader = static_cast<uint32_t>(l);
+      my_group = grp;
+    }
+    rest &= ~grp;
+  }
+  uint32_t base = 0;
+  if (pred && lane() == my_leader)
+    base = atomicAdd(&p.ctl->bincount[j & p.ring_mask], static_cast<uint32_t>(__popcll(my_group)));
+  base = __shfl(base, static_cast<int>(my_leader));
+  if (pred) st_agent(&p.bins[static_cast<size_t>(j & p.ring_mask) * p.n + base + lanes_below(my_group)], v);
+}
+
+// List appends of a workgroup are staged in LDS and flushed together: one
+// global atomic per destination list per flush instead of one per wave.
+constexpr uint32_t kSlotFront = kRingMax;     // the current bucket's next frontier
+constexpr uint32_t kSlotFar = kRingMax + 1;   // the far list
+constexpr uint32_t kSlots = kRingMax + 2;     // ring slots 0..kRingMax-1, then the two above
+constexpr uint32_t kNoSlot = 0xFFu;
+
+struct Stage {
+  uint32_t v[kStage];
+  uint32_t rank[kStage];
+  uint8_t slot[kStage];
+  uint32_t n;
+  uint32_t cnt[kSlots];
+  uint32_t base[kSlots];
+};
+
+__device__ inline void stage_push(Stage& sg, bool push, uint32_t slot, uint32_t v) {
+  const uint64_t mask = __ballot(push);
+  if (mask == 0) return;
+  const int leader = first_lane(mask);
+  uint32_t b = 0;
+  if (static_cast<int>(lane()) == leader) b = atomicAdd(&sg.n, static_cast<uint32_t>(__popcll(mask)));
+  b = __shfl(b, leader);
+  if (push) {
+    const uint32_t i = b + lanes_below(mask);
+    sg.v[i] = v;
+    sg.slot[i] = static_cast<uint8_t>(slot);
+  }
+}
+
+// Move the staged appends to their lists. Unless `force`, only when another
+// round of kWG * kILP appends might not fit. All threads of the workgroup call it.
+__device__ void stage_flush(const Params& p, const Sched& s, Stage& sg, bool force) {
+  __syncthreads();
+  const uint32_t n = sg.n;
+  if (n == 0 || (!force && n <= kStage - kWG * kILP)) return;
+  if (threadIdx.x < kSlots) sg.cnt[threadIdx.x] = 0;
+  __syncthreads();
+  // rank of each entry within its destination: lanes grouped by destination, one LDS atomic per group
+  for (uint32_t i0 = 0; i0 < n; i0 += kWG) {
+    const uint32_t i = i0 + threadIdx.x;
+    const bool valid = i < n;
+    const uint32_t slot = valid ? sg.slot[i] : kNoSlot;
+    uint64_t rest = __ballot(valid);
+    uint32_t my_leader = 0;
+    uint64_t my_group = 0;
+    while (rest) {
+      const int l = first_lane(rest);
+      const uint32_t sl = __builtin_amdgcn_readlane(slot, l);
+      const bool same = valid && slot == sl;
+      const uint64_t grp = __ballot(same);
+      if (same) {
+        my_leader = static_cast<uint32_t>(l);
+        my_group = grp;
+      }
+      rest &= ~grp;
+    }
+    uint32_t b = 0;
+    if (valid && lane() == my_leader) b = atomicAdd(&sg.cnt[slot], static_cast<uint32_t>(__popcll(my_group)));
+    b = __shfl(b, static_cast<int>(my_leader));
+    if (valid) sg.rank[i] = b + lanes_below(my_group);
+  }
+  __syncthreads();
+  if (threadIdx.x < kSlots) {
+    const uint32_t k = threadIdx.x;
+    const uint32_t c = sg.cnt[k];
+    uint32_t* ctr = k < kRingMax ? &p.ctl->bincount[k] : k == kSlotFront ? &p.ctl->fcount[s.out_buf]
+                                                                         : &p.ctl->farcount[s.far_cur];
+    sg.base[k] = c ? atomicAdd(ctr, c) : 0u;
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < n; i += kWG) {
+    const uint32_t slot = sg.slot[i];
+    uint32_t* list = slot < kRingMax ? p.bins + static_cast<size_t>(slot) * p.n
+                                     : slot == kSlotFront ? p.front[s.out_buf] : p.far[s.far_cur];
+    st_agent(&list[sg.base[slot] + sg.rank[i]], sg.v[i]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) sg.n = 0;
+  __syncthreads();
+}
+
+// kILP requests (v, t(u) (+) w) per lane: t(v) = min(t(v), request) (Sec. III-C
+// relax; Sec. IV-C/IV-D t = min(t, t_Req)), then file each improved v by the
+// bucket of its new tentative distance: back into the current bucket's frontier
+// (the re-insertion mask (i*delta <= t_Req < (i+1)*delta) o (t_Req < t) of
+// Sec. IV-C), into the ring of near buckets, or into the far list. The loads and
+// atomics of the kILP requests are independent and overlap in flight.
+template <class W>
+__device__ inline void relax_batch(const Params& p, uint32_t* t, const Sched& s, const bool (&active)[kILP],
+                                   const uint32_t (&tu)[kILP], const uint32_t (&v)[kILP],
+                                   const uint32_t (&w)[kILP], uint32_t near_end, WgStats& st, Stage& sg) {
+  uint32_t cand[kILP], tv[kILP];
+  bool ok[kILP], win[kILP];
+#pragma unroll
+  for (uint32_t q = 0; q < kILP; ++q) {
+    ok[q] = active[q] && W::add(tu[q], w[q], &cand[q]);
+    if (active[q] && !ok[q]) {
+      st_agent(&p.ovf_at[v[q]], 1u);
+      st_agent(&p.ctl->ovf_seen, 1u);
+    }
+    tv[q] = ok[q] ? t[v[q]] : 0u;  // may be stale, but never below the current value
+  }
+#pragma unroll
+  for (uint32_t q = 0; q < kILP; ++q) win[q] = ok[q] && cand[q] < tv[q] && cand[q] < atomicMin(&t[v[q]], cand[q]);
+  uint32_t slot[kILP];
+#pragma unroll
+  for (uint32_t q = 0; q < kILP; ++q) {
+    slot[q] = kNoSlot;
+    if (win[q]) {
+      const uint32_t j = W::bucket(cand[q], p);
+      if (j <= s.bucket) {
+        if (atomicExch(&p.qstamp[v[q]], s.step + 1u) != s.step + 1u) slot[q] = kSlotFront;
+      } else if (j < near_end) {
+        if (atomicMin(&p.bstamp[v[q]], j) > j) slot[q] = j & p.ring_mask;
+      } else {
+        atomicMin(&p.ctl->far_min, j);
+        if (atomicExch(&p.fstamp[v[q]], s.far_epoch) != s.far_epoch) slot[q] = kSlotFar;
+      }
+    }
+  }
+#pragma unroll
+  for (uint32_t q = 0; q < kILP; ++q) {
+    const uint64_t wins = __ballot(win[q]);
+    if (lane() == 0) st.improvements += __popcll(wins);
+    stage_push(sg, slot[q] != kNoSlot, slot[q], v[q]);
+  }
+}
+
+// Work distribution over `nitems` items: in a device-wide step, workgroup b
+// first takes item b with no atomic, then claims further items from a shared
+// counter; the leader workgroup running a step alone walks every item in order.
+__device__ inline uint32_t claim_next(Ctl* c, uint32_t prev, uint32_t nitems, bool solo, uint32_t* s_claim) {
+  if (solo) return prev + 1;
+  if (nitems <= gridDim.x) return nitems;  // every item was taken statically
+  __syncthreads();
+  if (threadIdx.x == 0) *s_claim = gridDim.x + atomicAdd(&c->chunk_next, 1u);
+  __syncthreads();
+  return *s_claim;
+}
+
+// Queue the pieces of one high-degree vertex (kHub or more edges in this phase).
+__device__ inline void queue_hub(const Params& p, uint32_t u, uint32_t deg) {
+  const uint32_t pieces = (deg + kPiece - 1) / kPiece;
+  const uint32_t base = atomicAdd(&p.ctl->hub_count, pieces);
+  for (uint32_t k = 0; k < pieces && base + k < p.hub_cap; ++k)
+    st_agent(&p.hub[base + k], static_cast<uint64_t>(u) | (static_cast<uint64_t>(k) << 32));
+}
+
+// One relaxation phase: every vertex u of the input list sends t(u) (+) w along
+// its light (kLight) or heavy out-edges -- the masked min-plus product
+// t_Req = A_L^T (t o t_Bi) or A_H^T (t o S) of Sec. IV-C/IV-D, fused with the
+// min-merge into t (the paper's fusion of the Hadamard product into vxm).
+// Edges are balanced over the workgroup: the degrees of kChunk list entries
+// are prefix-summed in LDS and the lanes walk the concatenated edge ranges, so
+// consecutive lanes read consecutive edges of a row. Vertices with kHub or
+// more edges are queued as pieces for a grid-wide hub step instead.
+// List entries per claimed chunk: enough chunks for about four per workgroup.
+__device__ inline uint32_t chunk_for(uint32_t count) {
+  const uint32_t target = (count + 4 * gridDim.x - 1) / (4 * gridDim.x);
+  uint32_t c = kMinChunk;
+  while (c < target && c < kChunk) c <<= 1;
+  return c;
+}
+
+template <class W, bool kLight>
+__device__ void phase(const Params& p, uint32_t* t, const Sched& s, WgStats& st, Stage& sg, bool solo) {
+  __shared__ uint32_t s_pref[kChunk];
+  __shared__ uint32_t s_beg[kChunk];
+  __shared__ uint32_t s_tu[kChunk];
+  __shared__ uint32_t s_wsum[kWG / 64];
+  __shared__ uint32_t s_claim;
+
+  const bool from_bin = kLight && s.in_kind == kInBin;
+  const uint32_t* list = phase_list(p, s, kLight);
+  const uint32_t count = s.in_count;
+  const uint32_t near_end = s.bucket + p.ring;
+  const uint32_t chunk = solo ? kChunk : chunk_for(count);
+  const uint32_t nchunks = (count + chunk - 1) / chunk;
+
+  for (uint32_t c = solo ? 0u : blockIdx.x; c < nchunks; c = claim_next(p.ctl, c, nchunks, solo, &s_claim)) {
+    const uint32_t k = c * chunk + threadIdx.x;
+    uint32_t beg = 0, deg = 0, tu = W::kInf, u = 0;
+    bool take = false;
+    if (threadIdx.x < chunk && k < count) {
+      u = ld_agent(&list[k]);
+      tu = ld_agent(&t[u]);
+      // a ring slot may hold vertices that have since moved to a lower bucket
+      take = !from_bin || in_bucket<W>(tu, s);
+      if (take) {
+        if (kLight) {
+          beg = p.off[u];
+          deg = p.split[u] - beg;
+        } else {
+          beg = p.split[u];
+          deg = p.off[u + 1] - beg;
+        }
+      }
+    }
+    if (kLight) {  // S = (S + t_Bi) > 0: each expanded vertex joins S once per round
+      bool to_s = false;
+      if (take && ld_agent(&p.sstamp[u]) != s.round) to_s = atomicExch(&p.sstamp[u], s.round) != s.round;
+      push_wave(p.slist, &p.ctl->scount, to_s, u);
+    }
+    if (!solo && deg >= kHub) {
+      queue_hub(p, u, deg);
+      if (kLight) st.light_edges += deg;
+      else st.heavy_edges += deg;
+      deg = 0;
+    }
+    uint32_t total;
+    const uint32_t excl = block_exclusive_scan(deg, &total, s_wsum);
+    if (threadIdx.x < kChunk) {
+      s_pref[threadIdx.x] = excl;
+      s_beg[threadIdx.x] = beg;
+      s_tu[threadIdx.x] = tu;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (kLight) st.light_edges += total;
+      else st.heavy_edges += total;
+    }
+    const uint32_t rounds = (total + kWG * kILP - 1) / (kWG * kILP);
+    for (uint32_t r = 0; r < rounds; ++r) {
+      bool active[kILP];
+      uint32_t v[kILP], w[kILP], tw[kILP];
+#pragma unroll
+      for (uint32_t q = 0; q < kILP; ++q) {
+        const uint32_t e = (r * kILP + q) * kWG + threadIdx.x;
+        active[q] = e < total;
+        v[q] = 0;
+        w[q] = 0;
+        tw[q] = W::kInf;
+        if (active[q]) {
+          uint32_t lo = 0, hi = chunk - 1;  // last entry whose range starts at or before e
+          while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (s_pref[mid] <= e) lo = mid;
+            else hi = mid - 1;
+          }
+          const uint64_t ed = p.edges[s_beg[lo] + (e - s_pref[lo])];
+          v[q] = static_cast<uint32_t>(ed);
+          w[q] = static_cast<uint32_t>(ed >> 32);
+          tw[q] = s_tu[lo];
+        }
+      }
+      relax_batch<W>(p, t, s, active, tw, v, w, near_end, st, sg);
+      stage_flush(p, s, sg, false);
+    }
+    __syncthreads();
+  }
+  stage_flush(p, s, sg, true);
+}
+
+// Hub step: pieces of kPiece consecutive edges of the high-degree vertices
+// queued by the previous phase, spread over all workgroups.
+template <class W>
+__device__ void hub_step(const Params& p, uint32_t* t, const Sched& s, WgStats& st, Stage& sg) {
+  __shared__ uint32_t s_beg, s_end, s_tu, s_claim;
+  const bool light = s.hub_parent == kActLight;
+  const uint32_t count = s.hub_count < p.hub_cap ? s.hub_count : p.hub_cap;
+  const uint32_t near_end = s.bucket + p.ring;
+  for (uint32_t c = blockIdx.x; c < count; c = claim_next(p.ctl, c, count, false, &s_claim)) {
+    if (threadIdx.x == 0) {
+      const uint64_t rec = ld_agent(&p.hub[c]);
+      const uint32_t u = static_cast<uint32_t>(rec);
+      const uint32_t piece = static_cast<uint32_t>(rec >> 32);
+      const uint32_t b = light ? p.off[u] : p.split[u];
+      const uint32_t e = light ? p.split[u] : p.off[u + 1];
+      const uint32_t pb = b + piece * kPiece;
+      s_beg = pb;
+      s_end = e - pb > kPiece ? pb + kPiece : e;
+      s_tu = ld_agent(&t[u]);
+    }
+    __syncthreads();
+    bool active[kILP];
+    uint32_t v[kILP], w[kILP], tw[kILP];
+#pragma unroll
+    for (uint32_t q = 0; q < kILP; ++q) {
+      const uint32_t e = s_beg + q * kWG + threadIdx.x;
+      active[q] = e < s_end;
+      v[q] = 0;
+      w[q] = 0;
+      tw[q] = s_tu;
+      if (active[q]) {
+        const uint64_t ed = p.edges[e];
+        v[q] = static_cast<uint32_t>(ed);
+        w[q] = static_cast<uint32_t>(ed >> 32);
+      }
+    }
+    relax_batch<W>(p, t, s, active, tw, v, w, near_end, st, sg);
+    stage_flush(p, s, sg, false);
+  }
+  stage_flush(p, s, sg, true);
+}
+
+// Far-list redistribution: far vertices whose bucket is now within the ring
+// move into it; the rest move to the other far list.
+template <class W>
+__device__ void far_step(const Params& p, uint32_t* t, const Sched& s) {
+  const uint32_t count = s.in_count;
+  const uint32_t* list = p.far[s.far_cur];
+  const uint32_t nxt = 1u - s.far_cur;
+  const uint32_t near_end = s.far_base + p.ring;
+  const uint32_t iters = (count + gridDim.x * kWG - 1) / (gridDim.x * kWG);
+  for (uint32_t it = 0; it < iters; ++it) {
+    const uint32_t k = (it * gridDim.x + blockIdx.x) * kWG + threadIdx.x;
+    bool to_ring = false, to_far = false;
+    uint32_t v = 0, j = 0;
+    if (k < count) {
+      v = ld_agent(&list[k]);
+      // still only filed far (never moved into the ring since)?
+      if (ld_agent(&p.bstamp[v]) == kNone) {
+        j = W::bucket(ld_agent(&t[v]), p);
+        if (j < near_end) {
+          to_ring = atomicMin(&p.bstamp[v], j) > j;
+        } else {
+          atomicMin(&p.ctl->far_min_next, j);
+          to_far = atomicExch(&p.fstamp[v], s.far_epoch + 1u) != s.far_epoch + 1u;
+        }
+      }
+    }
+    push_ring(p, to_ring, j, v);
+    push_wave(p.far[nxt], &p.ctl->farcount[nxt], to_far, v);
+  }
+}
+
+// A candidate that did not fit marked its target; the distance of that target
+// is unrepresentable exactly when no other path reached it.
+template <class W>
+__device__ void overflow_step(const Params& p, uint32_t* t) {
+  for (uint32_t v = blockIdx.x * kWG + threadIdx.x; v < p.n; v += gridDim.x * kWG) {
+    if (ld_agent(&p.ovf_at[v])) {
+      if (ld_agent(&t[v]) == W::kInf) st_agent(&p.ctl->ovf_real, 1u);
+      st_agent(&p.ovf_at[v], 0u);
+    }
+  }
 }
 
 // ------------------------------------------------------------------ leader decisions
@@ -218,7 +641,7 @@ __device__ void choose_next(const Params& p, uint32_t from, uint32_t len) {
     bool nonempty = false;
     if (l < len) nonempty = ld_agent(&c->bincount[(from + l) & p.ring_mask]) != 0u;
     const uint64_t m = __ballot(nonempty);
-    if (l == 0) s_jn = m ? from + static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(m)) - 1) : kNone;
+    if (l == 0) s_jn = m ? from + static_cast<uint32_t>(first_lane(m)) : kNone;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -231,7 +654,7 @@ __device__ void choose_next(const Params& p, uint32_t from, uint32_t len) {
       st_agent(&c->in_count, fc);
     } else if (jn == kNone) {
       st_agent(&c->action, static_cast<uint32_t>(ld_agent(&c->ovf_seen) ? kActOverflowCheck : kActDone));
-    } else {
+    } else {  // B_i = {v : i*delta <= t(v) < (i+1)*delta} for the smallest non-empty i
       set_bucket<W>(p, jn);
       st_agent(&c->action, static_cast<uint32_t>(kActLight));
       st_agent(&c->in_kind, static_cast<uint32_t>(kInBin));
@@ -240,6 +663,7 @@ __device__ void choose_next(const Params& p, uint32_t from, uint32_t len) {
       atomicAdd(&c->buckets, 1ull);
     }
   }
+  __syncthreads();
 }
 
 template <class W>
@@ -257,6 +681,8 @@ __device__ void leader_start(const Params& p, uint32_t* t, uint32_t src) {
     st_agent(&c->far_min, kNone);
     st_agent(&c->far_min_next, kNone);
     st_agent(&c->ovf_seen, 0u);
+    st_agent(&c->hub_count, 0u);
+    st_agent(&c->chunk_next, 0u);
     st_agent(&c->step, ld_agent(&c->step) + 1u);
     st_agent(&c->round, ld_agent(&c->round) + 1u);
     // t = inf, t[s] = 0 (Fig. 1 left); the source is the only member of B_0
@@ -264,6 +690,7 @@ __device__ void leader_start(const Params& p, uint32_t* t, uint32_t src) {
     st_agent(&p.bstamp[src], 0u);
     st_agent(&p.bins[0], src);  // ring slot of bucket 0, first entry
   }
+  drain_stores();
   __syncthreads();
   if (threadIdx.x == 0) {
     st_agent(&c->bincount[0], 1u);
@@ -274,291 +701,145 @@ __device__ void leader_start(const Params& p, uint32_t* t, uint32_t src) {
     st_agent(&c->out_buf, 0u);
     atomicAdd(&c->buckets, 1ull);
   }
-}
-
-template <class W>
-__device__ void leader_after_light(const Params& p, const Sched& s) {
-  Ctl* c = p.ctl;
-  if (threadIdx.x == 0) {
-    atomicAdd(&c->light_phases, 1ull);
-    st_agent(&c->step, s.step + 1u);
-    const uint32_t n_next = ld_agent(&c->fcount[s.out_buf]);
-    if (s.in_kind == kInBin) st_agent(&c->bincount[s.bucket & p.ring_mask], 0u);
-    else st_agent(&c->fcount[s.in_kind], 0u);
-    if (n_next > 0) {  // while t_Bi != 0: another light phase on the re-inserted vertices
-      st_agent(&c->action, static_cast<uint32_t>(kActLight));
-      st_agent(&c->in_kind, s.out_buf);
-      st_agent(&c->in_count, n_next);
-      st_agent(&c->out_buf, 1u - s.out_buf);
-    } else {  // B_i is empty: one heavy phase over S
-      st_agent(&c->action, static_cast<uint32_t>(kActHeavy));
-      st_agent(&c->in_count, ld_agent(&c->scount));
-    }
-  }
-}
-
-template <class W>
-__device__ void leader_after_heavy(const Params& p, const Sched& s) {
-  Ctl* c = p.ctl;
-  __shared__ uint32_t s_redo;
-  if (threadIdx.x == 0) {
-    atomicAdd(&c->heavy_phases, 1ull);
-    st_agent(&c->step, s.step + 1u);
-    st_agent(&c->round, s.round + 1u);
-    st_agent(&c->scount, 0u);
-    // A heavy request can only fall back into bucket i through fp32 rounding
-    // (t(u) + w > (i+1)*delta in exact arithmetic); such vertices restart bucket i.
-    const uint32_t n_redo = ld_agent(&c->fcount[s.out_buf]);
-    s_redo = n_redo;
-    if (n_redo > 0) {
-      st_agent(&c->action, static_cast<uint32_t>(kActLight));
-      st_agent(&c->in_kind, s.out_buf);
-      st_agent(&c->in_count, n_redo);
-      st_agent(&c->out_buf, 1u - s.out_buf);
-    }
-  }
+  drain_stores();
   __syncthreads();
-  if (s_redo == 0) choose_next<W>(p, s.bucket + 1u, p.ring - 1u);
 }
 
+// Schedule the step that follows the completed step `s`.
 template <class W>
-__device__ void leader_after_far(const Params& p, const Sched& s) {
+__device__ void after_step(const Params& p, const Sched& s) {
   Ctl* c = p.ctl;
+  __shared__ uint32_t s_next;  // 0: decided, 1: choose the next bucket after s.bucket, 2: after a far step
   if (threadIdx.x == 0) {
-    atomicAdd(&c->far_phases, 1ull);
-    st_agent(&c->step, s.step + 1u);
-    st_agent(&c->farcount[s.far_cur], 0u);
-    st_agent(&c->far_cur, 1u - s.far_cur);
-    st_agent(&c->far_min, ld_agent(&c->far_min_next));
-    st_agent(&c->far_min_next, kNone);
-    st_agent(&c->far_epoch, s.far_epoch + 1u);
-  }
-  __syncthreads();
-  choose_next<W>(p, s.far_base, p.ring);
-}
-
-// ------------------------------------------------------------------ relaxation
-
-struct WgStats {
-  unsigned long long light_edges, heavy_edges, improvements;
-};
-
-// Append winners to the ring slot of their bucket: one atomic per distinct
-// bucket present in the wave.
-__device__ inline void push_ring(const Params& p, bool pred, uint32_t j, uint32_t v) {
-  bool pending = pred;
-  uint64_t mask = __ballot(pending);
-  while (mask) {
-    const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
-    const uint32_t jl = __shfl(j, leader);
-    const bool mine = pending && j == jl;
-    const uint64_t same = __ballot(mine);
-    uint32_t base = 0;
-    if (static_cast<int>(lane()) == leader) base = atomicAdd(&p.ctl->bincount[jl & p.ring_mask], static_cast<uint32_t>(__popcll(same)));
-    base = __shfl(base, leader);
-    if (mine) {
-      p.bins[static_cast<size_t>(jl & p.ring_mask) * p.n + base + lanes_below(same)] = v;
-      pending = false;
-    }
-    mask = __ballot(pending);
-  }
-}
-
-// One request (v, t(u) (+) w): t(v) = min(t(v), request) (Sec. III-C relax;
-// Sec. IV-C/IV-D t = min(t, t_Req)), then file v by the bucket of its new
-// tentative distance: back into the current bucket's frontier (the re-insertion
-// mask (i*delta <= t_Req < (i+1)*delta) o (t_Req < t) of Sec. IV-C), into the
-// ring of near buckets, or into the far list.
-template <class W>
-__device__ inline void relax(const Params& p, uint32_t* t, const Sched& s, bool active, uint32_t tu, uint32_t v,
-                             uint32_t w, uint32_t near_end, WgStats& st) {
-  bool win = false;
-  uint32_t cand = 0;
-  if (active) {
-    if (!W::add(tu, w, &cand)) {
-      p.ovf_at[v] = 1;
-      st_agent(&p.ctl->ovf_seen, 1u);
+    st_agent(&c->chunk_next, 0u);
+    uint32_t next = 0;
+    const uint32_t hubs = ld_agent(&c->hub_count);
+    const bool phase_done = s.action == kActLight || s.action == kActHeavy;
+    if (phase_done && hubs > 0) {  // finish the phase: its high-degree vertices
+      st_agent(&c->hub_parent, s.action);
+      st_agent(&c->action, static_cast<uint32_t>(kActHub));
     } else {
-      const uint32_t tv = t[v];  // may be stale, but never below the current value
-      if (cand < tv) win = cand < atomicMin(&t[v], cand);
+      const uint32_t parent = s.action == kActHub ? s.hub_parent : s.action;
+      st_agent(&c->hub_count, 0u);
+      if (parent == kActLight) {
+        atomicAdd(&c->light_phases, 1ull);
+        st_agent(&c->step, s.step + 1u);
+        const uint32_t n_next = ld_agent(&c->fcount[s.out_buf]);
+        if (s.in_kind == kInBin) st_agent(&c->bincount[s.bucket & p.ring_mask], 0u);
+        else st_agent(&c->fcount[s.in_kind], 0u);
+        if (n_next > 0) {  // while t_Bi != 0: another light phase on the re-inserted vertices
+          st_agent(&c->action, static_cast<uint32_t>(kActLight));
+          st_agent(&c->in_kind, s.out_buf);
+          st_agent(&c->in_count, n_next);
+          st_agent(&c->out_buf, 1u - s.out_buf);
+        } else {  // B_i is empty: one heavy phase over S
+          st_agent(&c->action, static_cast<uint32_t>(kActHeavy));
+          st_agent(&c->in_count, ld_agent(&c->scount));
+        }
+      } else if (parent == kActHeavy) {
+        atomicAdd(&c->heavy_phases, 1ull);
+        st_agent(&c->step, s.step + 1u);
+        st_agent(&c->round, s.round + 1u);
+        st_agent(&c->scount, 0u);
+        // A heavy request can only fall back into bucket i through fp32 rounding
+        // (t(u) + w > (i+1)*delta in exact arithmetic); such vertices restart bucket i.
+        const uint32_t n_redo = ld_agent(&c->fcount[s.out_buf]);
+        if (n_redo > 0) {
+          st_agent(&c->action, static_cast<uint32_t>(kActLight));
+          st_agent(&c->in_kind, s.out_buf);
+          st_agent(&c->in_count, n_redo);
+          st_agent(&c->out_buf, 1u - s.out_buf);
+        } else {
+          next = 1;
+        }
+      } else if (parent == kActFar) {
+        atomicAdd(&c->far_phases, 1ull);
+        st_agent(&c->step, s.step + 1u);
+        st_agent(&c->farcount[s.far_cur], 0u);
+        st_agent(&c->far_cur, 1u - s.far_cur);
+        st_agent(&c->far_min, ld_agent(&c->far_min_next));
+        st_agent(&c->far_min_next, kNone);
+        st_agent(&c->far_epoch, s.far_epoch + 1u);
+        next = 2;
+      } else {  // overflow check
+        st_agent(&c->action, static_cast<uint32_t>(kActDone));
+      }
     }
+    s_next = next;
   }
-  uint32_t j = 0;
-  bool to_front = false, to_ring = false, to_far = false;
-  if (win) {
-    j = W::bucket(cand, p);
-    if (j <= s.bucket) to_front = atomicExch(&p.qstamp[v], s.step + 1u) != s.step + 1u;
-    else if (j < near_end) to_ring = atomicMin(&p.bstamp[v], j) > j;
-    else {
-      atomicMin(&p.ctl->far_min, j);
-      to_far = atomicExch(&p.fstamp[v], s.far_epoch) != s.far_epoch;
-    }
-  }
-  const uint64_t wins = __ballot(win);
-  if (lane() == 0) st.improvements += __popcll(wins);
-  push_wave(p.front[s.out_buf], &p.ctl->fcount[s.out_buf], to_front, v);
-  push_ring(p, to_ring, j, v);
-  push_wave(p.far[s.far_cur], &p.ctl->farcount[s.far_cur], to_far, v);
+  __syncthreads();
+  const uint32_t next = s_next;
+  if (next == 1) choose_next<W>(p, s.bucket + 1u, p.ring - 1u);
+  else if (next == 2) choose_next<W>(p, s.far_base, p.ring);
+  drain_stores();
+  __syncthreads();
 }
 
-// One relaxation phase: every vertex u of the input list sends t(u) (+) w along
-// its light (kLight) or heavy out-edges -- the masked min-plus product
-// t_Req = A_L^T (t o t_Bi) or A_H^T (t o S) of Sec. IV-C/IV-D, fused with the
-// min-merge into t (the paper's fusion of the Hadamard product into vxm).
-// Edges are balanced over the workgroup: the degrees of up to 256 list entries
-// are prefix-summed in LDS and the lanes walk the concatenated edge ranges, so
-// consecutive lanes read consecutive edges of a row.
-template <class W, bool kLight>
-__device__ void phase(const Params& p, uint32_t* t, const Sched& s, WgStats& st) {
-  __shared__ uint32_t s_pref[kWG];
-  __shared__ uint32_t s_beg[kWG];
-  __shared__ uint32_t s_tu[kWG];
+// Edges a light or heavy step would scan (its list has at most kWG entries).
+template <bool kLight>
+__device__ uint32_t step_edges(const Params& p, const Sched& s, uint32_t* s_wsum) {
+  const uint32_t* list = phase_list(p, s, kLight);
+  uint32_t deg = 0;
+  if (threadIdx.x < s.in_count) {
+    const uint32_t u = ld_agent(&list[threadIdx.x]);
+    deg = kLight ? p.split[u] - p.off[u] : p.off[u + 1] - p.split[u];
+  }
+  uint32_t total;
+  (void)block_exclusive_scan(deg, &total, s_wsum);
+  return total;
+}
+
+// The leader's part of a barrier: schedule the step after `s`; while that step
+// is a small light or heavy phase, run it on this workgroup alone and schedule again.
+template <class W>
+__device__ void lead(const Params& p, uint32_t* t, Sched* s, WgStats& st, Stage& sg, bool schedule_first) {
   __shared__ uint32_t s_wsum[kWG / 64];
-
-  const bool from_bin = kLight && s.in_kind == kInBin;
-  const uint32_t* list = !kLight ? p.slist
-                         : from_bin ? p.bins + static_cast<size_t>(s.bucket & p.ring_mask) * p.n
-                                    : p.front[s.in_kind];
-  const uint32_t count = s.in_count;
-  const uint32_t near_end = s.bucket + p.ring;
-
-  for (uint32_t base = blockIdx.x * kWG; base < count; base += gridDim.x * kWG) {
-    const uint32_t k = base + threadIdx.x;
-    uint32_t beg = 0, deg = 0, tu = W::kInf, u = 0;
-    bool take = false;
-    if (k < count) {
-      u = list[k];
-      tu = ld_agent(&t[u]);
-      // a ring slot may hold vertices that have since moved to a lower bucket
-      take = !from_bin || in_bucket<W>(tu, s);
-      if (take) {
-        if (kLight) {
-          beg = p.off[u];
-          deg = p.split[u] - beg;
-        } else {
-          beg = p.split[u];
-          deg = p.off[u + 1] - beg;
-        }
-      }
-    }
-    if (kLight) {  // S = (S + t_Bi) > 0: each expanded vertex joins S once per round
-      bool to_s = false;
-      if (take && ld_agent(&p.sstamp[u]) != s.round) to_s = atomicExch(&p.sstamp[u], s.round) != s.round;
-      push_wave(p.slist, &p.ctl->scount, to_s, u);
-    }
-    uint32_t total;
-    const uint32_t excl = block_exclusive_scan(deg, &total, s_wsum);
-    s_pref[threadIdx.x] = excl;
-    s_beg[threadIdx.x] = beg;
-    s_tu[threadIdx.x] = tu;
+  if (schedule_first) after_step<W>(p, *s);
+  for (;;) {
+    load_sched(p.ctl, s);
+    const bool light = s->action == kActLight;
+    if (!(light || s->action == kActHeavy) || s->in_count > static_cast<uint32_t>(kChunk)) break;
+    const uint32_t edges = light ? step_edges<true>(p, *s, s_wsum) : step_edges<false>(p, *s, s_wsum);
+    if (edges > p.inline_edges) break;
+    if (threadIdx.x == 0) record_trace(p.ctl, 0x80u);
+    if (light) phase<W, true>(p, t, *s, st, sg, true);
+    else phase<W, false>(p, t, *s, st, sg, true);
+    drain_stores();
     __syncthreads();
-    if (threadIdx.x == 0) {
-      if (kLight) st.light_edges += total;
-      else st.heavy_edges += total;
-    }
-    const uint32_t rounds = (total + kWG - 1) / kWG;
-    for (uint32_t r = 0; r < rounds; ++r) {
-      const uint32_t e = r * kWG + threadIdx.x;
-      const bool active = e < total;
-      uint32_t owner = 0, v = 0, w = 0, tw = W::kInf;
-      if (active) {
-        uint32_t lo = 0, hi = kWG - 1;  // last entry whose range starts at or before e
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi + 1) >> 1;
-          if (s_pref[mid] <= e) lo = mid;
-          else hi = mid - 1;
-        }
-        owner = lo;
-        const uint64_t ed = p.edges[s_beg[owner] + (e - s_pref[owner])];
-        v = static_cast<uint32_t>(ed);
-        w = static_cast<uint32_t>(ed >> 32);
-        tw = s_tu[owner];
-      }
-      relax<W>(p, t, s, active, tw, v, w, near_end, st);
-    }
-    __syncthreads();
-  }
-}
-
-// Far-list redistribution: far vertices whose bucket is now within the ring
-// move into it; the rest move to the other far list.
-template <class W>
-__device__ void far_step(const Params& p, uint32_t* t, const Sched& s) {
-  const uint32_t count = s.in_count;
-  const uint32_t* list = p.far[s.far_cur];
-  const uint32_t nxt = 1u - s.far_cur;
-  const uint32_t near_end = s.far_base + p.ring;
-  const uint32_t iters = (count + gridDim.x * kWG - 1) / (gridDim.x * kWG);
-  for (uint32_t it = 0; it < iters; ++it) {
-    const uint32_t k = (it * gridDim.x + blockIdx.x) * kWG + threadIdx.x;
-    bool to_ring = false, to_far = false;
-    uint32_t v = 0, j = 0;
-    if (k < count) {
-      v = list[k];
-      // still only filed far (never moved into the ring since)?
-      if (ld_agent(&p.bstamp[v]) == kNone) {
-        j = W::bucket(ld_agent(&t[v]), p);
-        if (j < near_end) {
-          to_ring = atomicMin(&p.bstamp[v], j) > j;
-        } else {
-          atomicMin(&p.ctl->far_min_next, j);
-          to_far = atomicExch(&p.fstamp[v], s.far_epoch + 1u) != s.far_epoch + 1u;
-        }
-      }
-    }
-    push_ring(p, to_ring, j, v);
-    push_wave(p.far[nxt], &p.ctl->farcount[nxt], to_far, v);
-  }
-}
-
-// A candidate that did not fit marked its target; the distance of that target
-// is unrepresentable exactly when no other path reached it.
-template <class W>
-__device__ void overflow_step(const Params& p, uint32_t* t) {
-  for (uint32_t v = blockIdx.x * kWG + threadIdx.x; v < p.n; v += gridDim.x * kWG) {
-    if (p.ovf_at[v]) {
-      if (ld_agent(&t[v]) == W::kInf) st_agent(&p.ctl->ovf_real, 1u);
-      p.ovf_at[v] = 0;
-    }
+    after_step<W>(p, *s);
   }
 }
 
 template <class W>
 __global__ __launch_bounds__(kWG) void solver_kernel(Params p, const int32_t* sources, int k, uint32_t* dist) {
   __shared__ Sched s;
+  __shared__ Stage sg;
+  if (threadIdx.x == 0) sg.n = 0;
+  __syncthreads();
   WgStats st{0, 0, 0};
   bool alive = true;
   for (int r = 0; r < k && alive; ++r) {
     uint32_t* t = dist + static_cast<size_t>(r) * p.n;
     for (uint32_t v = blockIdx.x * kWG + threadIdx.x; v < p.n; v += gridDim.x * kWG) {
-      t[v] = W::kInf;
-      p.bstamp[v] = kNone;
+      st_agent(&t[v], W::kInf);
+      st_agent(&p.bstamp[v], kNone);
     }
     const uint32_t src = static_cast<uint32_t>(sources[r]);
-    if (!grid_sync(p.ctl, [&] { leader_start<W>(p, t, src); })) { alive = false; break; }
-    for (;;) {
+    alive = grid_sync(p.ctl, [&] {
+      leader_start<W>(p, t, src);
+      lead<W>(p, t, &s, st, sg, false);  // the first phases (around one vertex) are small
+    });
+    while (alive) {
       load_sched(p.ctl, &s);
       const uint32_t a = s.action;
       if (a == kActDone) break;
-      if (a == kActLight) {
-        phase<W, true>(p, t, s, st);
-        alive = grid_sync(p.ctl, [&] { leader_after_light<W>(p, s); });
-      } else if (a == kActHeavy) {
-        phase<W, false>(p, t, s, st);
-        alive = grid_sync(p.ctl, [&] { leader_after_heavy<W>(p, s); });
-      } else if (a == kActFar) {
-        far_step<W>(p, t, s);
-        alive = grid_sync(p.ctl, [&] { leader_after_far<W>(p, s); });
-      } else if (a == kActOverflowCheck) {
-        overflow_step<W>(p, t);
-        alive = grid_sync(p.ctl, [&] {
-          if (threadIdx.x == 0) st_agent(&p.ctl->action, static_cast<uint32_t>(kActDone));
-        });
-      } else {
-        alive = false;
-        if (threadIdx.x == 0) st_agent(&p.ctl->abort, 1u);
-      }
-      if (!alive) break;
+      if (a == kActLight) phase<W, true>(p, t, s, st, sg, false);
+      else if (a == kActHeavy) phase<W, false>(p, t, s, st, sg, false);
+      else if (a == kActHub) hub_step<W>(p, t, s, st, sg);
+      else if (a == kActFar) far_step<W>(p, t, s);
+      else if (a == kActOverflowCheck) overflow_step<W>(p, t);
+      else if (threadIdx.x == 0) st_agent(&p.ctl->abort, 1u);
+      alive = grid_sync(p.ctl, [&] { lead<W>(p, t, &s, st, sg, true); });
     }
   }
   // fold per-lane counters into the control block
@@ -579,13 +860,13 @@ __global__ __launch_bounds__(kWG) void solver_kernel(Params p, const int32_t* so
 
 // CSR and weight validation; max weight (as bits: positive floats order like
 // their bit patterns) and the fp32 weight total for the bucket-range check.
-__global__ __launch_bounds__(kWG) void validate_kernel(const int64_t* rp, const int32_t* col, const uint32_t* wbits,
-                                                       int wtype, int64_t n, int64_t m, uint32_t* status,
-                                                       uint32_t* wmax_bits, double* wsum) {
+__global__ __launch_bounds__(kAuxWG) void validate_kernel(const int64_t* rp, const int32_t* col,
+                                                          const uint32_t* wbits, int wtype, int64_t n, int64_t m,
+                                                          uint32_t* status, uint32_t* wmax_bits, double* wsum) {
   uint32_t bad = 0, wmax = 0;
   double sum = 0.0;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kWG;
-  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kAuxWG;
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kAuxWG + threadIdx.x;
   for (int64_t u = i0; u <= n; u += stride) {
     const int64_t a = rp[u];
     if (u == 0 && a != 0) bad |= kBadRowPtr;
@@ -621,11 +902,12 @@ __global__ __launch_bounds__(kWG) void validate_kernel(const int64_t* rp, const 
 // (w <= delta) first and its heavy edges (w > delta) after, each group in its
 // original order, as packed (destination | weight << 32) records; perm maps a
 // position back to the caller's edge index.
-__global__ __launch_bounds__(kWG) void split_kernel(const int64_t* rp, const int32_t* col, const uint32_t* wbits,
-                                                    int wtype, int64_t n, uint32_t delta_u, float delta_f,
-                                                    uint32_t* off, uint32_t* split, uint64_t* edges, uint32_t* perm) {
-  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x) >> 6;
-  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * kWG) >> 6;
+__global__ __launch_bounds__(kAuxWG) void split_kernel(const int64_t* rp, const int32_t* col, const uint32_t* wbits,
+                                                       int wtype, int64_t n, uint32_t delta_u, float delta_f,
+                                                       uint32_t* off, uint32_t* split, uint64_t* edges,
+                                                       uint32_t* perm) {
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kAuxWG + threadIdx.x) >> 6;
+  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * kAuxWG) >> 6;
   const uint32_t l = lane();
   for (int64_t u = wave; u < n; u += nwaves) {
     const int64_t b = rp[u], e = rp[u + 1];
@@ -669,8 +951,12 @@ __global__ __launch_bounds__(kWG) void split_kernel(const int64_t* rp, const int
 
 // Prepare the control block for a launch: clear the counters and the abort
 // flag (and the epochs when the de-duplication stamps were just cleared).
-__global__ void ctl_reset_kernel(Ctl* c, int reset_epochs) {
+__global__ void ctl_reset_kernel(Ctl* c, int reset_epochs, unsigned long long* trace, uint32_t trace_cap) {
   if (threadIdx.x != 0) return;
+  c->trace = trace;
+  c->trace_cap = trace_cap;
+  c->trace_len = 0;
+  for (uint32_t g = 0; g < kBarGroups; ++g) c->bar_sub[g][0] = 0;
   c->bar_arrive = 0;
   c->abort = 0;
   c->ovf_real = 0;
@@ -687,18 +973,18 @@ __global__ void ctl_reset_kernel(Ctl* c, int reset_epochs) {
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t launch_ctl_reset(Ctl* c, int reset_epochs, hipStream_t s) {
-  hipLaunchKernelGGL(ctl_reset_kernel, dim3(1), dim3(64), 0, s, c, reset_epochs);
+hipError_t launch_ctl_reset(Ctl* c, int reset_epochs, unsigned long long* trace, uint32_t trace_cap, hipStream_t s) {
+  hipLaunchKernelGGL(ctl_reset_kernel, dim3(1), dim3(64), 0, s, c, reset_epochs, trace, trace_cap);
   return hipGetLastError();
 }
 
 hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, const void* w, int wtype, int64_t n,
                            int64_t m, uint32_t* status, uint32_t* wmax_bits, double* wsum, hipStream_t s) {
   const int64_t work = m > n + 1 ? m : n + 1;
-  int64_t blocks = (work + kWG - 1) / kWG;
+  int64_t blocks = (work + kAuxWG - 1) / kAuxWG;
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(validate_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kWG), 0, s, row_ptr, col,
+  hipLaunchKernelGGL(validate_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kAuxWG), 0, s, row_ptr, col,
                      static_cast<const uint32_t*>(w), wtype, n, m, status, wmax_bits, wsum);
   return hipGetLastError();
 }
@@ -706,10 +992,10 @@ hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, const voi
 hipError_t launch_split(const int64_t* row_ptr, const int32_t* col, const void* w, int wtype, int64_t n,
                         uint32_t delta_u, float delta_f, uint32_t* off, uint32_t* split, uint64_t* edges,
                         uint32_t* perm, hipStream_t s) {
-  int64_t blocks = (n * 64 + kWG - 1) / kWG;
+  int64_t blocks = (n * 64 + kAuxWG - 1) / kAuxWG;
   if (blocks > 16384) blocks = 16384;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(split_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kWG), 0, s, row_ptr, col,
+  hipLaunchKernelGGL(split_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kAuxWG), 0, s, row_ptr, col,
                      static_cast<const uint32_t*>(w), wtype, n, delta_u, delta_f, off, split, edges, perm);
   return hipGetLastError();
 }

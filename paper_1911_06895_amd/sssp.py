@@ -26,8 +26,8 @@ SSSP_ERR_UNSUPPORTED = 7
 SSSP_WEIGHT_U32 = 0
 SSSP_WEIGHT_F32 = 1
 
-EXPORTS = ("sssp_create", "sssp_solve", "sssp_last_stats", "sssp_set_tuning", "sssp_graph_info", "sssp_destroy",
-           "sssp_status_string")
+EXPORTS = ("sssp_create", "sssp_solve", "sssp_last_stats", "sssp_set_tuning", "sssp_set_trace", "sssp_graph_info",
+           "sssp_destroy", "sssp_status_string")
 
 
 class SsspGraph(ctypes.Structure):
@@ -38,11 +38,12 @@ class SsspGraph(ctypes.Structure):
 class SsspStats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint64) for name in
                 ("sources", "buckets", "light_phases", "heavy_phases", "far_phases", "light_edges", "heavy_edges",
-                 "improvements", "barriers")]
+                 "improvements", "barriers", "trace_records")]
 
 
 class SsspTuning(ctypes.Structure):
-    _fields_ = [("workgroups_per_cu", ctypes.c_int32), ("ring_buckets", ctypes.c_int32)]
+    _fields_ = [("workgroups_per_cu", ctypes.c_int32), ("ring_buckets", ctypes.c_int32),
+                ("inline_edges", ctypes.c_int32)]
 
 
 class SsspError(RuntimeError):
@@ -71,6 +72,8 @@ def load_library(path: str = LIBRARY) -> ctypes.CDLL:
     lib.sssp_last_stats.restype = ctypes.c_int
     lib.sssp_set_tuning.argtypes = [P, ctypes.POINTER(SsspTuning)]
     lib.sssp_set_tuning.restype = ctypes.c_int
+    lib.sssp_set_trace.argtypes = [P, P, ctypes.c_int64]
+    lib.sssp_set_trace.restype = ctypes.c_int
     lib.sssp_graph_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                     ctypes.POINTER(ctypes.c_int32)]
     lib.sssp_graph_info.restype = ctypes.c_int
@@ -143,9 +146,30 @@ def sssp_last_stats(handle) -> dict:
     return {name: int(getattr(st, name)) for name, _ in SsspStats._fields_}
 
 
-def sssp_set_tuning(handle, workgroups_per_cu: int = 0, ring_buckets: int = 0) -> None:
-    t = SsspTuning(workgroups_per_cu=workgroups_per_cu, ring_buckets=ring_buckets)
+def sssp_set_tuning(handle, workgroups_per_cu: int = 0, ring_buckets: int = 0, inline_edges: int = 0) -> None:
+    t = SsspTuning(workgroups_per_cu=workgroups_per_cu, ring_buckets=ring_buckets, inline_edges=inline_edges)
     _check(load_library().sssp_set_tuning(handle, ctypes.byref(t)), "sssp_set_tuning")
+
+
+def sssp_set_trace(handle, buffer, capacity: int) -> None:
+    """buffer: GPU int64/uint64 tensor with at least 2 * capacity elements (or None)."""
+    ptr = ctypes.c_void_p(buffer.data_ptr()) if buffer is not None and capacity > 0 else None
+    _check(load_library().sssp_set_trace(handle, ptr, int(capacity) if ptr is not None else 0), "sssp_set_trace")
+
+
+ACTIONS = {1: "light", 2: "heavy", 3: "far", 4: "done", 5: "overflow-check", 6: "hub"}
+
+
+def decode_trace(words, records: int, clock_khz: float) -> list[dict]:
+    """Step records as dicts with the duration of each step in microseconds."""
+    w = np.asarray(words, dtype=np.uint64).reshape(-1, 2)[:records]
+    out = []
+    for k in range(len(w) - 1):
+        what = int(w[k, 1])
+        out.append({"action": ACTIONS.get(what & 0x7F, str(what & 0x7F)), "inline": bool(what & 0x80),
+                    "bucket": (what >> 8) & 0xFFFFFF, "entries": what >> 32,
+                    "us": float(int(w[k + 1, 0]) - int(w[k, 0])) * 1e3 / clock_khz})
+    return out
 
 
 def sssp_graph_info(handle) -> tuple[int, int, int]:
