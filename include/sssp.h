@@ -137,14 +137,15 @@ sssp_status sssp_set_tuning(sssp_handle *h, const sssp_tuning *t);
 
 /*
  * sssp_set_trace -- attach a step trace (profiling aid; NULL/0 detaches).
- *   device_buffer: DEVICE uint64 [2 * capacity], caller-owned, must stay valid
- *   while attached. Every later sssp_solve writes one record per device-wide
- *   step, from its start: word 0 = device wall clock (hipDeviceAttributeWallClockRate
- *   ticks) when the step began; word 1 = (input entries << 32) | (bucket & 0xFFFFFF) << 8
- *   | action (1 light phase, 2 heavy phase, 3 far redistribution, 4 done,
- *   5 overflow check, 6 high-degree pieces of the previous phase; bit 0x80 set
- *   when one workgroup ran the phase alone). Records past capacity are counted
- *   in trace_records but not written.
+ *   device_buffer: DEVICE uint64 [4 * capacity], caller-owned, must stay valid
+ *   while attached. Every later sssp_solve writes one record per step when the
+ *   step begins: word 0 = device wall clock (hipDeviceAttributeWallClockRate
+ *   ticks); word 1 = (input entries << 32) | (bucket & 0xFFFFFF) << 8 | action
+ *   (1 light phase, 2 heavy phase, 3 far redistribution, 4 done, 5 overflow
+ *   check, 6 high-degree pieces of the previous phase; bit 0x80 set when one
+ *   workgroup ran the phase alone); words 2 and 3 = edges scanned and distances
+ *   lowered by the previous step. Records past capacity are counted in
+ *   trace_records but not written. Tracing adds one atomic per workgroup per step.
  */
 sssp_status sssp_set_trace(sssp_handle *h, uint64_t *device_buffer, int64_t capacity);
 

@@ -22,6 +22,8 @@ struct sssp_handle {
   sssp_tuning tuning{};
   sssp::Params p{};
   uint32_t* perm = nullptr;
+  uint32_t* off = nullptr;    // [n+1] row starts of the split copy (solver ids)
+  uint32_t* split = nullptr;  // [n] end of each row's light edges
   int32_t* src_dev = nullptr;
   int32_t src_cap = 0;
   int32_t* src_host = nullptr;   // pinned staging for sources
@@ -59,9 +61,10 @@ hipError_t dalloc(T** p, size_t count) {
 void free_handle(sssp_handle* h) {
   if (!h) return;
   sssp::Params& p = h->p;
-  void* dev[] = {const_cast<uint32_t*>(p.off), const_cast<uint32_t*>(p.split), const_cast<uint64_t*>(p.edges),
+  void* dev[] = {h->off, h->split, const_cast<uint4*>(p.rows), const_cast<uint64_t*>(p.edges),
                  p.qstamp, p.sstamp, p.bstamp, p.fstamp, p.ovf_at, p.front[0], p.front[1], p.slist, p.bins,
-                 p.far[0], p.far[1], p.hub, p.ctl, h->perm, h->src_dev};
+                 p.far[0], p.far[1], p.hub, p.ctl, h->perm, h->src_dev, const_cast<uint32_t*>(p.vid), p.tbuf[0],
+                 p.tbuf[1]};
   for (void* q : dev)
     if (q) (void)hipFree(q);
   if (h->src_host) (void)hipHostFree(h->src_host);
@@ -148,9 +151,12 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   uint32_t *off = nullptr, *split = nullptr;
   uint64_t* edges = nullptr;
   SSSP_TRY(dalloc(&off, un + 1));
-  p.off = off;
+  h->off = off;
   SSSP_TRY(dalloc(&split, un));
-  p.split = split;
+  h->split = split;
+  uint4* rows = nullptr;
+  SSSP_TRY(dalloc(&rows, un));
+  p.rows = rows;
   SSSP_TRY(dalloc(&edges, um));
   p.edges = edges;
   SSSP_TRY(dalloc(&h->perm, um));
@@ -179,10 +185,20 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   SSSP_TRY(hipMemsetAsync(p.ctl, 0, sizeof(sssp::Ctl), stream));
   SSSP_TRY(sssp::launch_ctl_reset(p.ctl, 1, nullptr, 0, stream));
 
-  // 4. light/heavy split (A_L, A_H)
-  SSSP_TRY(sssp::launch_split(g->row_ptr, g->col_idx, g->weights, g->wtype, n, h->delta_u, h->delta_f, off, split,
-                              edges, h->perm, stream));
-  SSSP_TRY(hipStreamSynchronize(stream));
+  // 4. relabel by in-degree, then the light/heavy split (A_L, A_H)
+  uint32_t* vid = nullptr;
+  SSSP_TRY(dalloc(&vid, un));
+  p.vid = vid;
+  SSSP_TRY(dalloc(&p.tbuf[0], un));
+  SSSP_TRY(dalloc(&p.tbuf[1], un));
+  uint32_t* build = nullptr;
+  SSSP_TRY(dalloc(&build, sssp::build_scratch_words(n)));
+  hipError_t be = sssp::launch_relabel_and_split(g->row_ptr, g->col_idx, g->weights, g->wtype, n, m, h->delta_u,
+                                                 h->delta_f, build, vid, off, split, edges, h->perm, stream);
+  if (be == hipSuccess) be = sssp::launch_pack_rows(off, split, n, rows, stream);
+  if (be == hipSuccess) be = hipStreamSynchronize(stream);
+  (void)hipFree(build);
+  SSSP_TRY(be);
   return configure_grid(h);
 }
 

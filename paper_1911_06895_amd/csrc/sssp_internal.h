@@ -16,6 +16,7 @@ constexpr uint32_t kHub = 1024;        // a vertex with at least this many edges
 constexpr uint32_t kStage = 2 * kWG * kILP;  // LDS staging capacity for list appends (entries)
 constexpr uint32_t kBarGroups = 8;     // arrival sub-counters of the grid barrier
 constexpr uint32_t kRingMax = 64;      // near-bucket ring capacity
+constexpr uint32_t kDegClasses = 65536;  // in-degree classes of the relabelling (the last one open-ended)
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 // Tentative distances are kept as 32-bit patterns: uint32 values for integer
@@ -73,7 +74,8 @@ struct Ctl {
   uint32_t ovf_seen;     // some candidate did not fit the distance type
   uint32_t ovf_real;     // a reachable vertex has an unrepresentable distance
   uint32_t trace_len;    // step records written (may exceed trace_cap)
-  unsigned long long* trace;  // optional step trace: 2 words per record
+  unsigned long long* trace;  // optional step trace: 4 words per record
+  unsigned long long tr_edges, tr_impr;  // edges scanned and improvements of the running step (traced runs)
   uint32_t trace_cap;
   uint32_t pad;
   uint32_t bincount[kRingMax];
@@ -90,8 +92,9 @@ struct Params {
   uint32_t delta_u;     // u32 delta
   double delta_d;       // f32: (double)(float)delta
   double inv_delta_d;   // f32: 1 / delta_d (an estimate; bucket indices are corrected exactly)
-  const uint32_t* off;    // [n+1] row starts of the split copy
-  const uint32_t* split;  // [n] end of the light range of each row
+  const uint32_t* vid;    // [n] solver id of each caller vertex (decreasing in-degree order)
+  uint32_t* tbuf[2];      // [n] tentative distances in solver ids (alternating between sources)
+  const uint4* rows;      // [n] row u of the split copy: (start, end of light edges, end, 0)
   const uint64_t* edges;  // [m] (destination | weight bits << 32)
   uint32_t* qstamp;       // [n] frontier tag of the last push
   uint32_t* sstamp;       // [n] round tag of the last S insertion
@@ -111,10 +114,13 @@ struct Params {
 // launchers (sssp_kernels.hip)
 hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, const void* w, int wtype, int64_t n,
                            int64_t m, uint32_t* status, uint32_t* wmax_bits, double* wsum, hipStream_t s);
-hipError_t launch_split(const int64_t* row_ptr, const int32_t* col, const void* w, int wtype, int64_t n,
-                        uint32_t delta_u, float delta_f, uint32_t* off, uint32_t* split, uint64_t* edges,
-                        uint32_t* perm, hipStream_t s);
+size_t build_scratch_words(int64_t n);
+hipError_t launch_relabel_and_split(const int64_t* row_ptr, const int32_t* col, const void* w, int wtype, int64_t n,
+                                    int64_t m, uint32_t delta_u, float delta_f, uint32_t* scratch,
+                                    uint32_t* new_id, uint32_t* off, uint32_t* split, uint64_t* edges,
+                                    uint32_t* perm, hipStream_t s);
 hipError_t solver_occupancy(int wtype, int* blocks_per_cu);
+hipError_t launch_pack_rows(const uint32_t* off, const uint32_t* split, int64_t n, uint4* rows, hipStream_t s);
 hipError_t launch_ctl_reset(Ctl* c, int reset_epochs, unsigned long long* trace, uint32_t trace_cap, hipStream_t s);
 hipError_t launch_solver(const Params& p, const int32_t* sources, int k, uint32_t* dist, int grid,
                          hipStream_t s);

@@ -182,8 +182,10 @@ __device__ inline void record_trace(Ctl* c, uint32_t flags) {
     const unsigned long long what = static_cast<unsigned long long>(ld_agent(&c->in_count)) << 32 |
                                     static_cast<unsigned long long>(ld_agent(&c->bucket) & 0xFFFFFFu) << 8 |
                                     (ld_agent(&c->action) | flags);
-    st_agent(&c->trace[2 * idx], static_cast<unsigned long long>(wall_clock64()));
-    st_agent(&c->trace[2 * idx + 1], what);
+    st_agent(&c->trace[4 * idx], static_cast<unsigned long long>(wall_clock64()));
+    st_agent(&c->trace[4 * idx + 1], what);
+    st_agent(&c->trace[4 * idx + 2], __hip_atomic_exchange(&c->tr_edges, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    st_agent(&c->trace[4 * idx + 3], __hip_atomic_exchange(&c->tr_impr, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
   }
 }
 
@@ -247,7 +249,36 @@ __device__ bool grid_sync(Ctl* c, F&& leader) {
 
 struct WgStats {
   unsigned long long light_edges, heavy_edges, improvements;
+  unsigned long long step_edges, step_impr;  // since the last traced step boundary
 };
+
+// Traced runs only: add this workgroup's counts of the finished step to the
+// control block (one atomic per workgroup), for the next trace record.
+__device__ inline void trace_step_counts(Ctl* c, WgStats& st) {
+  if (!c->trace) return;
+  __shared__ unsigned long long s_e[kWG / 64], s_i[kWG / 64];
+  unsigned long long e = st.step_edges, im = st.step_impr;
+  st.step_edges = st.step_impr = 0;
+  for (int d = 32; d > 0; d >>= 1) {
+    e += __shfl_down(e, d);
+    im += __shfl_down(im, d);
+  }
+  if (lane() == 0) {
+    s_e[threadIdx.x >> 6] = e;
+    s_i[threadIdx.x >> 6] = im;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long te = 0, ti = 0;
+    for (int w = 0; w < kWG / 64; ++w) {
+      te += s_e[w];
+      ti += s_i[w];
+    }
+    if (te) atomicAdd(&c->tr_edges, te);
+    if (ti) atomicAdd(&c->tr_impr, ti);
+  }
+  __syncthreads();
+}
 
 // Append winners to the ring slot of their bucket. Lanes are grouped by
 // bucket with ballots only; then every group leader issues its atomic at the
@@ -280,7 +311,8 @@ __device__ inline void push_ring(const Params& p, bool pred, uint32_t j, uint32_
 // global atomic per destination list per flush instead of one per wave.
 constexpr uint32_t kSlotFront = kRingMax;     // the current bucket's next frontier
 constexpr uint32_t kSlotFar = kRingMax + 1;   // the far list
-constexpr uint32_t kSlots = kRingMax + 2;     // ring slots 0..kRingMax-1, then the two above
+constexpr uint32_t kSlotS = kRingMax + 2;     // S, the vertices expanded in this bucket
+constexpr uint32_t kSlots = kRingMax + 3;     // ring slots 0..kRingMax-1, then the three above
 constexpr uint32_t kNoSlot = 0xFFu;
 
 struct Stage {
@@ -342,15 +374,19 @@ __device__ void stage_flush(const Params& p, const Sched& s, Stage& sg, bool for
   if (threadIdx.x < kSlots) {
     const uint32_t k = threadIdx.x;
     const uint32_t c = sg.cnt[k];
-    uint32_t* ctr = k < kRingMax ? &p.ctl->bincount[k] : k == kSlotFront ? &p.ctl->fcount[s.out_buf]
-                                                                         : &p.ctl->farcount[s.far_cur];
+    uint32_t* ctr = k < kRingMax      ? &p.ctl->bincount[k]
+                    : k == kSlotFront ? &p.ctl->fcount[s.out_buf]
+                    : k == kSlotFar   ? &p.ctl->farcount[s.far_cur]
+                                      : &p.ctl->scount;
     sg.base[k] = c ? atomicAdd(ctr, c) : 0u;
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < n; i += kWG) {
     const uint32_t slot = sg.slot[i];
-    uint32_t* list = slot < kRingMax ? p.bins + static_cast<size_t>(slot) * p.n
-                                     : slot == kSlotFront ? p.front[s.out_buf] : p.far[s.far_cur];
+    uint32_t* list = slot < kRingMax      ? p.bins + static_cast<size_t>(slot) * p.n
+                     : slot == kSlotFront ? p.front[s.out_buf]
+                     : slot == kSlotFar   ? p.far[s.far_cur]
+                                          : p.slist;
     st_agent(&list[sg.base[slot] + sg.rank[i]], sg.v[i]);
   }
   __syncthreads();
@@ -400,7 +436,10 @@ __device__ inline void relax_batch(const Params& p, uint32_t* t, const Sched& s,
 #pragma unroll
   for (uint32_t q = 0; q < kILP; ++q) {
     const uint64_t wins = __ballot(win[q]);
-    if (lane() == 0) st.improvements += __popcll(wins);
+    if (lane() == 0) {
+      st.improvements += __popcll(wins);
+      st.step_impr += __popcll(wins);
+    }
     stage_push(sg, slot[q] != kNoSlot, slot[q], v[q]);
   }
 }
@@ -466,24 +505,29 @@ __device__ void phase(const Params& p, uint32_t* t, const Sched& s, WgStats& st,
       // a ring slot may hold vertices that have since moved to a lower bucket
       take = !from_bin || in_bucket<W>(tu, s);
       if (take) {
-        if (kLight) {
-          beg = p.off[u];
-          deg = p.split[u] - beg;
-        } else {
-          beg = p.split[u];
-          deg = p.off[u + 1] - beg;
-        }
+        const uint4 row = p.rows[u];
+        beg = kLight ? row.x : row.y;
+        deg = (kLight ? row.y : row.z) - beg;
       }
     }
     if (kLight) {  // S = (S + t_Bi) > 0: each expanded vertex joins S once per round
       bool to_s = false;
-      if (take && ld_agent(&p.sstamp[u]) != s.round) to_s = atomicExch(&p.sstamp[u], s.round) != s.round;
-      push_wave(p.slist, &p.ctl->scount, to_s, u);
+      if (take) {
+        if (from_bin) {  // the first phase of a round: ring-slot entries are distinct and new to S
+          st_agent(&p.sstamp[u], s.round);
+          to_s = true;
+        } else if (ld_agent(&p.sstamp[u]) != s.round) {
+          to_s = atomicExch(&p.sstamp[u], s.round) != s.round;
+        }
+      }
+      stage_push(sg, to_s, kSlotS, u);
+      stage_flush(p, s, sg, false);
     }
     if (!solo && deg >= kHub) {
       queue_hub(p, u, deg);
       if (kLight) st.light_edges += deg;
       else st.heavy_edges += deg;
+      st.step_edges += deg;
       deg = 0;
     }
     uint32_t total;
@@ -497,6 +541,7 @@ __device__ void phase(const Params& p, uint32_t* t, const Sched& s, WgStats& st,
     if (threadIdx.x == 0) {
       if (kLight) st.light_edges += total;
       else st.heavy_edges += total;
+      st.step_edges += total;
     }
     const uint32_t rounds = (total + kWG * kILP - 1) / (kWG * kILP);
     for (uint32_t r = 0; r < rounds; ++r) {
@@ -543,8 +588,9 @@ __device__ void hub_step(const Params& p, uint32_t* t, const Sched& s, WgStats& 
       const uint64_t rec = ld_agent(&p.hub[c]);
       const uint32_t u = static_cast<uint32_t>(rec);
       const uint32_t piece = static_cast<uint32_t>(rec >> 32);
-      const uint32_t b = light ? p.off[u] : p.split[u];
-      const uint32_t e = light ? p.split[u] : p.off[u + 1];
+      const uint4 row = p.rows[u];
+      const uint32_t b = light ? row.x : row.y;
+      const uint32_t e = light ? row.y : row.z;
       const uint32_t pb = b + piece * kPiece;
       s_beg = pb;
       s_end = e - pb > kPiece ? pb + kPiece : e;
@@ -782,7 +828,8 @@ __device__ uint32_t step_edges(const Params& p, const Sched& s, uint32_t* s_wsum
   uint32_t deg = 0;
   if (threadIdx.x < s.in_count) {
     const uint32_t u = ld_agent(&list[threadIdx.x]);
-    deg = kLight ? p.split[u] - p.off[u] : p.off[u + 1] - p.split[u];
+    const uint4 row = p.rows[u];
+    deg = kLight ? row.y - row.x : row.z - row.y;
   }
   uint32_t total;
   (void)block_exclusive_scan(deg, &total, s_wsum);
@@ -804,6 +851,7 @@ __device__ void lead(const Params& p, uint32_t* t, Sched* s, WgStats& st, Stage&
     if (threadIdx.x == 0) record_trace(p.ctl, 0x80u);
     if (light) phase<W, true>(p, t, *s, st, sg, true);
     else phase<W, false>(p, t, *s, st, sg, true);
+    trace_step_counts(p.ctl, st);
     drain_stores();
     __syncthreads();
     after_step<W>(p, *s);
@@ -816,15 +864,17 @@ __global__ __launch_bounds__(kWG) void solver_kernel(Params p, const int32_t* so
   __shared__ Stage sg;
   if (threadIdx.x == 0) sg.n = 0;
   __syncthreads();
-  WgStats st{0, 0, 0};
+  WgStats st{0, 0, 0, 0, 0};
   bool alive = true;
   for (int r = 0; r < k && alive; ++r) {
-    uint32_t* t = dist + static_cast<size_t>(r) * p.n;
+    // distances live in solver ids; consecutive sources alternate buffers so that
+    // copying out source r never races with the initialisation of source r + 1
+    uint32_t* t = p.tbuf[r & 1];
     for (uint32_t v = blockIdx.x * kWG + threadIdx.x; v < p.n; v += gridDim.x * kWG) {
       st_agent(&t[v], W::kInf);
       st_agent(&p.bstamp[v], kNone);
     }
-    const uint32_t src = static_cast<uint32_t>(sources[r]);
+    const uint32_t src = p.vid[sources[r]];
     alive = grid_sync(p.ctl, [&] {
       leader_start<W>(p, t, src);
       lead<W>(p, t, &s, st, sg, false);  // the first phases (around one vertex) are small
@@ -839,7 +889,13 @@ __global__ __launch_bounds__(kWG) void solver_kernel(Params p, const int32_t* so
       else if (a == kActFar) far_step<W>(p, t, s);
       else if (a == kActOverflowCheck) overflow_step<W>(p, t);
       else if (threadIdx.x == 0) st_agent(&p.ctl->abort, 1u);
+      trace_step_counts(p.ctl, st);
       alive = grid_sync(p.ctl, [&] { lead<W>(p, t, &s, st, sg, true); });
+    }
+    if (alive) {  // row r of the output in the caller's vertex numbering
+      uint32_t* out = dist + static_cast<size_t>(r) * p.n;
+      for (uint32_t v = blockIdx.x * kWG + threadIdx.x; v < p.n; v += gridDim.x * kWG)
+        out[v] = ld_agent(&t[p.vid[v]]);
     }
   }
   // fold per-lane counters into the control block
@@ -856,99 +912,6 @@ __global__ __launch_bounds__(kWG) void solver_kernel(Params p, const int32_t* so
   }
 }
 
-// ------------------------------------------------------------------ create-time kernels
-
-// CSR and weight validation; max weight (as bits: positive floats order like
-// their bit patterns) and the fp32 weight total for the bucket-range check.
-__global__ __launch_bounds__(kAuxWG) void validate_kernel(const int64_t* rp, const int32_t* col,
-                                                          const uint32_t* wbits, int wtype, int64_t n, int64_t m,
-                                                          uint32_t* status, uint32_t* wmax_bits, double* wsum) {
-  uint32_t bad = 0, wmax = 0;
-  double sum = 0.0;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kAuxWG;
-  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kAuxWG + threadIdx.x;
-  for (int64_t u = i0; u <= n; u += stride) {
-    const int64_t a = rp[u];
-    if (u == 0 && a != 0) bad |= kBadRowPtr;
-    if (u == n && a != m) bad |= kBadRowPtr;
-    if (u < n && rp[u + 1] < a) bad |= kBadRowPtr;
-  }
-  for (int64_t e = i0; e < m; e += stride) {
-    const int32_t c = col[e];
-    if (c < 0 || c >= n) bad |= kBadCol;
-    const uint32_t wb = wbits[e];
-    if (wtype == 0) {
-      if (wb == 0) bad |= kBadWeight;
-    } else {
-      // reject -0.0 and negatives (sign bit), +0.0, and inf/NaN (exponent all ones)
-      if ((wb & 0x80000000u) || wb == 0 || (wb & 0x7F800000u) == 0x7F800000u) bad |= kBadWeight;
-      else sum += static_cast<double>(__uint_as_float(wb));
-    }
-    wmax = max(wmax, wb);
-  }
-  for (int d = 32; d > 0; d >>= 1) {
-    bad |= __shfl_down(bad, d);
-    wmax = max(wmax, __shfl_down(wmax, d));
-    sum += __shfl_down(sum, d);
-  }
-  if (lane() == 0) {
-    if (bad) atomicOr(status, bad);
-    if (wmax) atomicMax(wmax_bits, wmax);
-    if (sum != 0.0) atomicAdd(wsum, sum);
-  }
-}
-
-// Light/heavy split (Sec. IV-A): one wave per row writes the row's light edges
-// (w <= delta) first and its heavy edges (w > delta) after, each group in its
-// original order, as packed (destination | weight << 32) records; perm maps a
-// position back to the caller's edge index.
-__global__ __launch_bounds__(kAuxWG) void split_kernel(const int64_t* rp, const int32_t* col, const uint32_t* wbits,
-                                                       int wtype, int64_t n, uint32_t delta_u, float delta_f,
-                                                       uint32_t* off, uint32_t* split, uint64_t* edges,
-                                                       uint32_t* perm) {
-  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kAuxWG + threadIdx.x) >> 6;
-  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * kAuxWG) >> 6;
-  const uint32_t l = lane();
-  for (int64_t u = wave; u < n; u += nwaves) {
-    const int64_t b = rp[u], e = rp[u + 1];
-    uint32_t nlight = 0;
-    for (int64_t x = b; x < e; x += 64) {
-      bool light = false;
-      if (x + l < e) {
-        const uint32_t wb = wbits[x + l];
-        light = wtype == 0 ? wb <= delta_u : __uint_as_float(wb) <= delta_f;
-      }
-      nlight += static_cast<uint32_t>(__popcll(__ballot(light)));
-    }
-    if (l == 0) {
-      off[u] = static_cast<uint32_t>(b);
-      split[u] = static_cast<uint32_t>(b) + nlight;
-      if (u == n - 1) off[n] = static_cast<uint32_t>(e);
-    }
-    uint32_t lpos = static_cast<uint32_t>(b), hpos = static_cast<uint32_t>(b) + nlight;
-    for (int64_t x = b; x < e; x += 64) {
-      const bool in = x + l < e;
-      bool light = false;
-      uint32_t wb = 0;
-      int32_t c = 0;
-      if (in) {
-        wb = wbits[x + l];
-        c = col[x + l];
-        light = wtype == 0 ? wb <= delta_u : __uint_as_float(wb) <= delta_f;
-      }
-      const uint64_t ml = __ballot(in && light);
-      const uint64_t mh = __ballot(in && !light);
-      if (in) {
-        const uint32_t pos = light ? lpos + lanes_below(ml) : hpos + lanes_below(mh);
-        edges[pos] = static_cast<uint64_t>(static_cast<uint32_t>(c)) | (static_cast<uint64_t>(wb) << 32);
-        perm[pos] = static_cast<uint32_t>(x + l);
-      }
-      lpos += static_cast<uint32_t>(__popcll(ml));
-      hpos += static_cast<uint32_t>(__popcll(mh));
-    }
-  }
-}
-
 // Prepare the control block for a launch: clear the counters and the abort
 // flag (and the epochs when the de-duplication stamps were just cleared).
 __global__ void ctl_reset_kernel(Ctl* c, int reset_epochs, unsigned long long* trace, uint32_t trace_cap) {
@@ -956,6 +919,8 @@ __global__ void ctl_reset_kernel(Ctl* c, int reset_epochs, unsigned long long* t
   c->trace = trace;
   c->trace_cap = trace_cap;
   c->trace_len = 0;
+  c->tr_edges = 0;
+  c->tr_impr = 0;
   for (uint32_t g = 0; g < kBarGroups; ++g) c->bar_sub[g][0] = 0;
   c->bar_arrive = 0;
   c->abort = 0;
@@ -975,28 +940,6 @@ __global__ void ctl_reset_kernel(Ctl* c, int reset_epochs, unsigned long long* t
 
 hipError_t launch_ctl_reset(Ctl* c, int reset_epochs, unsigned long long* trace, uint32_t trace_cap, hipStream_t s) {
   hipLaunchKernelGGL(ctl_reset_kernel, dim3(1), dim3(64), 0, s, c, reset_epochs, trace, trace_cap);
-  return hipGetLastError();
-}
-
-hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, const void* w, int wtype, int64_t n,
-                           int64_t m, uint32_t* status, uint32_t* wmax_bits, double* wsum, hipStream_t s) {
-  const int64_t work = m > n + 1 ? m : n + 1;
-  int64_t blocks = (work + kAuxWG - 1) / kAuxWG;
-  if (blocks > 8192) blocks = 8192;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(validate_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kAuxWG), 0, s, row_ptr, col,
-                     static_cast<const uint32_t*>(w), wtype, n, m, status, wmax_bits, wsum);
-  return hipGetLastError();
-}
-
-hipError_t launch_split(const int64_t* row_ptr, const int32_t* col, const void* w, int wtype, int64_t n,
-                        uint32_t delta_u, float delta_f, uint32_t* off, uint32_t* split, uint64_t* edges,
-                        uint32_t* perm, hipStream_t s) {
-  int64_t blocks = (n * 64 + kAuxWG - 1) / kAuxWG;
-  if (blocks > 16384) blocks = 16384;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(split_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kAuxWG), 0, s, row_ptr, col,
-                     static_cast<const uint32_t*>(w), wtype, n, delta_u, delta_f, off, split, edges, perm);
   return hipGetLastError();
 }
 

@@ -152,7 +152,7 @@ def sssp_set_tuning(handle, workgroups_per_cu: int = 0, ring_buckets: int = 0, i
 
 
 def sssp_set_trace(handle, buffer, capacity: int) -> None:
-    """buffer: GPU int64/uint64 tensor with at least 2 * capacity elements (or None)."""
+    """buffer: GPU int64/uint64 tensor with at least 4 * capacity elements (or None)."""
     ptr = ctypes.c_void_p(buffer.data_ptr()) if buffer is not None and capacity > 0 else None
     _check(load_library().sssp_set_trace(handle, ptr, int(capacity) if ptr is not None else 0), "sssp_set_trace")
 
@@ -161,13 +161,14 @@ ACTIONS = {1: "light", 2: "heavy", 3: "far", 4: "done", 5: "overflow-check", 6: 
 
 
 def decode_trace(words, records: int, clock_khz: float) -> list[dict]:
-    """Step records as dicts with the duration of each step in microseconds."""
-    w = np.asarray(words, dtype=np.uint64).reshape(-1, 2)[:records]
+    """Step records as dicts: duration in microseconds, entries, edges scanned, distances lowered."""
+    w = np.asarray(words, dtype=np.uint64).reshape(-1, 4)[:records]
     out = []
     for k in range(len(w) - 1):
         what = int(w[k, 1])
         out.append({"action": ACTIONS.get(what & 0x7F, str(what & 0x7F)), "inline": bool(what & 0x80),
                     "bucket": (what >> 8) & 0xFFFFFF, "entries": what >> 32,
+                    "edges": int(w[k + 1, 2]), "improved": int(w[k + 1, 3]),
                     "us": float(int(w[k + 1, 0]) - int(w[k, 0])) * 1e3 / clock_khz})
     return out
 
