@@ -100,10 +100,38 @@ __global__ __launch_bounds__(kB) void indegree_kernel(const int32_t* col, int64_
 
 __device__ inline uint32_t degree_class(uint32_t d) { return d < kDegClasses - 1 ? d : kDegClasses - 1; }
 
+// Lanes of a wave holding the same key form a group; returns this lane's group
+// (as a lane mask) and its leader, with ballots only. Degree classes are very
+// unequal in size, so one atomic per group instead of per lane avoids long
+// same-address queues.
+__device__ inline uint64_t group_by_key(bool active, uint32_t key, int* leader) {
+  uint64_t rest = __ballot(active), mine = 0;
+  *leader = 0;
+  while (rest) {
+    const int l = __ffsll(static_cast<unsigned long long>(rest)) - 1;
+    const uint32_t kl = __builtin_amdgcn_readlane(key, l);
+    const bool same = active && key == kl;
+    const uint64_t grp = __ballot(same);
+    if (same) {
+      mine = grp;
+      *leader = l;
+    }
+    rest &= ~grp;
+  }
+  return mine;
+}
+
 __global__ __launch_bounds__(kB) void degree_histogram_kernel(const uint32_t* indeg, int64_t n, uint32_t* hist) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kB;
-  for (int64_t v = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x; v < n; v += stride)
-    atomicAdd(&hist[degree_class(indeg[v])], 1u);
+  const int64_t iters = (n + stride - 1) / stride;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t v = it * stride + static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+    const bool active = v < n;
+    const uint32_t c = active ? degree_class(indeg[v]) : 0u;
+    int leader;
+    const uint64_t grp = group_by_key(active, c, &leader);
+    if (active && static_cast<int>(lane_id()) == leader) atomicAdd(&hist[c], static_cast<uint32_t>(__popcll(grp)));
+  }
 }
 
 // cursor[d] = number of vertices in higher degree classes (one block)
@@ -125,8 +153,18 @@ __global__ __launch_bounds__(kB) void class_start_kernel(const uint32_t* hist, u
 __global__ __launch_bounds__(kB) void assign_ids_kernel(const uint32_t* indeg, int64_t n, uint32_t* cursor,
                                                         uint32_t* new_id) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kB;
-  for (int64_t v = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x; v < n; v += stride)
-    new_id[v] = atomicAdd(&cursor[degree_class(indeg[v])], 1u);
+  const int64_t iters = (n + stride - 1) / stride;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t v = it * stride + static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+    const bool active = v < n;
+    const uint32_t c = active ? degree_class(indeg[v]) : 0u;
+    int leader;
+    const uint64_t grp = group_by_key(active, c, &leader);
+    uint32_t base = 0;
+    if (active && static_cast<int>(lane_id()) == leader) base = atomicAdd(&cursor[c], static_cast<uint32_t>(__popcll(grp)));
+    base = __shfl(base, leader);
+    if (active) new_id[v] = base + lanes_below(grp);
+  }
 }
 
 // out-degree of each vertex, stored at its new id

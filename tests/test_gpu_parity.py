@@ -232,3 +232,37 @@ def test_tuning_variants_agree():
     for wpc in (1, 2, 4):
         got, _ = gpu_solve(g, 16, [s], tuning={"workgroups_per_cu": wpc})
         assert_exact(g, got[0], s, f"wg/cu={wpc}")
+
+
+@pytest.fixture(scope="module")
+def rmat_s22():
+    return G.workload("rmat_s22_u32")
+
+
+def test_rmat_s22_bench_configuration(rmat_s22):
+    """The benchmark's launch: R-MAT scale 22, 64 sources in one call, delta 64. Two rows are
+    compared with the oracle vertex by vertex, eight are checked by the optimality certificate."""
+    g = rmat_s22
+    srcs = G.sources_with_outedges(g, 64, cfg=2)
+    got, st = gpu_solve(g, 64, srcs)
+    assert st["sources"] == 64
+    for r in range(2):
+        assert_exact(g, got[r], srcs[r], "rmat s22 delta=64")
+    for r in range(2, 8):
+        assert oracle.certify(g, int(srcs[r]), got[r]) == oracle.CERT_OK, f"row {r}"
+
+
+def test_rmat_s22_small_delta(rmat_s22):
+    g = rmat_s22
+    srcs = G.sources_with_outedges(g, 64, cfg=2)[-1:]
+    got, _ = gpu_solve(g, 8, srcs)
+    assert_exact(g, got[0], srcs[0], "rmat s22 delta=8")
+
+
+def test_grid_4096_many_buckets():
+    """The high-diameter grid: about 10^4 buckets with small frontiers (corner source)."""
+    g = G.workload("grid4096_u32")
+    got, st = gpu_solve(g, 400, [0])
+    assert oracle.certify(g, 0, got[0]) == oracle.CERT_OK
+    assert_exact(g, got[0], 0, "grid4096 delta=400")
+    assert st["buckets"] >= len(np.unique(got[0] // 400))
