@@ -86,6 +86,8 @@ class Oracle:
         lib.orc_certify.restype = ctypes.c_int
         lib.orc_bucket_of.argtypes = [ctypes.c_double, ctypes.c_double]
         lib.orc_bucket_of.restype = ctypes.c_int64
+        lib.orc_sp_gradient.argtypes = [I64, P, P, P, ctypes.c_int, ctypes.c_int32, P, P, P, P]
+        lib.orc_sp_gradient.restype = ctypes.c_int
         self.lib = lib
 
     def dijkstra(self, g, src: int) -> tuple[np.ndarray, int]:
@@ -146,6 +148,21 @@ class Oracle:
     def bucket_of(self, t: float, delta: float) -> int:
         return int(self.lib.orc_bucket_of(float(t), float(delta)))
 
+    def sp_gradient(self, g, src: int, dist: np.ndarray, grad_dist: np.ndarray, grad_w: np.ndarray | None = None):
+        """Accumulate dL/dw (float64 [m], caller edge order) for L = sum grad_dist * dist over the
+        shortest-path tree from ``src``; returns (grad_w, parent_edge int64 [n])."""
+        rp, col, w, kind = _csr(g)
+        d = np.ascontiguousarray(dist, dtype=w.dtype)
+        gd = np.ascontiguousarray(grad_dist, dtype=np.float64)
+        if grad_w is None:
+            grad_w = np.zeros(g.m, dtype=np.float64)
+        pe = np.empty(g.n, dtype=np.int64)
+        rc = self.lib.orc_sp_gradient(g.n, _ptr(rp), _ptr(col), _ptr(w), kind, int(src), _ptr(d), _ptr(gd),
+                                      _ptr(grad_w), _ptr(pe))
+        if rc != OK:
+            raise ValueError(f"sp_gradient: distances are not a shortest-path vector ({rc})")
+        return grad_w, pe
+
 
 _default: Oracle | None = None
 
@@ -181,6 +198,10 @@ def certify(g, src, dist):
 
 def bucket_of(t, delta):
     return default().bucket_of(t, delta)
+
+
+def sp_gradient(g, src, dist, grad_dist, grad_w=None):
+    return default().sp_gradient(g, src, dist, grad_dist, grad_w)
 
 
 def reached_edges(g, dist: np.ndarray) -> int:

@@ -28,7 +28,8 @@
  *   orc_delta_sets    Meyer-Sanders delta-stepping with explicit buckets and
  *                     the relax procedure (Sec. III-C, Fig. 1 right);
  *   orc_bellman_ford  brute-force Bellman-Ford (n rounds over all edges);
- *   orc_certify       O(m) optimality certificate of a candidate distance vector.
+ *   orc_certify       O(m) optimality certificate of a candidate distance vector;
+ *   orc_sp_gradient   dL/dw by reverse accumulation over the shortest-path tree.
  *
  * Build: gcc -O2 -fPIC -shared -ffp-contract=off -fno-fast-math (x86-64 SSE
  * arithmetic: float and double operations are rounded once, no excess precision).
@@ -554,4 +555,84 @@ int orc_certify(int64_t n, const int64_t *rp, const int32_t *col, const void *w,
   }
   free(d); free(seen); free(queue);
   return verdict;
+}
+
+/* ------------------------------------------------------------ adjoint */
+
+/*
+ * Gradient of L = sum over reached v of grad_dist[v] * d(v) with respect to
+ * the edge weights, through the shortest-path tree (reverse accumulation).
+ *   parent of v != s (d(v) finite): the tight in-edge (d(u) finite and
+ *   d(u) (+) w == d(v)) with the smallest edge index; d(v) is the fold of the
+ *   weights along its tree path, so dd(v)/dw_e = 1 for the edges of that path
+ *   and 0 otherwise, and dL/dw_e for e = (parent(v), v) is the sum of
+ *   grad_dist over the subtree below v (grad_dist of s and of unreached
+ *   vertices is ignored). Where several shortest paths tie, this is the
+ *   gradient along the chosen tree (a subgradient).
+ * grad_w is ACCUMULATED (+=), in double. parent_edge (optional) receives the
+ * chosen edge index of every vertex, -1 for s and unreached vertices.
+ * Returns ORC_BADARG when dist is not a shortest-path vector (a reached vertex
+ * without a tight in-edge, or parent pointers that do not lead to s).
+ */
+int orc_sp_gradient(int64_t n, const int64_t *rp, const int32_t *col, const void *w, int kind, int32_t src,
+                    const void *dist, const double *grad_dist, double *grad_w, int64_t *parent_edge) {
+  if (!check_args(n, rp, col, src) || kind < 0 || kind > 2 || !dist || !grad_dist || !grad_w) return ORC_BADARG;
+  double *d = malloc(sizeof(double) * n), *g = malloc(sizeof(double) * n);
+  int64_t *pe = malloc(sizeof(int64_t) * n), *pv = malloc(sizeof(int64_t) * n);
+  int64_t *nchild = calloc(n + 1, sizeof(int64_t)), *child = malloc(sizeof(int64_t) * (n + 1));
+  int64_t *stack = malloc(sizeof(int64_t) * (n + 1)), *order = malloc(sizeof(int64_t) * (n + 1));
+  if (!d || !g || !pe || !pv || !nchild || !child || !stack || !order) {
+    free(d); free(g); free(pe); free(pv); free(nchild); free(child); free(stack); free(order);
+    return ORC_NOMEM;
+  }
+  int rc = ORC_OK;
+  for (int64_t v = 0; v < n; ++v) { d[v] = load_dist(kind, dist, v); pe[v] = -1; pv[v] = -1; }
+  /* parents: smallest-index tight in-edge */
+  for (int64_t u = 0; u < n; ++u) {
+    if (isinf(d[u])) continue;
+    for (int64_t e = rp[u]; e < rp[u + 1]; ++e) {
+      int64_t v = col[e];
+      if (v == src) continue;
+      int ovf;
+      double c = plus(kind, d[u], weight_of(kind, w, e), &ovf);
+      if (!ovf && c == d[v] && (pe[v] < 0 || e < pe[v])) { pe[v] = e; pv[v] = u; }
+    }
+  }
+  int64_t reached = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    if (isinf(d[v])) continue;
+    reached++;
+    if (v != src && pe[v] < 0) rc = ORC_BADARG;
+  }
+  if (rc == ORC_OK) {
+    /* children lists (CSR over parent vertices) */
+    for (int64_t v = 0; v < n; ++v) if (pv[v] >= 0) nchild[pv[v] + 1]++;
+    for (int64_t v = 0; v < n; ++v) nchild[v + 1] += nchild[v];
+    int64_t *fill = calloc(n, sizeof(int64_t));
+    if (!fill) rc = ORC_NOMEM;
+    else {
+      for (int64_t v = 0; v < n; ++v) if (pv[v] >= 0) child[nchild[pv[v]] + fill[pv[v]]++] = v;
+      free(fill);
+      /* preorder from s; children come after their parent, so a reverse walk
+       * visits every child before its parent */
+      int64_t top = 0, len = 0;
+      stack[top++] = src;
+      while (top > 0) {
+        int64_t v = stack[--top];
+        order[len++] = v;
+        for (int64_t k = nchild[v]; k < nchild[v + 1]; ++k) stack[top++] = child[k];
+      }
+      if (len != reached) rc = ORC_BADARG; /* parent pointers with a cycle */
+      for (int64_t v = 0; v < n; ++v) g[v] = (isinf(d[v]) || v == src) ? 0.0 : grad_dist[v];
+      for (int64_t k = len - 1; k >= 0 && rc == ORC_OK; --k) {
+        int64_t v = order[k];
+        if (v == src) continue;
+        grad_w[pe[v]] += g[v];
+        g[pv[v]] += g[v];
+      }
+    }
+  }
+  if (parent_edge) for (int64_t v = 0; v < n; ++v) parent_edge[v] = pe[v];
+  free(d); free(g); free(pe); free(pv); free(nchild); free(child); free(stack); free(order);
+  return rc;
 }

@@ -383,3 +383,124 @@ def pin_bucket_of(o) -> list[str]:
 ALL_PINS = [pin_golden_worked_example, pin_golden_fp32, pin_tiny_random_agree, pin_scipy, pin_closed_forms,
             pin_bfs_mode, pin_schedule_invariants, pin_special_deltas, pin_certificate, pin_overflow,
             pin_bucket_of]
+
+
+# ---------------------------------------------------------------- adjoint (dL/dw) pins
+
+def _tree_parents_bruteforce(g, s, d):
+    """Parent of every reached v != s: the tight in-edge with the smallest edge index (numpy)."""
+    src = g.edge_src()
+    fin = finite(d)
+    wd = g.w.astype(np.float64)
+    dd = d.astype(np.float64)
+    if g.w.dtype == np.float32:
+        cand = (d[src].astype(np.float32) + g.w).astype(np.float64)
+    else:
+        cand = dd[src] + wd
+    tight = fin[src] & (cand == dd[g.col]) & (g.col != s)
+    parent = np.full(g.n, -1, dtype=np.int64)
+    for e in np.nonzero(tight)[0][::-1]:  # descending, so the smallest index is written last
+        parent[g.col[e]] = e
+    return parent, src
+
+
+def pin_gradient_closed_forms(o) -> list[str]:
+    fails = []
+    r = G.rng_for(8100, G.S_WEIGHT)
+    # path 0 -> 1 -> ... -> n-1: d(t) = sum of the first t weights, dL/dw_j = sum_{t > j} c_t
+    n = 60
+    w = r.uniform(1.0, 2.0, size=n - 1)
+    c = r.standard_normal(n)
+    g = G.path_graph(n, w)
+    d, _ = o.dijkstra(g, 0)
+    gw, _ = o.sp_gradient(g, 0, d, c)
+    want = np.cumsum(c[::-1])[::-1][1:]
+    if not np.allclose(gw, want, rtol=1e-12, atol=1e-12):
+        fails.append("adjoint on a path: not the suffix sums of the coefficients")
+    # star: dL/dw_(0,t) = c_t
+    g = G.star_graph(25, r.uniform(1.0, 2.0, size=24))
+    c = r.standard_normal(25)
+    d, _ = o.dijkstra(g, 0)
+    gw, _ = o.sp_gradient(g, 0, d, c)
+    if not np.allclose(gw, c[1:], rtol=0, atol=0):
+        fails.append("adjoint on a star")
+    # unit coefficients: every tree edge receives the size of the subtree below it (integers),
+    # checked by walking each vertex's tree path in Python; non-tree edges receive 0
+    for dt in (np.uint32, np.float32, np.float64):
+        g = G.er_graph(150, 900, cfg=81, weights="u32", wlo=1, whi=9)
+        if dt != np.uint32:
+            g = G.Graph(n=g.n, row_ptr=g.row_ptr, col=g.col, w=g.w.astype(dt))
+        s = int(G.sources_with_outedges(g, 1, cfg=81)[0])
+        d, _ = o.dijkstra(g, s)
+        ones = finite(d).astype(np.float64)
+        gw, pe = o.sp_gradient(g, s, d, ones)
+        parent, src = _tree_parents_bruteforce(g, s, d)
+        if not np.array_equal(pe, parent):
+            fails.append(f"adjoint parents ({dt.__name__}): not the smallest tight in-edge")
+            continue
+        want = np.zeros(g.m)
+        for t in np.nonzero(finite(d))[0]:
+            v = t
+            while v != s:
+                want[parent[v]] += 1.0
+                v = src[parent[v]]
+        if not np.array_equal(gw, want):
+            fails.append(f"adjoint subtree sizes ({dt.__name__})")
+    return fails
+
+
+def pin_gradient_finite_differences(o) -> list[str]:
+    """Central differences (h = 1e-3) of L(w) = sum_s sum_t c_t d_s(t) with float64 weights on
+    a 200-vertex instance (continuous weights: shortest paths unique almost surely). Edges whose
+    response is not linear over [w - h, w + h] (a path change within h) are skipped."""
+    fails = []
+    g = G.er_graph(200, 1600, cfg=82, weights="f64", wlo=1.0, whi=2.0)
+    srcs = [int(x) for x in G.sources_with_outedges(g, 2, cfg=82)]
+    c = G.rng_for(82, G.S_COEF).standard_normal(g.n)
+
+    def loss(wv):
+        gg = G.Graph(n=g.n, row_ptr=g.row_ptr, col=g.col, w=wv)
+        total = 0.0
+        for s in srcs:
+            d, _ = o.dijkstra(gg, s)
+            fin = np.isfinite(d)
+            total += float(np.dot(c[fin], d[fin]))
+        return total
+
+    grad = np.zeros(g.m)
+    for s in srcs:
+        d, _ = o.dijkstra(g, s)
+        o.sp_gradient(g, s, d, c, grad)
+    h = 1e-3
+    l0 = loss(g.w)
+    compared = 0
+    for e in range(g.m):
+        wp = g.w.copy(); wp[e] += h
+        wm = g.w.copy(); wm[e] -= h
+        lp, lm = loss(wp), loss(wm)
+        if abs(lp - 2 * l0 + lm) > 1e-9 * max(1.0, abs(l0)):
+            continue
+        compared += 1
+        fd = (lp - lm) / (2 * h)
+        if abs(fd - grad[e]) > 1e-6 * max(1.0, abs(grad[e])):
+            fails.append(f"edge {e}: finite difference {fd} vs adjoint {grad[e]}")
+            if len(fails) > 5:
+                break
+    if compared < 0.9 * g.m:
+        fails.append(f"only {compared} of {g.m} edges had a linear response")
+    return fails
+
+
+def pin_gradient_ties(o) -> list[str]:
+    """Two equal shortest paths to vertex 3: the gradient follows the in-edge of smallest index."""
+    g = G.csr_from_edges(4, np.array([0, 0, 1, 2]), np.array([1, 2, 3, 3]),
+                         np.array([1.0, 1.0, 1.0, 1.0]), dedup=False)
+    d, _ = o.dijkstra(g, 0)
+    gw, pe = o.sp_gradient(g, 0, d, np.array([0.0, 0.0, 0.0, 5.0]))
+    # edges in CSR order: 0->1 (0), 0->2 (1), 1->3 (2), 2->3 (3); the tie at 3 goes to edge 2
+    if pe[3] != 2 or not np.array_equal(gw, [5.0, 0.0, 5.0, 0.0]):
+        return [f"tie-break: parent {pe[3]}, grad {gw}"]
+    return []
+
+
+ALL_PINS += [pin_gradient_closed_forms, pin_gradient_finite_differences, pin_gradient_ties]
