@@ -129,6 +129,39 @@ sssp_status sssp_create(const sssp_graph *g, double delta, void *stream, sssp_ha
  */
 sssp_status sssp_solve(sssp_handle *h, const int32_t *sources, int32_t k, void *dist, void *stream);
 
+/*
+ * sssp_backward -- gradient of a loss of the distances with respect to the
+ *   edge weights (fp32 handles). For each source s = sources[r] with distances
+ *   dist[r] (as returned by sssp_solve on this handle with its current weights)
+ *   and dL/dd = grad_dist[r], d_s(v) is the sum of the weights along v's path in
+ *   the shortest-path tree (Sec. III: the minimum-weight path; the relaxations
+ *   of Sec. III-C define which in-edge is tight), so
+ *     dL/dw_e = sum over sources of the sum of grad_dist over the tree's
+ *               subtree below e        (0 for edges in no tree).
+ *   The tree is recomputed from dist: the parent of v is its tight in-edge
+ *   (dist(u) (+) w == dist(v)) with the smallest caller edge index, which makes
+ *   the result well defined under ties. grad_dist at unreachable vertices and
+ *   at the source is ignored. Sums run in fp64; grad_w is written in fp32.
+ *   sources: HOST int32 [k].  dist: DEVICE [k][n] float.  grad_dist: DEVICE
+ *   [k][n] float.  grad_w: DEVICE [m] float, caller edge order, overwritten.
+ *   The call synchronises the stream.
+ *   Errors: INVALID_ARGUMENT (pointers, sources, or dist not a shortest-path
+ *   vector of this graph), UNSUPPORTED (uint32 handles), NO_FORWARD (no
+ *   successful sssp_solve since the handle's weights were set), DEVICE.
+ */
+sssp_status sssp_backward(sssp_handle *h, const int32_t *sources, int32_t k, const void *dist,
+                          const float *grad_dist, float *grad_w, void *stream);
+
+/*
+ * sssp_set_weights -- replace the weights of the handle's graph (same CSR
+ *   structure, caller edge order) and redo the light/heavy split for the
+ *   handle's delta (Sec. IV-A). weights: DEVICE [m] of the handle's weight
+ *   type, validated as in sssp_create. Synchronises the stream.
+ *   Errors: INVALID_WEIGHT, UNSUPPORTED (fp32 total weight / delta >= 2^29),
+ *   OUT_OF_MEMORY, DEVICE, INVALID_ARGUMENT.
+ */
+sssp_status sssp_set_weights(sssp_handle *h, const void *weights, void *stream);
+
 /* Counters of the last successful sssp_solve (host struct, caller-owned). */
 sssp_status sssp_last_stats(const sssp_handle *h, sssp_stats *out);
 

@@ -33,6 +33,15 @@ struct sssp_handle {
   bool stamps_dirty = false;
   unsigned long long* trace = nullptr;  // caller-owned device buffer (optional)
   uint32_t trace_cap = 0;
+  uint32_t* inv = nullptr;  // [n] solver id -> caller id
+  // adjoint working set, allocated on first use
+  uint32_t* adj_d = nullptr;
+  unsigned long long* adj_parent = nullptr;
+  uint32_t* adj_cnt = nullptr;
+  double* adj_g = nullptr;
+  double* adj_grad64 = nullptr;
+  unsigned long long* aux = nullptr;  // [2] small device scratch for status reads
+  int adj_grid = 0;
 };
 
 namespace {
@@ -61,6 +70,9 @@ hipError_t dalloc(T** p, size_t count) {
 void free_handle(sssp_handle* h) {
   if (!h) return;
   sssp::Params& p = h->p;
+  void* extra[] = {h->inv, h->adj_d, h->adj_parent, h->adj_cnt, h->adj_g, h->adj_grad64, h->aux};
+  for (void* q : extra)
+    if (q) (void)hipFree(q);
   void* dev[] = {h->off, h->split, const_cast<uint4*>(p.rows), const_cast<uint64_t*>(p.edges),
                  p.qstamp, p.sstamp, p.bstamp, p.fstamp, p.ovf_at, p.front[0], p.front[1], p.slist, p.bins,
                  p.far[0], p.far[1], p.hub, p.ctl, h->perm, h->src_dev, const_cast<uint32_t*>(p.vid), p.tbuf[0],
@@ -196,10 +208,47 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   hipError_t be = sssp::launch_relabel_and_split(g->row_ptr, g->col_idx, g->weights, g->wtype, n, m, h->delta_u,
                                                  h->delta_f, build, vid, off, split, edges, h->perm, stream);
   if (be == hipSuccess) be = sssp::launch_pack_rows(off, split, n, rows, stream);
+  if (be == hipSuccess) be = dalloc(&h->inv, un);
+  if (be == hipSuccess) be = sssp::launch_inverse(vid, n, h->inv, stream);
+  if (be == hipSuccess) be = dalloc(&h->aux, 2);
   if (be == hipSuccess) be = hipStreamSynchronize(stream);
   (void)hipFree(build);
   SSSP_TRY(be);
   return configure_grid(h);
+}
+
+// Copy host sources into the handle's device buffer (checked against n).
+sssp_status stage_sources(sssp_handle* h, const int32_t* sources, int32_t k, hipStream_t s) {
+  for (int32_t r = 0; r < k; ++r)
+    if (sources[r] < 0 || sources[r] >= h->n) return SSSP_ERR_INVALID_ARGUMENT;
+  if (k > h->src_cap) {
+    if (h->src_dev) (void)hipFree(h->src_dev);
+    if (h->src_host) (void)hipHostFree(h->src_host);
+    h->src_dev = nullptr;
+    h->src_host = nullptr;
+    h->src_cap = 0;
+    SSSP_TRY(dalloc(&h->src_dev, static_cast<size_t>(k)));
+    SSSP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->src_host), sizeof(int32_t) * k, hipHostMallocDefault));
+    h->src_cap = k;
+  }
+  SSSP_TRY(hipStreamSynchronize(s));  // the pinned staging buffer may still feed an earlier copy
+  std::memcpy(h->src_host, sources, sizeof(int32_t) * k);
+  SSSP_TRY(hipMemcpyAsync(h->src_dev, h->src_host, sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
+  return SSSP_OK;
+}
+
+// fp32 bucket-range and ring-size rule shared by create and set_weights
+uint32_t ring_for(const sssp_handle* h, uint32_t wmax_bits) {
+  double span;
+  if (h->wtype == SSSP_WEIGHT_U32) {
+    span = static_cast<double>(wmax_bits) / static_cast<double>(h->delta_u);
+  } else {
+    float wmax;
+    std::memcpy(&wmax, &wmax_bits, sizeof(float));
+    span = static_cast<double>(wmax) / static_cast<double>(h->delta_f);
+  }
+  uint32_t ring = pow2_at_least(static_cast<uint32_t>(std::min(span + 2.0, 64.0)));
+  return ring < 2 ? 2 : ring;
 }
 
 }  // namespace
@@ -249,22 +298,10 @@ sssp_status sssp_create(const sssp_graph* g, double delta, void* stream, sssp_ha
 
 sssp_status sssp_solve(sssp_handle* h, const int32_t* sources, int32_t k, void* dist, void* stream) {
   if (!h || !sources || k < 1 || !dist) return SSSP_ERR_INVALID_ARGUMENT;
-  for (int32_t r = 0; r < k; ++r)
-    if (sources[r] < 0 || sources[r] >= h->n) return SSSP_ERR_INVALID_ARGUMENT;
   hipStream_t s = static_cast<hipStream_t>(stream);
   SSSP_TRY(hipSetDevice(h->device));
-  if (k > h->src_cap) {
-    if (h->src_dev) (void)hipFree(h->src_dev);
-    if (h->src_host) (void)hipHostFree(h->src_host);
-    h->src_dev = nullptr;
-    h->src_host = nullptr;
-    h->src_cap = 0;
-    SSSP_TRY(dalloc(&h->src_dev, static_cast<size_t>(k)));
-    SSSP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->src_host), sizeof(int32_t) * k, hipHostMallocDefault));
-    h->src_cap = k;
-  }
-  std::memcpy(h->src_host, sources, sizeof(int32_t) * k);
-  SSSP_TRY(hipMemcpyAsync(h->src_dev, h->src_host, sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
+  const sssp_status st = stage_sources(h, sources, k, s);
+  if (st != SSSP_OK) return st;
   int reset_epochs = 0;
   if (h->stamps_dirty) {
     const size_t un = static_cast<size_t>(h->n);
@@ -294,6 +331,120 @@ sssp_status sssp_solve(sssp_handle* h, const int32_t* sources, int32_t k, void* 
   h->last.trace_records = c.trace_len;
   if (c.ovf_real) return SSSP_ERR_OVERFLOW;
   h->solved = true;
+  return SSSP_OK;
+}
+
+sssp_status sssp_backward(sssp_handle* h, const int32_t* sources, int32_t k, const void* dist,
+                          const float* grad_dist, float* grad_w, void* stream) {
+  if (!h || !sources || k < 1 || !dist || !grad_dist || !grad_w) return SSSP_ERR_INVALID_ARGUMENT;
+  if (h->wtype != SSSP_WEIGHT_F32) return SSSP_ERR_UNSUPPORTED;
+  if (!h->solved) return SSSP_ERR_NO_FORWARD;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SSSP_TRY(hipSetDevice(h->device));
+  const size_t un = static_cast<size_t>(h->n), um = static_cast<size_t>(h->m);
+  if (!h->adj_d) {
+    SSSP_TRY(dalloc(&h->adj_d, un));
+    SSSP_TRY(dalloc(&h->adj_parent, un));
+    SSSP_TRY(dalloc(&h->adj_cnt, un));
+    SSSP_TRY(dalloc(&h->adj_g, un));
+    SSSP_TRY(dalloc(&h->adj_grad64, um));
+    int occ = 0;
+    SSSP_TRY(sssp::adjoint_occupancy(&occ));
+    if (occ < 1) return SSSP_ERR_UNSUPPORTED;
+    h->adj_grid = h->cus;
+  }
+  const sssp_status st = stage_sources(h, sources, k, s);
+  if (st != SSSP_OK) return st;
+  sssp::AdjParams a{};
+  a.n = static_cast<uint32_t>(h->n);
+  a.m = static_cast<uint64_t>(h->m);
+  a.vid = h->p.vid;
+  a.inv = h->inv;
+  a.rows = h->p.rows;
+  a.edges = h->p.edges;
+  a.perm = h->perm;
+  a.d = h->adj_d;
+  a.parent = h->adj_parent;
+  a.cnt = h->adj_cnt;
+  a.g = h->adj_g;
+  a.front[0] = h->p.front[0];
+  a.front[1] = h->p.front[1];
+  a.grad64 = h->adj_grad64;
+  a.ctl = h->p.ctl;
+  SSSP_TRY(hipMemsetAsync(h->aux, 0, 2 * sizeof(unsigned long long), s));
+  SSSP_TRY(sssp::launch_count_reached(static_cast<const uint32_t*>(dist), a.n, k, h->wtype, h->aux, s));
+  SSSP_TRY(sssp::launch_ctl_reset(h->p.ctl, 0, nullptr, 0, s));
+  SSSP_TRY(sssp::launch_adjoint(a, h->src_dev, k, static_cast<const uint32_t*>(dist), grad_dist, grad_w, h->adj_grid,
+                                s));
+  unsigned long long reached = 0;
+  SSSP_TRY(hipMemcpyAsync(h->ctl_host, h->p.ctl, sizeof(sssp::Ctl), hipMemcpyDeviceToHost, s));
+  SSSP_TRY(hipMemcpyAsync(&reached, h->aux, sizeof(reached), hipMemcpyDeviceToHost, s));
+  SSSP_TRY(hipStreamSynchronize(s));
+  const sssp::Ctl& c = *h->ctl_host;
+  if (c.abort) return SSSP_ERR_DEVICE;
+  // a reached vertex without a tight in-edge, or parents that never lead to the source
+  if (c.ovf_real || c.adj_released != reached) return SSSP_ERR_INVALID_ARGUMENT;
+  return SSSP_OK;
+}
+
+sssp_status sssp_set_weights(sssp_handle* h, const void* weights, void* stream) {
+  if (!h || (h->m > 0 && !weights)) return SSSP_ERR_INVALID_ARGUMENT;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SSSP_TRY(hipSetDevice(h->device));
+  if (h->m == 0) return SSSP_OK;
+  uint32_t* scratch = nullptr;  // [0] status, [1] max weight bits, [2..3] fp64 weight total
+  SSSP_TRY(dalloc(&scratch, 4));
+  hipError_t e = hipMemsetAsync(scratch, 0, 4 * sizeof(uint32_t), s);
+  if (e == hipSuccess)
+    e = sssp::launch_validate_weights(weights, h->wtype, h->m, scratch, scratch + 1,
+                                      reinterpret_cast<double*>(scratch + 2), s);
+  uint32_t res[4] = {0, 0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(res, scratch, sizeof(res), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(scratch);
+  SSSP_TRY(e);
+  if (res[0] & sssp::kBadWeight) return SSSP_ERR_INVALID_WEIGHT;
+  if (h->wtype == SSSP_WEIGHT_F32) {
+    double wsum;
+    std::memcpy(&wsum, res + 2, sizeof(double));
+    if (wsum * 2.0 / static_cast<double>(h->delta_f) >= static_cast<double>(1u << 29)) return SSSP_ERR_UNSUPPORTED;
+  }
+  sssp::Params& p = h->p;
+  const size_t un = static_cast<size_t>(h->n), um = static_cast<size_t>(h->m);
+  const uint32_t ring = ring_for(h, res[1]);
+  if (ring > p.ring) {  // a larger weight spread needs more near buckets
+    uint32_t* bins = nullptr;
+    SSSP_TRY(dalloc(&bins, un * ring));
+    (void)hipFree(p.bins);
+    p.bins = bins;
+    p.ring = ring;
+    p.ring_mask = ring - 1;
+  }
+  uint4* rows = nullptr;
+  uint64_t* edges = nullptr;
+  uint32_t* perm = nullptr;
+  if (dalloc(&rows, un) != hipSuccess || dalloc(&edges, um) != hipSuccess || dalloc(&perm, um) != hipSuccess) {
+    if (rows) (void)hipFree(rows);
+    if (edges) (void)hipFree(edges);
+    return SSSP_ERR_OUT_OF_MEMORY;
+  }
+  e = sssp::launch_resplit(static_cast<uint32_t>(h->n), p.rows, p.edges, h->perm, weights, h->wtype, h->delta_u,
+                           h->delta_f, rows, edges, perm, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(rows);
+    (void)hipFree(edges);
+    (void)hipFree(perm);
+    return from_hip(e);
+  }
+  (void)hipFree(const_cast<uint4*>(p.rows));
+  (void)hipFree(const_cast<uint64_t*>(p.edges));
+  (void)hipFree(h->perm);
+  p.rows = rows;
+  p.edges = edges;
+  h->perm = perm;
+  h->wmax_bits = res[1];
+  h->solved = false;  // distances of earlier solves used the old weights
   return SSSP_OK;
 }
 

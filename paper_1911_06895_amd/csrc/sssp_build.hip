@@ -91,6 +91,40 @@ __global__ __launch_bounds__(kB) void validate_kernel(const int64_t* rp, const i
   }
 }
 
+// weights only (used when a handle's weights are replaced)
+__global__ __launch_bounds__(kB) void validate_weights_kernel(const uint32_t* wbits, int wtype, int64_t m,
+                                                              uint32_t* status, uint32_t* wmax_bits, double* wsum) {
+  uint32_t bad = 0, wmax = 0;
+  double sum = 0.0;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kB;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x; e < m; e += stride) {
+    const uint32_t wb = wbits[e];
+    if (wtype == 0) {
+      if (wb == 0) bad |= kBadWeight;
+    } else {
+      if ((wb & 0x80000000u) || wb == 0 || (wb & 0x7F800000u) == 0x7F800000u) bad |= kBadWeight;
+      else sum += static_cast<double>(__uint_as_float(wb));
+    }
+    wmax = max(wmax, wb);
+  }
+  for (int d = 32; d > 0; d >>= 1) {
+    bad |= __shfl_down(bad, d);
+    wmax = max(wmax, __shfl_down(wmax, d));
+    sum += __shfl_down(sum, d);
+  }
+  if (lane_id() == 0) {
+    if (bad) atomicOr(status, bad);
+    if (wmax) atomicMax(wmax_bits, wmax);
+    if (sum != 0.0) atomicAdd(wsum, sum);
+  }
+}
+
+__global__ __launch_bounds__(kB) void inverse_kernel(const uint32_t* vid, int64_t n, uint32_t* inv) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kB;
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x; v < n; v += stride)
+    inv[vid[v]] = static_cast<uint32_t>(v);
+}
+
 // in-degree of every vertex (col is validated)
 __global__ __launch_bounds__(kB) void indegree_kernel(const int32_t* col, int64_t m, uint32_t* indeg) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kB;
@@ -294,6 +328,18 @@ hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, const voi
 
 hipError_t launch_pack_rows(const uint32_t* off, const uint32_t* split, int64_t n, uint4* rows, hipStream_t s) {
   hipLaunchKernelGGL(pack_rows_kernel, dim3(grid_for(n, 8192)), dim3(kB), 0, s, off, split, n, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate_weights(const void* w, int wtype, int64_t m, uint32_t* status, uint32_t* wmax_bits,
+                                   double* wsum, hipStream_t s) {
+  hipLaunchKernelGGL(validate_weights_kernel, dim3(grid_for(m, 8192)), dim3(kB), 0, s,
+                     static_cast<const uint32_t*>(w), wtype, m, status, wmax_bits, wsum);
+  return hipGetLastError();
+}
+
+hipError_t launch_inverse(const uint32_t* vid, int64_t n, uint32_t* inv, hipStream_t s) {
+  hipLaunchKernelGGL(inverse_kernel, dim3(grid_for(n, 8192)), dim3(kB), 0, s, vid, n, inv);
   return hipGetLastError();
 }
 

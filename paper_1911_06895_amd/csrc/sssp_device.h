@@ -1,0 +1,185 @@
+// Device helpers shared by the solver and the adjoint: device-scope loads and
+// stores, wave-level utilities, the weight arithmetic and the grid barrier.
+#pragma once
+
+#include "sssp_internal.h"
+
+namespace sssp {
+namespace {
+
+// ------------------------------------------------------------------ helpers
+
+template <typename T>
+__device__ inline T ld_agent(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ inline void st_agent(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// number of set bits of `mask` in lanes below this one
+__device__ inline uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+__device__ inline uint32_t lane() { return __lane_id(); }
+
+__device__ inline int first_lane(uint64_t mask) { return __ffsll(static_cast<unsigned long long>(mask)) - 1; }
+
+// Append `v` to list[*count] for every lane with `pred`; one atomic per wave.
+__device__ inline void push_wave(uint32_t* list, uint32_t* count, bool pred, uint32_t v) {
+  const uint64_t mask = __ballot(pred);
+  if (mask == 0) return;
+  const int leader = first_lane(mask);
+  uint32_t base = 0;
+  if (static_cast<int>(lane()) == leader) base = atomicAdd(count, static_cast<uint32_t>(__popcll(mask)));
+  base = __shfl(base, leader);
+  if (pred) st_agent(&list[base + lanes_below(mask)], v);
+}
+
+// Inclusive prefix sum across a wave64.
+__device__ inline uint32_t wave_scan(uint32_t x) {
+  const uint32_t l = lane();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d);
+    if (l >= static_cast<uint32_t>(d)) x += y;
+  }
+  return x;
+}
+
+// Exclusive prefix sum across the workgroup; returns the total in *total.
+__device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t* total, uint32_t* s_wsum) {
+  const uint32_t inc = wave_scan(x);
+  const uint32_t w = threadIdx.x >> 6;
+  if (lane() == 63) s_wsum[w] = inc;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kWG / 64; ++k) {
+    const uint32_t s = s_wsum[k];
+    before += (k < w) ? s : 0u;
+    all += s;
+  }
+  *total = all;
+  __syncthreads();  // s_wsum is reused by the next scan
+  return before + inc - x;
+}
+
+// ------------------------------------------------------------------ weights
+
+// x (+) w in the weight type, and the bucket index floor(x / delta).
+struct WeightU32 {
+  static constexpr uint32_t kInf = kInfU32;
+  __device__ static bool add(uint32_t t, uint32_t w, uint32_t* out) {
+    const uint64_t s = static_cast<uint64_t>(t) + static_cast<uint64_t>(w);
+    *out = static_cast<uint32_t>(s);
+    return s <= 0xFFFFFFFEull;  // 2^32-1 is reserved for "unreachable"
+  }
+  __device__ static uint32_t bucket(uint32_t x, const Params& p) { return x / p.delta_u; }
+};
+
+struct WeightF32 {
+  static constexpr uint32_t kInf = kInfF32;
+  __device__ static bool add(uint32_t t, uint32_t w, uint32_t* out) {
+    const float s = __fadd_rn(__uint_as_float(t), __uint_as_float(w));
+    *out = __float_as_uint(s);
+    return *out < kInfF32;  // non-negative operands: the sum is finite or +inf
+  }
+  // floor(x / delta) exactly: the estimate from one rounded product is off by
+  // at most one, and j * delta is exact in double for j < 2^29.
+  __device__ static uint32_t bucket(uint32_t x, const Params& p) {
+    const double d = static_cast<double>(__uint_as_float(x));
+    double j = floor(d * p.inv_delta_d);
+    if (j * p.delta_d > d) j -= 1.0;
+    else if ((j + 1.0) * p.delta_d <= d) j += 1.0;
+    return static_cast<uint32_t>(j);
+  }
+};
+
+// ------------------------------------------------------------------ barrier
+
+constexpr unsigned long long kWaitLimitTicks = 3000000000ull;  // 30 s of the 100 MHz wall clock
+
+// Every wave's device-scope stores and atomics complete (are acknowledged by
+// the device-coherent level) before its workgroup arrives: s_waitcnt with all
+// counters zero.
+__device__ inline void drain_stores() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
+__device__ inline void record_trace(Ctl* c, uint32_t flags) {
+  if (!c->trace) return;
+  const uint32_t idx = atomicAdd(&c->trace_len, 1u);
+  if (idx < c->trace_cap) {
+    const unsigned long long what = static_cast<unsigned long long>(ld_agent(&c->in_count)) << 32 |
+                                    static_cast<unsigned long long>(ld_agent(&c->bucket) & 0xFFFFFFu) << 8 |
+                                    (ld_agent(&c->action) | flags);
+    st_agent(&c->trace[4 * idx], static_cast<unsigned long long>(wall_clock64()));
+    st_agent(&c->trace[4 * idx + 1], what);
+    st_agent(&c->trace[4 * idx + 2], __hip_atomic_exchange(&c->tr_edges, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    st_agent(&c->trace[4 * idx + 3], __hip_atomic_exchange(&c->tr_impr, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  }
+}
+
+// Device-wide barrier over all (co-resident) workgroups. Arrivals are counted
+// first per group of workgroups (blockIdx % 8), then once per group, which
+// keeps same-address atomics short. The last workgroup to arrive runs `leader`
+// (all its threads) before releasing the others. Returns false when the
+// schedule was aborted (a wait ran past kWaitLimitTicks).
+template <class F>
+__device__ bool grid_sync(Ctl* c, F&& leader) {
+  __shared__ uint32_t s_is_leader;
+  __shared__ uint32_t s_ok;
+  drain_stores();
+  __syncthreads();
+  uint32_t gen = 0;
+  if (threadIdx.x == 0) {
+    const uint32_t groups = gridDim.x < kBarGroups ? gridDim.x : kBarGroups;
+    const uint32_t g = blockIdx.x % groups;
+    const uint32_t gsize = (gridDim.x - g + groups - 1) / groups;
+    gen = ld_agent(&c->bar_gen);
+    bool last = false;
+    const uint32_t prev = atomicAdd(&c->bar_sub[g][0], 1u);
+    if (prev == gsize - 1) {
+      st_agent(&c->bar_sub[g][0], 0u);  // the whole group has arrived; nobody re-arrives before the release
+      last = atomicAdd(&c->bar_arrive, 1u) == groups - 1;
+      if (last) st_agent(&c->bar_arrive, 0u);
+    }
+    s_is_leader = last ? 1u : 0u;
+    uint32_t ok = 1;
+    if (!last) {
+      const unsigned long long t0 = wall_clock64();
+      while (ld_agent(&c->bar_gen) == gen) {
+        if (ld_agent(&c->abort) != 0u || wall_clock64() - t0 > kWaitLimitTicks) {
+          st_agent(&c->abort, 1u);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  if (s_is_leader) {
+    leader();
+    drain_stores();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      atomicAdd(&c->barriers, 1ull);
+      record_trace(c, 0u);
+      drain_stores();
+      st_agent(&c->bar_gen, gen + 1u);
+    }
+  }
+  const bool ok = s_ok != 0u;
+  __syncthreads();
+  return ok;
+}
+
+}  // namespace
+}  // namespace sssp

@@ -82,6 +82,7 @@ struct Ctl {
   // statistics (summed over sources)
   unsigned long long sources, buckets, light_phases, heavy_phases, far_phases;
   unsigned long long light_edges, heavy_edges, improvements, barriers;
+  unsigned long long adj_released;  // adjoint: vertices released (equals the reached count)
 };
 
 struct Params {
@@ -111,7 +112,36 @@ struct Params {
   Ctl* ctl;
 };
 
-// launchers (sssp_kernels.hip)
+// Adjoint working set (solver ids unless noted).
+struct AdjParams {
+  uint32_t n;
+  uint64_t m;
+  const uint32_t* vid;        // [n] caller -> solver id
+  const uint32_t* inv;        // [n] solver -> caller id
+  const uint4* rows;
+  const uint64_t* edges;
+  const uint32_t* perm;       // packed position -> caller edge index
+  uint32_t* d;                // [n] distances
+  unsigned long long* parent; // [n] (caller edge index << 32 | parent solver id), all ones = none
+  uint32_t* cnt;              // [n] children still to report
+  double* g;                  // [n] accumulated coefficients
+  uint32_t* front[2];         // [n] level lists
+  double* grad64;             // [m] dL/dw in caller edge order
+  Ctl* ctl;
+};
+
+// launchers (sssp_kernels.hip, sssp_adjoint.hip, sssp_build.hip)
+hipError_t adjoint_occupancy(int* blocks_per_cu);
+hipError_t launch_adjoint(const AdjParams& a, const int32_t* sources, int k, const uint32_t* dist,
+                          const float* grad_dist, float* grad_w, int grid, hipStream_t s);
+hipError_t launch_count_reached(const uint32_t* dist, uint32_t n, int k, int wtype, unsigned long long* out,
+                                hipStream_t s);
+hipError_t launch_resplit(uint32_t n, const uint4* rows_in, const uint64_t* edges_in, const uint32_t* perm_in,
+                          const void* w, int wtype, uint32_t delta_u, float delta_f, uint4* rows_out,
+                          uint64_t* edges_out, uint32_t* perm_out, hipStream_t s);
+hipError_t launch_inverse(const uint32_t* vid, int64_t n, uint32_t* inv, hipStream_t s);
+hipError_t launch_validate_weights(const void* w, int wtype, int64_t m, uint32_t* status, uint32_t* wmax_bits,
+                                   double* wsum, hipStream_t s);
 hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, const void* w, int wtype, int64_t n,
                            int64_t m, uint32_t* status, uint32_t* wmax_bits, double* wsum, hipStream_t s);
 size_t build_scratch_words(int64_t n);

@@ -26,8 +26,8 @@ SSSP_ERR_UNSUPPORTED = 7
 SSSP_WEIGHT_U32 = 0
 SSSP_WEIGHT_F32 = 1
 
-EXPORTS = ("sssp_create", "sssp_solve", "sssp_last_stats", "sssp_set_tuning", "sssp_set_trace", "sssp_graph_info",
-           "sssp_destroy", "sssp_status_string")
+EXPORTS = ("sssp_create", "sssp_solve", "sssp_backward", "sssp_set_weights", "sssp_last_stats", "sssp_set_tuning",
+           "sssp_set_trace", "sssp_graph_info", "sssp_destroy", "sssp_status_string")
 
 
 class SsspGraph(ctypes.Structure):
@@ -68,6 +68,10 @@ def load_library(path: str = LIBRARY) -> ctypes.CDLL:
     lib.sssp_create.restype = ctypes.c_int
     lib.sssp_solve.argtypes = [P, P, ctypes.c_int32, P, P]
     lib.sssp_solve.restype = ctypes.c_int
+    lib.sssp_backward.argtypes = [P, P, ctypes.c_int32, P, P, P, P]
+    lib.sssp_backward.restype = ctypes.c_int
+    lib.sssp_set_weights.argtypes = [P, P, P]
+    lib.sssp_set_weights.restype = ctypes.c_int
     lib.sssp_last_stats.argtypes = [P, ctypes.POINTER(SsspStats)]
     lib.sssp_last_stats.restype = ctypes.c_int
     lib.sssp_set_tuning.argtypes = [P, ctypes.POINTER(SsspTuning)]
@@ -138,6 +142,25 @@ def sssp_solve(handle, sources, dist, stream=None) -> None:
         raise ValueError("dist must be a contiguous GPU tensor")
     _check(load_library().sssp_solve(handle, src.ctypes.data_as(ctypes.c_void_p), int(src.size),
                                      ctypes.c_void_p(dist.data_ptr()), _stream(stream)), "sssp_solve")
+
+
+def sssp_backward(handle, sources, dist, grad_dist, grad_w, stream=None) -> None:
+    """dL/dw into grad_w (GPU float32 [m], caller edge order) for dL/ddist = grad_dist ([k, n])."""
+    src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32).reshape(-1))
+    for t in (dist, grad_dist, grad_w):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("dist, grad_dist and grad_w must be contiguous GPU tensors")
+    _check(load_library().sssp_backward(handle, src.ctypes.data_as(ctypes.c_void_p), int(src.size),
+                                        ctypes.c_void_p(dist.data_ptr()), ctypes.c_void_p(grad_dist.data_ptr()),
+                                        ctypes.c_void_p(grad_w.data_ptr()), _stream(stream)), "sssp_backward")
+
+
+def sssp_set_weights(handle, weights, stream=None) -> None:
+    """weights: contiguous GPU tensor [m] of the handle's weight type (uint32 as int32 bits, or float32)."""
+    if not weights.is_cuda or not weights.is_contiguous():
+        raise ValueError("weights must be a contiguous GPU tensor")
+    _check(load_library().sssp_set_weights(handle, ctypes.c_void_p(weights.data_ptr() if weights.numel() else 0),
+                                           _stream(stream)), "sssp_set_weights")
 
 
 def sssp_last_stats(handle) -> dict:
@@ -222,6 +245,18 @@ class DeltaStepping:
     def stats(self) -> dict:
         return sssp_last_stats(self.handle)
 
+    def set_weights(self, w) -> None:
+        """New weights for the same structure (numpy or GPU tensor, caller edge order)."""
+        if isinstance(w, np.ndarray):
+            w = self.torch.from_numpy(w.view(np.int32) if w.dtype == np.uint32 else w).to(self.device)
+        sssp_set_weights(self.handle, w.contiguous())
+
+    def backward(self, sources, dist, grad_dist):
+        """dL/dw (float32 [m]) for dL/ddist = grad_dist, dist from solve(sources)."""
+        grad_w = self.torch.empty(self.m, dtype=self.torch.float32, device=self.device)
+        sssp_backward(self.handle, sources, dist.contiguous(), grad_dist.contiguous().float(), grad_w)
+        return grad_w
+
     def set_tuning(self, **kw):
         sssp_set_tuning(self.handle, **kw)
 
@@ -235,3 +270,26 @@ class DeltaStepping:
             self.close()
         except Exception:
             pass
+
+
+def shortest_paths(w, solver: DeltaStepping, sources):
+    """Differentiable distances: dist = SSSP(w) from ``sources`` ([k, n], float32), with
+    dL/dw computed by the shortest-path-tree adjoint (sssp_backward) in the backward pass.
+    ``w`` is a float32 GPU tensor [m] in the caller's edge order; the solver's weights are
+    replaced by it (sssp_set_weights) before the solve."""
+    import torch
+
+    class _Sssp(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, weights):
+            solver.set_weights(weights.detach())
+            dist = solver.solve(sources)
+            ctx.save_for_backward(dist)
+            return dist
+
+        @staticmethod
+        def backward(ctx, grad_dist):
+            (dist,) = ctx.saved_tensors
+            return solver.backward(sources, dist, grad_dist)
+
+    return _Sssp.apply(w)

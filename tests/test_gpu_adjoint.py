@@ -1,0 +1,163 @@
+"""GPU adjoint (sssp_backward), weight replacement (sssp_set_weights) and the autograd
+wrapper, against the CPU oracle's shortest-path-tree gradient (itself pinned by closed
+forms, subtree sizes and central finite differences in tests/pins.py)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_1911_06895_amd import graphs as G  # noqa: E402
+from paper_1911_06895_amd import sssp  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU-only hosts
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def oracle_gradient(g, srcs, dist_rows, grad_rows):
+    acc = np.zeros(g.m, dtype=np.float64)
+    for r, s in enumerate(srcs):
+        oracle.sp_gradient(g, int(s), dist_rows[r], grad_rows[r], acc)
+    return acc
+
+
+def check_close(got, want, what):
+    got = np.asarray(got, dtype=np.float64)
+    want32 = np.asarray(want, dtype=np.float32).astype(np.float64)  # the GPU writes fp32
+    err = np.abs(got - want32) / np.maximum(1.0, np.abs(want32))
+    assert err.max() <= 1e-6, f"{what}: max relative difference {err.max()} at edge {int(err.argmax())}"
+
+
+def run(g, delta, srcs, grad_rows):
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, delta)
+    try:
+        dist = solver.solve(srcs)
+        gd = torch.from_numpy(np.ascontiguousarray(grad_rows, dtype=np.float32)).cuda()
+        gw = solver.backward(srcs, dist, gd).cpu().numpy()
+        return dist.cpu().numpy(), gw
+    finally:
+        solver.close()
+
+
+def test_subtree_sizes_exact():
+    """Coefficient 1 on every reached vertex: each tree edge receives its subtree size, an integer."""
+    g = G.rmat_graph(12, 16, cfg=5, weights="f32_one_two")
+    srcs = G.sources_with_outedges(g, 3, cfg=5)
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, 0.5)
+    try:
+        dist = solver.solve(srcs)
+        ones = torch.isfinite(dist).float()
+        gw = solver.backward(srcs, dist, ones).cpu().numpy()
+        d = dist.cpu().numpy()
+    finally:
+        solver.close()
+    want = oracle_gradient(g, srcs, d, np.isfinite(d).astype(np.float64))
+    assert np.array_equal(gw.astype(np.float64), want)
+    assert np.all(gw == np.round(gw))
+
+
+@pytest.mark.parametrize("delta", [0.5, 2.0, 0.37])
+def test_backward_random_coefficients(delta):
+    g = G.rmat_graph(13, 16, cfg=5, weights="f32_one_two")
+    srcs = G.sources_with_outedges(g, 4, cfg=5)
+    targets, coef = G.targets_and_coefs(g.n, 256, cfg=5)
+    grad_rows = np.zeros((len(srcs), g.n))
+    grad_rows[:, targets] = coef
+    d, gw = run(g, delta, srcs, grad_rows)
+    for r, s in enumerate(srcs):
+        want, _ = oracle.dijkstra(g, int(s))
+        assert np.array_equal(d[r].view(np.uint32), want.view(np.uint32))
+    check_close(gw, oracle_gradient(g, srcs, d, grad_rows), f"delta={delta}")
+
+
+def test_backward_ties_follow_smallest_edge():
+    g = G.csr_from_edges(4, np.array([0, 0, 1, 2]), np.array([1, 2, 3, 3]),
+                         np.array([1.0, 1.0, 1.0, 1.0], dtype=np.float32), dedup=False)
+    d, gw = run(g, 1.0, [0], np.array([[0.0, 0.0, 0.0, 5.0]]))
+    assert gw.tolist() == [5.0, 0.0, 5.0, 0.0]
+
+
+def test_backward_c5_configuration():
+    """R-MAT scale 18, fp32 weights in [1, 2), 16 sources, 1024 targets with N(0,1) coefficients."""
+    g = G.workload("rmat_s18_f32onetwo")
+    srcs = G.sources_with_outedges(g, 16, cfg=5)
+    targets, coef = G.targets_and_coefs(g.n, 1024, cfg=5)
+    grad_rows = np.zeros((len(srcs), g.n))
+    grad_rows[:, targets] = coef
+    d, gw = run(g, 1.0, srcs, grad_rows)
+    check_close(gw, oracle_gradient(g, srcs, d, grad_rows), "C5")
+
+
+def test_autograd_wrapper():
+    g = G.er_graph(3000, 24000, cfg=83, weights="f32_one_two")
+    srcs = [int(x) for x in G.sources_with_outedges(g, 2, cfg=83)]
+    c = torch.from_numpy(G.rng_for(83, G.S_COEF).standard_normal(g.n).astype(np.float32)).cuda()
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, 0.25)
+    try:
+        w = torch.from_numpy(g.w).cuda().requires_grad_(True)
+        dist = sssp.shortest_paths(w, solver, srcs)
+        finite = torch.isfinite(dist)
+        loss = (torch.where(finite, dist, torch.zeros_like(dist)) * c).sum()
+        loss.backward()
+        d = dist.detach().cpu().numpy()
+        grad_rows = np.where(np.isfinite(d), c.cpu().numpy()[None, :], 0.0)
+        check_close(w.grad.cpu().numpy(), oracle_gradient(g, srcs, d, grad_rows), "autograd")
+        # new weights through the same handle (a training step)
+        w2 = (w.detach() * 1.5).contiguous()
+        d2 = sssp.shortest_paths(w2, solver, srcs).cpu().numpy()
+        g2 = G.Graph(n=g.n, row_ptr=g.row_ptr, col=g.col, w=(g.w * np.float32(1.5)).astype(np.float32))
+        for r, s in enumerate(srcs):
+            want, _ = oracle.dijkstra(g2, s)
+            assert np.array_equal(d2[r].view(np.uint32), want.view(np.uint32))
+    finally:
+        solver.close()
+
+
+def test_set_weights_grows_the_ring():
+    """Replacing weights by much larger ones enlarges the ring of near buckets."""
+    r = G.rng_for(84, G.S_WEIGHT)
+    g = G.er_graph(2000, 16000, cfg=84, weights="u32", wlo=1, whi=4)
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, 2)
+    try:
+        w_big = r.integers(1, 200, size=g.m).astype(np.uint32)
+        solver.set_weights(w_big)
+        g2 = G.Graph(n=g.n, row_ptr=g.row_ptr, col=g.col, w=w_big)
+        d = solver.solve_numpy([0, 7])
+        for row, s in zip(d, (0, 7)):
+            want, _ = oracle.dijkstra(g2, s)
+            assert np.array_equal(row, want)
+    finally:
+        solver.close()
+
+
+def test_backward_error_paths():
+    g = G.er_graph(500, 3000, cfg=85, weights="f32_one_two")
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, 0.5)
+    try:
+        dist = torch.zeros((1, g.n), dtype=torch.float32, device="cuda")
+        gd = torch.ones_like(dist)
+        with pytest.raises(sssp.SsspError) as e:
+            solver.backward([0], dist, gd)
+        assert e.value.status == sssp.SSSP_ERR_NO_FORWARD
+        dist = solver.solve([0])
+        bad = dist.clone()
+        fin = torch.nonzero(torch.isfinite(bad[0]) & (bad[0] > 0))[0, 0]
+        bad[0, fin] += 0.25  # no longer a shortest-path vector
+        with pytest.raises(sssp.SsspError) as e:
+            solver.backward([0], bad, gd)
+        assert e.value.status == sssp.SSSP_ERR_INVALID_ARGUMENT
+        solver.backward([0], dist, gd)  # still usable
+    finally:
+        solver.close()
+    gu = G.er_graph(200, 1000, cfg=86, weights="u32", wlo=1, whi=9)
+    solver = sssp.DeltaStepping(gu.row_ptr, gu.col, gu.w, 4)
+    try:
+        dist = solver.solve([0])
+        with pytest.raises(sssp.SsspError) as e:
+            sssp.sssp_backward(solver.handle, [0], dist, torch.ones((1, gu.n), device="cuda"),
+                               torch.empty(gu.m, device="cuda"))
+        assert e.value.status == sssp.SSSP_ERR_UNSUPPORTED
+    finally:
+        solver.close()
