@@ -89,6 +89,9 @@ typedef struct {
   int32_t ring_buckets;      /* buckets held in the near ring, power of two in [2, 64] (default: fit max weight) */
   int32_t inline_edges;      /* phases scanning at most this many edges (and at most 512 list entries)
                                 run on one workgroup without a device-wide barrier (default 4096) */
+  int32_t concurrent_sources; /* sources solved at the same time, each by its own group of workgroups
+                                 (a divisor of the launch's workgroup count, at most 256; default 1).
+                                 Each extra group holds its own working set, about (11 + ring) * 4 * n bytes */
 } sssp_tuning;
 
 typedef struct sssp_handle sssp_handle;
@@ -101,7 +104,8 @@ typedef struct sssp_handle sssp_handle;
  *   one row-partitioned copy: each row holds its light edges, then its heavy ones.
  *   delta: for SSSP_WEIGHT_U32 an integer in [1, 2^32-1]; for SSSP_WEIGHT_F32 the
  *   threshold is (float)delta, which must be finite and > 0, and the total weight
- *   divided by delta must stay below 2^29 (bucket indices stay exact in fp64 products).
+ *   times exp((n-1) * 2^-24) (a bound on any rounded path sum) divided by delta
+ *   must stay below 2^32 - 256 (bucket indices fit 32 bits).
  *   stream: enqueue work here; the call synchronises it before returning.
  *   out: host pointer receiving the new handle (library-owned; free with
  *   sssp_destroy), NULL on error.
@@ -128,6 +132,34 @@ sssp_status sssp_create(const sssp_graph *g, double delta, void *stream, sssp_ha
  *   Errors: INVALID_ARGUMENT, OVERFLOW, DEVICE.
  */
 sssp_status sssp_solve(sssp_handle *h, const int32_t *sources, int32_t k, void *dist, void *stream);
+
+/*
+ * sssp_solve_async -- the same solves as sssp_solve, enqueued only.
+ *   The k independent single-source problems of one call are the columns of a
+ *   distance matrix T (n x k); each step of Fig. 1 then applies to every column
+ *   with its own bucket index, i.e. T_Req = A_L^T (T o T_B) column by column
+ *   (Sec. IV-C with the vector t generalised to a matrix). With
+ *   concurrent_sources = G, G columns are advanced at the same time.
+ *   sources: DEVICE int32 [k], read when the work runs; an entry outside [0, n)
+ *   leaves its row all-unreachable and is reported by sssp_solve_status.
+ *   dist: DEVICE [k][n] as for sssp_solve. k >= 1.
+ *   Nothing is synchronised and no memory is allocated or set by copy/memset
+ *   calls, so the call may be recorded into a HIP graph by stream capture (its
+ *   kernels: a control-block reset and one cooperative launch) and replayed;
+ *   every replay recomputes dist from the sources it finds in memory.
+ *   Errors (before anything is enqueued): INVALID_ARGUMENT, DEVICE.
+ */
+sssp_status sssp_solve_async(sssp_handle *h, const int32_t *sources, int32_t k, void *dist, void *stream);
+
+/*
+ * sssp_solve_status -- wait for the last enqueued solve (sssp_solve_async, or
+ *   the last replay of a graph that recorded it) on `stream` and report its
+ *   outcome; on success its counters become those of sssp_last_stats and
+ *   sssp_backward may use its distances. Synchronises the stream.
+ *   Errors: NO_FORWARD (nothing enqueued on this handle), INVALID_ARGUMENT (a
+ *   source outside [0, n)), OVERFLOW, DEVICE.
+ */
+sssp_status sssp_solve_status(sssp_handle *h, void *stream);
 
 /*
  * sssp_backward -- gradient of a loss of the distances with respect to the
@@ -157,7 +189,7 @@ sssp_status sssp_backward(sssp_handle *h, const int32_t *sources, int32_t k, con
  *   structure, caller edge order) and redo the light/heavy split for the
  *   handle's delta (Sec. IV-A). weights: DEVICE [m] of the handle's weight
  *   type, validated as in sssp_create. Synchronises the stream.
- *   Errors: INVALID_WEIGHT, UNSUPPORTED (fp32 total weight / delta >= 2^29),
+ *   Errors: INVALID_WEIGHT, UNSUPPORTED (fp32 bucket range as for sssp_create),
  *   OUT_OF_MEMORY, DEVICE, INVALID_ARGUMENT.
  */
 sssp_status sssp_set_weights(sssp_handle *h, const void *weights, void *stream);
@@ -165,7 +197,13 @@ sssp_status sssp_set_weights(sssp_handle *h, const void *weights, void *stream);
 /* Counters of the last successful sssp_solve (host struct, caller-owned). */
 sssp_status sssp_last_stats(const sssp_handle *h, sssp_stats *out);
 
-/* Replace the schedule parameters of a handle (host struct; copied). */
+/*
+ * Replace the schedule parameters of a handle (host struct; copied). Allocates
+ * the working sets of new concurrent groups (and synchronises the device).
+ * Errors: INVALID_ARGUMENT (negative fields, a ring size other than the
+ * handle's), UNSUPPORTED (workgroups_per_cu above the device's occupancy, or
+ * concurrent_sources not dividing the workgroup count), OUT_OF_MEMORY.
+ */
 sssp_status sssp_set_tuning(sssp_handle *h, const sssp_tuning *t);
 
 /*

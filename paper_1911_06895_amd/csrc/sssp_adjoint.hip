@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kWG) void adjoint_kernel(AdjParams a, const int32_t
       st_agent(&a.cnt[x], 0u);
       st_agent(&a.g[x], (dx < W::kInf && x != s) ? static_cast<double>(grow[v]) : 0.0);
     }
-    alive = grid_sync(c, [&] {
+    alive = grid_sync(c, gridDim.x, blockIdx.x, [&] {
       if (threadIdx.x == 0) {
         st_agent(&c->fcount[0], 0u);
         st_agent(&c->fcount[1], 0u);
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kWG) void adjoint_kernel(AdjParams a, const int32_t
         }
       }
     }
-    alive = grid_sync(c, [] {});
+    alive = grid_sync(c, gridDim.x, blockIdx.x, [] {});
     if (!alive) break;
     // 2. children per vertex; a reached vertex other than s must have a parent
     for (uint32_t y = tid; y < n; y += nthreads) {
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kWG) void adjoint_kernel(AdjParams a, const int32_t
       if (pe == kNoParent) st_agent(&c->ovf_real, 1u);  // not a shortest-path vector
       else atomicAdd(&a.cnt[static_cast<uint32_t>(pe)], 1u);
     }
-    alive = grid_sync(c, [] {});
+    alive = grid_sync(c, gridDim.x, blockIdx.x, [] {});
     if (!alive) break;
     // 3. first level: reached vertices without children
     {
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kWG) void adjoint_kernel(AdjParams a, const int32_t
         push_wave(a.front[0], &c->fcount[0], leaf, y);
       }
     }
-    alive = grid_sync(c, [&] { adjoint_leader_level<W>(c, 1u); });  // in_count = fcount[0], out = 0
+    alive = grid_sync(c, gridDim.x, blockIdx.x, [&] { adjoint_leader_level<W>(c, 1u); });  // in_count = fcount[0], out = 0
     // 4. levels, leaves towards the source
     while (alive) {
       if (threadIdx.x == 0) {
@@ -126,11 +126,11 @@ __global__ __launch_bounds__(kWG) void adjoint_kernel(AdjParams a, const int32_t
       }
       // every reached vertex is released exactly once unless the parents form a cycle
       if (released) atomicAdd(&c->adj_released, static_cast<unsigned long long>(released));
-      alive = grid_sync(c, [&] { adjoint_leader_level<W>(c, cur); });
+      alive = grid_sync(c, gridDim.x, blockIdx.x, [&] { adjoint_leader_level<W>(c, cur); });
     }
   }
   if (alive) {
-    alive = grid_sync(c, [] {});
+    alive = grid_sync(c, gridDim.x, blockIdx.x, [] {});
     if (alive)
       for (uint64_t e = tid; e < a.m; e += nthreads) grad_w[e] = static_cast<float>(ld_agent(&a.grad64[e]));
   }

@@ -4,9 +4,21 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "sssp.h"
 #include "sssp_internal.h"
+
+// Working set of one extra concurrent group (the first group's lives in Params).
+struct GroupMem {
+  uint32_t* tbuf[2] = {nullptr, nullptr};
+  uint32_t *qstamp = nullptr, *sstamp = nullptr, *bstamp = nullptr, *fstamp = nullptr, *ovf_at = nullptr;
+  uint32_t* front[2] = {nullptr, nullptr};
+  uint32_t* slist = nullptr;
+  uint32_t* bins = nullptr;
+  uint32_t* far[2] = {nullptr, nullptr};
+  uint64_t* hub = nullptr;
+};
 
 struct sssp_handle {
   int device = 0;
@@ -27,7 +39,12 @@ struct sssp_handle {
   int32_t* src_dev = nullptr;
   int32_t src_cap = 0;
   int32_t* src_host = nullptr;   // pinned staging for sources
-  sssp::Ctl* ctl_host = nullptr;  // pinned copy of the control block
+  sssp::Ctl* ctl_host = nullptr;  // pinned copy of the control blocks [kMaxGroups]
+  sssp::Ctl* ctls = nullptr;      // [kMaxGroups] control blocks; group g uses ctls[g]
+  sssp::Params* params_dev = nullptr;  // [kMaxGroups] per-group parameters of the solver launch
+  uint32_t groups = 1;            // concurrent groups of the next launch
+  uint32_t enq_groups = 0;        // groups of the last enqueued launch (0: none)
+  std::vector<GroupMem> extra;    // working sets of groups 1, 2, ...
   sssp_stats last{};
   bool solved = false;
   bool stamps_dirty = false;
@@ -46,7 +63,6 @@ struct sssp_handle {
 
 namespace {
 
-constexpr uint32_t kEpochLimit = 1u << 30;
 constexpr uint32_t kDefaultInlineEdges = 4096;
 
 sssp_status from_hip(hipError_t e) {
@@ -70,12 +86,18 @@ hipError_t dalloc(T** p, size_t count) {
 void free_handle(sssp_handle* h) {
   if (!h) return;
   sssp::Params& p = h->p;
-  void* extra[] = {h->inv, h->adj_d, h->adj_parent, h->adj_cnt, h->adj_g, h->adj_grad64, h->aux};
+  void* extra[] = {h->inv, h->adj_d, h->adj_parent, h->adj_cnt, h->adj_g, h->adj_grad64, h->aux, h->params_dev};
   for (void* q : extra)
     if (q) (void)hipFree(q);
+  for (GroupMem& gm : h->extra) {
+    void* mem[] = {gm.tbuf[0], gm.tbuf[1], gm.qstamp, gm.sstamp, gm.bstamp, gm.fstamp, gm.ovf_at, gm.front[0],
+                   gm.front[1], gm.slist, gm.bins, gm.far[0], gm.far[1], gm.hub};
+    for (void* q : mem)
+      if (q) (void)hipFree(q);
+  }
   void* dev[] = {h->off, h->split, const_cast<uint4*>(p.rows), const_cast<uint64_t*>(p.edges),
                  p.qstamp, p.sstamp, p.bstamp, p.fstamp, p.ovf_at, p.front[0], p.front[1], p.slist, p.bins,
-                 p.far[0], p.far[1], p.hub, p.ctl, h->perm, h->src_dev, const_cast<uint32_t*>(p.vid), p.tbuf[0],
+                 p.far[0], p.far[1], p.hub, h->ctls, h->perm, h->src_dev, const_cast<uint32_t*>(p.vid), p.tbuf[0],
                  p.tbuf[1]};
   for (void* q : dev)
     if (q) (void)hipFree(q);
@@ -95,6 +117,79 @@ sssp_status configure_grid(sssp_handle* h) {
   if (per_cu > h->occupancy) per_cu = h->occupancy;
   if (per_cu < 1) return SSSP_ERR_UNSUPPORTED;
   h->grid = per_cu * h->cus;
+  return SSSP_OK;
+}
+
+// fp32 bucket indices floor(t / delta) of every distance the solver can
+// produce stay below 2^32 - 1 (the "none" tag). A tentative distance that wins
+// an update is the rounded left-to-right sum along a simple path (a walk with a
+// cycle never beats the value it had at the cycle's start), so it is at most
+// the total weight times (1 + 2^-24)^(n-1), one rounding per edge.
+bool f32_buckets_fit(double wsum, int64_t n, float delta) {
+  const double bound = wsum * std::exp(static_cast<double>(n - 1) * 0x1p-24) * (1.0 + 0x1p-40);
+  return bound / static_cast<double>(delta) < 4294967040.0;  // 2^32 - 256
+}
+
+// Working set of one more concurrent group: the same arrays as the first
+// group's, with the de-duplication stamps cleared (its tags start at zero).
+sssp_status alloc_group(sssp_handle* h, GroupMem* gm) {
+  const size_t un = static_cast<size_t>(h->n);
+  uint32_t** words[] = {&gm->tbuf[0], &gm->tbuf[1], &gm->qstamp, &gm->sstamp, &gm->bstamp, &gm->fstamp, &gm->ovf_at,
+                        &gm->front[0], &gm->front[1], &gm->slist, &gm->far[0], &gm->far[1]};
+  for (uint32_t** q : words) SSSP_TRY(dalloc(q, un));
+  SSSP_TRY(dalloc(&gm->bins, un * h->p.ring));
+  SSSP_TRY(dalloc(&gm->hub, h->p.hub_cap));
+  uint32_t* zero[] = {gm->qstamp, gm->sstamp, gm->fstamp, gm->ovf_at};
+  for (uint32_t* q : zero) SSSP_TRY(hipMemset(q, 0, un * sizeof(uint32_t)));
+  return SSSP_OK;
+}
+
+// Write the per-group launch parameters to the device. Every group shares the
+// graph and the schedule parameters; group g has its own control block and
+// working set. Waits for the device first: a launch may still read them.
+sssp_status upload_params(sssp_handle* h) {
+  std::vector<sssp::Params> all(h->groups, h->p);
+  for (uint32_t g = 0; g < h->groups; ++g) {
+    sssp::Params& q = all[g];
+    q.groups = h->groups;
+    q.ctl = h->ctls + g;
+    q.next_source = &h->ctls[0].next_source;
+    if (g == 0) continue;
+    const GroupMem& gm = h->extra[g - 1];
+    q.tbuf[0] = gm.tbuf[0];
+    q.tbuf[1] = gm.tbuf[1];
+    q.qstamp = gm.qstamp;
+    q.sstamp = gm.sstamp;
+    q.bstamp = gm.bstamp;
+    q.fstamp = gm.fstamp;
+    q.ovf_at = gm.ovf_at;
+    q.front[0] = gm.front[0];
+    q.front[1] = gm.front[1];
+    q.slist = gm.slist;
+    q.bins = gm.bins;
+    q.far[0] = gm.far[0];
+    q.far[1] = gm.far[1];
+    q.hub = gm.hub;
+  }
+  SSSP_TRY(hipDeviceSynchronize());
+  SSSP_TRY(hipMemcpy(h->params_dev, all.data(), sizeof(sssp::Params) * all.size(), hipMemcpyHostToDevice));
+  return SSSP_OK;
+}
+
+// Clear the de-duplication stamps and overflow marks of the groups of the next
+// launch with fill kernels (no memset nodes when the stream is being captured).
+sssp_status clear_stamps(sssp_handle* h, hipStream_t s) {
+  const size_t un = static_cast<size_t>(h->n);
+  for (uint32_t g = 0; g < h->groups; ++g) {
+    uint32_t* q[4];
+    if (g == 0) {
+      q[0] = h->p.qstamp, q[1] = h->p.sstamp, q[2] = h->p.fstamp, q[3] = h->p.ovf_at;
+    } else {
+      const GroupMem& gm = h->extra[g - 1];
+      q[0] = gm.qstamp, q[1] = gm.sstamp, q[2] = gm.fstamp, q[3] = gm.ovf_at;
+    }
+    for (uint32_t* a : q) SSSP_TRY(sssp::launch_fill(a, un, 0u, s));
+  }
   return SSSP_OK;
 }
 
@@ -141,9 +236,7 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
     std::memcpy(&wmax, &h->wmax_bits, sizeof(float));
     const double dd = static_cast<double>(h->delta_f);
     span = static_cast<double>(wmax) / dd;
-    // every finite fp32 path sum is at most the total weight (times a rounding
-    // factor well below 2): bucket indices then stay below 2^29
-    if (wsum * 2.0 / dd >= static_cast<double>(1u << 29)) return SSSP_ERR_UNSUPPORTED;
+    if (!f32_buckets_fit(wsum, n, h->delta_f)) return SSSP_ERR_UNSUPPORTED;
   }
   uint32_t ring = h->tuning.ring_buckets > 0 ? static_cast<uint32_t>(h->tuning.ring_buckets)
                                               : pow2_at_least(static_cast<uint32_t>(std::min(span + 2.0, 64.0)));
@@ -188,14 +281,19 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   SSSP_TRY(dalloc(&p.bins, un * ring));
   SSSP_TRY(dalloc(&p.far[0], un));
   SSSP_TRY(dalloc(&p.far[1], un));
-  SSSP_TRY(dalloc(&p.ctl, 1));
-  SSSP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->ctl_host), sizeof(sssp::Ctl), hipHostMallocDefault));
+  SSSP_TRY(dalloc(&h->ctls, sssp::kMaxGroups));
+  p.ctl = h->ctls;
+  p.next_source = &h->ctls[0].next_source;
+  p.groups = 1;
+  SSSP_TRY(dalloc(&h->params_dev, sssp::kMaxGroups));
+  SSSP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->ctl_host), sizeof(sssp::Ctl) * sssp::kMaxGroups,
+                         hipHostMallocDefault));
   SSSP_TRY(hipMemsetAsync(p.qstamp, 0, un * sizeof(uint32_t), stream));
   SSSP_TRY(hipMemsetAsync(p.sstamp, 0, un * sizeof(uint32_t), stream));
   SSSP_TRY(hipMemsetAsync(p.fstamp, 0, un * sizeof(uint32_t), stream));
   SSSP_TRY(hipMemsetAsync(p.ovf_at, 0, un * sizeof(uint32_t), stream));
-  SSSP_TRY(hipMemsetAsync(p.ctl, 0, sizeof(sssp::Ctl), stream));
-  SSSP_TRY(sssp::launch_ctl_reset(p.ctl, 1, nullptr, 0, stream));
+  SSSP_TRY(hipMemsetAsync(h->ctls, 0, sizeof(sssp::Ctl) * sssp::kMaxGroups, stream));
+  SSSP_TRY(sssp::launch_ctl_reset(h->ctls, sssp::kMaxGroups, 1, nullptr, 0, stream));
 
   // 4. relabel by in-degree, then the light/heavy split (A_L, A_H)
   uint32_t* vid = nullptr;
@@ -214,7 +312,9 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   if (be == hipSuccess) be = hipStreamSynchronize(stream);
   (void)hipFree(build);
   SSSP_TRY(be);
-  return configure_grid(h);
+  const sssp_status st = configure_grid(h);
+  if (st != SSSP_OK) return st;
+  return upload_params(h);
 }
 
 // Copy host sources into the handle's device buffer (checked against n).
@@ -249,6 +349,59 @@ uint32_t ring_for(const sssp_handle* h, uint32_t wmax_bits) {
   }
   uint32_t ring = pow2_at_least(static_cast<uint32_t>(std::min(span + 2.0, 64.0)));
   return ring < 2 ? 2 : ring;
+}
+
+// Enqueue one solver launch over k sources read from device memory: a reset of
+// the groups' control blocks (a kernel), then the cooperative launch.
+sssp_status enqueue_solve(sssp_handle* h, const int32_t* sources_dev, int32_t k, void* dist, hipStream_t s) {
+  int reset_epochs = 0;
+  if (h->stamps_dirty) {  // an aborted launch may have left stamps and marks behind
+    const sssp_status st = clear_stamps(h, s);
+    if (st != SSSP_OK) return st;
+    reset_epochs = 1;
+    h->stamps_dirty = false;
+  }
+  SSSP_TRY(sssp::launch_ctl_reset(h->ctls, h->groups, reset_epochs, h->trace, h->trace_cap, s));
+  SSSP_TRY(sssp::launch_solver(h->params_dev, h->groups, h->p.wtype, sources_dev, k, static_cast<uint32_t*>(dist),
+                               h->grid, s));
+  h->enq_groups = h->groups;
+  return SSSP_OK;
+}
+
+// Wait for the last enqueued launch and turn its control blocks into a status
+// and the statistics of sssp_last_stats.
+sssp_status read_status(sssp_handle* h, hipStream_t s) {
+  if (h->enq_groups == 0) return SSSP_ERR_NO_FORWARD;
+  const uint32_t groups = h->enq_groups;
+  SSSP_TRY(hipMemcpyAsync(h->ctl_host, h->ctls, sizeof(sssp::Ctl) * groups, hipMemcpyDeviceToHost, s));
+  SSSP_TRY(hipStreamSynchronize(s));
+  sssp_stats st{};
+  bool abort = false, ovf = false, bad = false;
+  for (uint32_t g = 0; g < groups; ++g) {
+    const sssp::Ctl& c = h->ctl_host[g];
+    abort |= c.abort != 0;
+    ovf |= c.ovf_real != 0;
+    bad |= c.bad_source != 0;
+    st.sources += c.sources;
+    st.buckets += c.buckets;
+    st.light_phases += c.light_phases;
+    st.heavy_phases += c.heavy_phases;
+    st.far_phases += c.far_phases;
+    st.light_edges += c.light_edges;
+    st.heavy_edges += c.heavy_edges;
+    st.improvements += c.improvements;
+    st.barriers += c.barriers;
+    st.trace_records += c.trace_len;
+  }
+  if (abort) {
+    h->stamps_dirty = true;
+    return SSSP_ERR_DEVICE;
+  }
+  h->last = st;
+  if (bad) return SSSP_ERR_INVALID_ARGUMENT;
+  if (ovf) return SSSP_ERR_OVERFLOW;
+  h->solved = true;
+  return SSSP_OK;
 }
 
 }  // namespace
@@ -300,38 +453,22 @@ sssp_status sssp_solve(sssp_handle* h, const int32_t* sources, int32_t k, void* 
   if (!h || !sources || k < 1 || !dist) return SSSP_ERR_INVALID_ARGUMENT;
   hipStream_t s = static_cast<hipStream_t>(stream);
   SSSP_TRY(hipSetDevice(h->device));
-  const sssp_status st = stage_sources(h, sources, k, s);
+  sssp_status st = stage_sources(h, sources, k, s);
+  if (st == SSSP_OK) st = enqueue_solve(h, h->src_dev, k, dist, s);
   if (st != SSSP_OK) return st;
-  int reset_epochs = 0;
-  if (h->stamps_dirty) {
-    const size_t un = static_cast<size_t>(h->n);
-    SSSP_TRY(hipMemsetAsync(h->p.qstamp, 0, un * sizeof(uint32_t), s));
-    SSSP_TRY(hipMemsetAsync(h->p.sstamp, 0, un * sizeof(uint32_t), s));
-    SSSP_TRY(hipMemsetAsync(h->p.fstamp, 0, un * sizeof(uint32_t), s));
-    SSSP_TRY(hipMemsetAsync(h->p.ovf_at, 0, un * sizeof(uint32_t), s));
-    reset_epochs = 1;
-  }
-  SSSP_TRY(sssp::launch_ctl_reset(h->p.ctl, reset_epochs, h->trace, h->trace_cap, s));
-  SSSP_TRY(sssp::launch_solver(h->p, h->src_dev, k, static_cast<uint32_t*>(dist), h->grid, s));
-  SSSP_TRY(hipMemcpyAsync(h->ctl_host, h->p.ctl, sizeof(sssp::Ctl), hipMemcpyDeviceToHost, s));
-  SSSP_TRY(hipStreamSynchronize(s));
-  const sssp::Ctl& c = *h->ctl_host;
-  // tags grow by one per step; clear the stamps long before they could wrap
-  h->stamps_dirty = c.abort || c.step > kEpochLimit || c.round > kEpochLimit || c.far_epoch > kEpochLimit;
-  if (c.abort) return SSSP_ERR_DEVICE;
-  h->last.sources = c.sources;
-  h->last.buckets = c.buckets;
-  h->last.light_phases = c.light_phases;
-  h->last.heavy_phases = c.heavy_phases;
-  h->last.far_phases = c.far_phases;
-  h->last.light_edges = c.light_edges;
-  h->last.heavy_edges = c.heavy_edges;
-  h->last.improvements = c.improvements;
-  h->last.barriers = c.barriers;
-  h->last.trace_records = c.trace_len;
-  if (c.ovf_real) return SSSP_ERR_OVERFLOW;
-  h->solved = true;
-  return SSSP_OK;
+  return read_status(h, s);
+}
+
+sssp_status sssp_solve_async(sssp_handle* h, const int32_t* sources, int32_t k, void* dist, void* stream) {
+  if (!h || !sources || k < 1 || !dist) return SSSP_ERR_INVALID_ARGUMENT;
+  SSSP_TRY(hipSetDevice(h->device));
+  return enqueue_solve(h, sources, k, dist, static_cast<hipStream_t>(stream));
+}
+
+sssp_status sssp_solve_status(sssp_handle* h, void* stream) {
+  if (!h) return SSSP_ERR_INVALID_ARGUMENT;
+  SSSP_TRY(hipSetDevice(h->device));
+  return read_status(h, static_cast<hipStream_t>(stream));
 }
 
 sssp_status sssp_backward(sssp_handle* h, const int32_t* sources, int32_t k, const void* dist,
@@ -373,7 +510,7 @@ sssp_status sssp_backward(sssp_handle* h, const int32_t* sources, int32_t k, con
   a.ctl = h->p.ctl;
   SSSP_TRY(hipMemsetAsync(h->aux, 0, 2 * sizeof(unsigned long long), s));
   SSSP_TRY(sssp::launch_count_reached(static_cast<const uint32_t*>(dist), a.n, k, h->wtype, h->aux, s));
-  SSSP_TRY(sssp::launch_ctl_reset(h->p.ctl, 0, nullptr, 0, s));
+  SSSP_TRY(sssp::launch_ctl_reset(h->ctls, 1, 0, nullptr, 0, s));
   SSSP_TRY(sssp::launch_adjoint(a, h->src_dev, k, static_cast<const uint32_t*>(dist), grad_dist, grad_w, h->adj_grid,
                                 s));
   unsigned long long reached = 0;
@@ -407,16 +544,22 @@ sssp_status sssp_set_weights(sssp_handle* h, const void* weights, void* stream) 
   if (h->wtype == SSSP_WEIGHT_F32) {
     double wsum;
     std::memcpy(&wsum, res + 2, sizeof(double));
-    if (wsum * 2.0 / static_cast<double>(h->delta_f) >= static_cast<double>(1u << 29)) return SSSP_ERR_UNSUPPORTED;
+    if (!f32_buckets_fit(wsum, h->n, h->delta_f)) return SSSP_ERR_UNSUPPORTED;
   }
   sssp::Params& p = h->p;
   const size_t un = static_cast<size_t>(h->n), um = static_cast<size_t>(h->m);
   const uint32_t ring = ring_for(h, res[1]);
-  if (ring > p.ring) {  // a larger weight spread needs more near buckets
+  if (ring > p.ring) {  // a larger weight spread needs more near buckets (in every group)
+    SSSP_TRY(hipDeviceSynchronize());
     uint32_t* bins = nullptr;
     SSSP_TRY(dalloc(&bins, un * ring));
     (void)hipFree(p.bins);
     p.bins = bins;
+    for (GroupMem& gm : h->extra) {
+      (void)hipFree(gm.bins);
+      gm.bins = nullptr;
+      SSSP_TRY(dalloc(&gm.bins, un * ring));
+    }
     p.ring = ring;
     p.ring_mask = ring - 1;
   }
@@ -445,7 +588,7 @@ sssp_status sssp_set_weights(sssp_handle* h, const void* weights, void* stream) 
   h->perm = perm;
   h->wmax_bits = res[1];
   h->solved = false;  // distances of earlier solves used the old weights
-  return SSSP_OK;
+  return upload_params(h);
 }
 
 sssp_status sssp_last_stats(const sssp_handle* h, sssp_stats* out) {
@@ -456,19 +599,30 @@ sssp_status sssp_last_stats(const sssp_handle* h, sssp_stats* out) {
 
 sssp_status sssp_set_tuning(sssp_handle* h, const sssp_tuning* t) {
   if (!h || !t) return SSSP_ERR_INVALID_ARGUMENT;
-  if (t->workgroups_per_cu < 0 || t->ring_buckets < 0 || t->inline_edges < 0) return SSSP_ERR_INVALID_ARGUMENT;
+  if (t->workgroups_per_cu < 0 || t->ring_buckets < 0 || t->inline_edges < 0 || t->concurrent_sources < 0)
+    return SSSP_ERR_INVALID_ARGUMENT;
   if (t->ring_buckets != 0 && t->ring_buckets != static_cast<int32_t>(h->p.ring))
     return SSSP_ERR_UNSUPPORTED;  // the ring is sized at create time
+  SSSP_TRY(hipSetDevice(h->device));
   const sssp_tuning old = h->tuning;
+  const int old_grid = h->grid;
   h->tuning = *t;
-  const sssp_status st = configure_grid(h);
+  sssp_status st = configure_grid(h);
+  const uint32_t groups = t->concurrent_sources > 0 ? static_cast<uint32_t>(t->concurrent_sources) : 1u;
+  if (st == SSSP_OK && (groups > sssp::kMaxGroups || h->grid % static_cast<int>(groups) != 0))
+    st = SSSP_ERR_UNSUPPORTED;  // every group gets the same number of workgroups
+  while (st == SSSP_OK && h->extra.size() + 1 < groups) {
+    h->extra.emplace_back();
+    st = alloc_group(h, &h->extra.back());
+  }
   if (st != SSSP_OK) {
     h->tuning = old;
-    (void)configure_grid(h);
+    h->grid = old_grid;
     return st;
   }
+  h->groups = groups;
   h->p.inline_edges = t->inline_edges > 0 ? static_cast<uint32_t>(t->inline_edges) : kDefaultInlineEdges;
-  return SSSP_OK;
+  return upload_params(h);
 }
 
 sssp_status sssp_set_trace(sssp_handle* h, uint64_t* device_buffer, int64_t capacity) {

@@ -88,13 +88,15 @@ struct WeightF32 {
     *out = __float_as_uint(s);
     return *out < kInfF32;  // non-negative operands: the sum is finite or +inf
   }
-  // floor(x / delta) exactly: the estimate from one rounded product is off by
-  // at most one, and j * delta is exact in double for j < 2^29.
+  // floor(x / delta) exactly (bucket i holds i*delta <= x < (i+1)*delta): the
+  // estimate from one rounded product is off by at most one, and the sign of
+  // j*delta - x is exact in a fused multiply-add (one rounding of an exact
+  // value, which is zero only when the value is), for every j below 2^32.
   __device__ static uint32_t bucket(uint32_t x, const Params& p) {
     const double d = static_cast<double>(__uint_as_float(x));
     double j = floor(d * p.inv_delta_d);
-    if (j * p.delta_d > d) j -= 1.0;
-    else if ((j + 1.0) * p.delta_d <= d) j += 1.0;
+    if (fma(j, p.delta_d, -d) > 0.0) j -= 1.0;
+    else if (fma(j + 1.0, p.delta_d, -d) <= 0.0) j += 1.0;
     return static_cast<uint32_t>(j);
   }
 };
@@ -125,22 +127,23 @@ __device__ inline void record_trace(Ctl* c, uint32_t flags) {
   }
 }
 
-// Device-wide barrier over all (co-resident) workgroups. Arrivals are counted
-// first per group of workgroups (blockIdx % 8), then once per group, which
-// keeps same-address atomics short. The last workgroup to arrive runs `leader`
-// (all its threads) before releasing the others. Returns false when the
-// schedule was aborted (a wait ran past kWaitLimitTicks).
+// Barrier over the `size` co-resident workgroups that share the control block
+// `c` (this one has index `rank` among them). Arrivals are counted first per
+// sub-group (rank % 8), then once per sub-group, which keeps same-address
+// atomics short. The last workgroup to arrive runs `leader` (all its threads)
+// before releasing the others. Returns false when the schedule was aborted (a
+// wait ran past kWaitLimitTicks).
 template <class F>
-__device__ bool grid_sync(Ctl* c, F&& leader) {
+__device__ bool grid_sync(Ctl* c, uint32_t size, uint32_t rank, F&& leader) {
   __shared__ uint32_t s_is_leader;
   __shared__ uint32_t s_ok;
   drain_stores();
   __syncthreads();
   uint32_t gen = 0;
   if (threadIdx.x == 0) {
-    const uint32_t groups = gridDim.x < kBarGroups ? gridDim.x : kBarGroups;
-    const uint32_t g = blockIdx.x % groups;
-    const uint32_t gsize = (gridDim.x - g + groups - 1) / groups;
+    const uint32_t groups = size < kBarGroups ? size : kBarGroups;
+    const uint32_t g = rank % groups;
+    const uint32_t gsize = (size - g + groups - 1) / groups;
     gen = ld_agent(&c->bar_gen);
     bool last = false;
     const uint32_t prev = atomicAdd(&c->bar_sub[g][0], 1u);

@@ -17,6 +17,8 @@ constexpr uint32_t kStage = 2 * kWG * kILP;  // LDS staging capacity for list ap
 constexpr uint32_t kBarGroups = 8;     // arrival sub-counters of the grid barrier
 constexpr uint32_t kRingMax = 64;      // near-bucket ring capacity
 constexpr uint32_t kDegClasses = 65536;  // in-degree classes of the relabelling (the last one open-ended)
+constexpr uint32_t kMaxGroups = 256;   // concurrent sources of one launch (workgroup groups)
+constexpr uint32_t kEpochLimit = 1u << 30;  // de-duplication tags are reset before they pass this
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 // Tentative distances are kept as 32-bit patterns: uint32 values for integer
@@ -46,7 +48,7 @@ struct Ctl {
   uint32_t bar_arrive;
   uint32_t bar_gen;
   uint32_t abort;
-  uint32_t source_index;
+  uint32_t source_index;  // source (row) the group is solving, kNone when the batch is done
   uint32_t chunk_next;   // dynamic chunk counter of the current step
   uint32_t hub_count;    // hub pieces queued by the current phase
   uint32_t hub_parent;   // action of the phase that queued them
@@ -64,9 +66,8 @@ struct Ctl {
   uint32_t far_cur;      // which far list is current (0/1)
   uint32_t far_min;      // lower bound on the bucket of any far vertex
   uint32_t far_min_next;
-  // bucket bounds of the current bucket: [lo, hi) as integers or doubles
+  // bounds [lo, hi) of the current bucket (integer weights)
   uint64_t lo_u, hi_u;
-  double lo_d, hi_d;
   // counters
   uint32_t fcount[2];
   uint32_t scount;
@@ -77,7 +78,8 @@ struct Ctl {
   unsigned long long* trace;  // optional step trace: 4 words per record
   unsigned long long tr_edges, tr_impr;  // edges scanned and improvements of the running step (traced runs)
   uint32_t trace_cap;
-  uint32_t pad;
+  uint32_t next_source;  // batch-wide source counter (used in the first group's block only)
+  uint32_t bad_source;   // a source index outside [0, n) was given
   uint32_t bincount[kRingMax];
   // statistics (summed over sources)
   unsigned long long sources, buckets, light_phases, heavy_phases, far_phases;
@@ -109,7 +111,9 @@ struct Params {
   uint64_t* hub;          // [hub_cap] pieces (vertex | piece index << 32)
   uint32_t hub_cap;
   uint32_t inline_edges;  // steps with at most this many edges run on the leader workgroup alone
-  Ctl* ctl;
+  uint32_t groups;        // workgroup groups of the launch, each solving its own sources
+  Ctl* ctl;               // this group's control block
+  uint32_t* next_source;  // shared by every group: next source row to claim
 };
 
 // Adjoint working set (solver ids unless noted).
@@ -151,9 +155,12 @@ hipError_t launch_relabel_and_split(const int64_t* row_ptr, const int32_t* col, 
                                     uint32_t* perm, hipStream_t s);
 hipError_t solver_occupancy(int wtype, int* blocks_per_cu);
 hipError_t launch_pack_rows(const uint32_t* off, const uint32_t* split, int64_t n, uint4* rows, hipStream_t s);
-hipError_t launch_ctl_reset(Ctl* c, int reset_epochs, unsigned long long* trace, uint32_t trace_cap, hipStream_t s);
-hipError_t launch_solver(const Params& p, const int32_t* sources, int k, uint32_t* dist, int grid,
-                         hipStream_t s);
+hipError_t launch_ctl_reset(Ctl* c, uint32_t groups, int reset_epochs, unsigned long long* trace, uint32_t trace_cap,
+                            hipStream_t s);
+hipError_t launch_fill(uint32_t* p, size_t count, uint32_t value, hipStream_t s);
+// `params` is a device array of one Params per group; grid must be a multiple of groups
+hipError_t launch_solver(const Params* params, uint32_t groups, uint32_t wtype, const int32_t* sources, int k,
+                         uint32_t* dist, int grid, hipStream_t s);
 
 // validation status bits
 enum : uint32_t {

@@ -10,6 +10,12 @@
 // the others. Steps too small to be worth a device-wide barrier run on the
 // leader workgroup alone, inside the barrier.
 //
+// Several sources can be solved at once: the workgroups then form groups
+// (workgroup b belongs to group b % groups; with eight groups each group is one
+// XCD, whose L2 keeps that group's distances). Each group has its own control
+// block and working set, claims source rows from a shared counter and runs the
+// schedule above over its own workgroups; the graph is shared.
+//
 // Memory model: every datum one workgroup writes and another reads (distances,
 // stamps, lists, counters, the schedule) is written with device-scope stores
 // or atomics and read with device-scope loads, which are coherent across the
@@ -23,23 +29,26 @@ namespace {
 
 // ------------------------------------------------------------------ schedule
 
+// index of this workgroup within its group, and the group's workgroup count
+__device__ inline uint32_t grp_rank(const Params& p) { return blockIdx.x / p.groups; }
+__device__ inline uint32_t grp_size(const Params& p) { return gridDim.x / p.groups; }
+
 struct Sched {
   uint32_t action, bucket, in_kind, in_count, out_buf, step, round, far_epoch, far_cur, far_base;
   uint32_t hub_count, hub_parent;
   uint64_t lo_u, hi_u;
-  double lo_d, hi_d;
 };
 
+// i*delta <= x < (i+1)*delta for the current bucket i
 template <class W>
-__device__ inline bool in_bucket(uint32_t x, const Sched& s);
+__device__ inline bool in_bucket(uint32_t x, const Sched& s, const Params& p);
 template <>
-__device__ inline bool in_bucket<WeightU32>(uint32_t x, const Sched& s) {
+__device__ inline bool in_bucket<WeightU32>(uint32_t x, const Sched& s, const Params&) {
   return x >= s.lo_u && x < s.hi_u;
 }
 template <>
-__device__ inline bool in_bucket<WeightF32>(uint32_t x, const Sched& s) {
-  const double d = static_cast<double>(__uint_as_float(x));
-  return d >= s.lo_d && d < s.hi_d;
+__device__ inline bool in_bucket<WeightF32>(uint32_t x, const Sched& s, const Params& p) {
+  return WeightF32::bucket(x, p) == s.bucket;
 }
 
 __device__ inline void load_sched(Ctl* c, Sched* s) {
@@ -58,8 +67,6 @@ __device__ inline void load_sched(Ctl* c, Sched* s) {
     s->hub_parent = ld_agent(&c->hub_parent);
     s->lo_u = ld_agent(&c->lo_u);
     s->hi_u = ld_agent(&c->hi_u);
-    s->lo_d = ld_agent(&c->lo_d);
-    s->hi_d = ld_agent(&c->hi_d);
   }
   __syncthreads();
 }
@@ -229,7 +236,7 @@ __device__ void stage_flush(const Params& p, const Sched& s, Stage& sg, bool for
 template <class W>
 __device__ inline void relax_batch(const Params& p, uint32_t* t, const Sched& s, const bool (&active)[kILP],
                                    const uint32_t (&tu)[kILP], const uint32_t (&v)[kILP],
-                                   const uint32_t (&w)[kILP], uint32_t near_end, WgStats& st, Stage& sg) {
+                                   const uint32_t (&w)[kILP], uint64_t near_end, WgStats& st, Stage& sg) {
   uint32_t cand[kILP], tv[kILP];
   bool ok[kILP], win[kILP];
 #pragma unroll
@@ -270,14 +277,16 @@ __device__ inline void relax_batch(const Params& p, uint32_t* t, const Sched& s,
   }
 }
 
-// Work distribution over `nitems` items: in a device-wide step, workgroup b
-// first takes item b with no atomic, then claims further items from a shared
-// counter; the leader workgroup running a step alone walks every item in order.
-__device__ inline uint32_t claim_next(Ctl* c, uint32_t prev, uint32_t nitems, bool solo, uint32_t* s_claim) {
+// Work distribution over `nitems` items: in a step run by a whole group, the
+// workgroup of rank b first takes item b with no atomic, then claims further
+// items from a shared counter; the leader workgroup running a step alone walks
+// every item in order.
+__device__ inline uint32_t claim_next(Ctl* c, uint32_t prev, uint32_t nitems, bool solo, uint32_t size,
+                                      uint32_t* s_claim) {
   if (solo) return prev + 1;
-  if (nitems <= gridDim.x) return nitems;  // every item was taken statically
+  if (nitems <= size) return nitems;  // every item was taken statically
   __syncthreads();
-  if (threadIdx.x == 0) *s_claim = gridDim.x + atomicAdd(&c->chunk_next, 1u);
+  if (threadIdx.x == 0) *s_claim = size + atomicAdd(&c->chunk_next, 1u);
   __syncthreads();
   return *s_claim;
 }
@@ -299,8 +308,8 @@ __device__ inline void queue_hub(const Params& p, uint32_t u, uint32_t deg) {
 // consecutive lanes read consecutive edges of a row. Vertices with kHub or
 // more edges are queued as pieces for a grid-wide hub step instead.
 // List entries per claimed chunk: enough chunks for about four per workgroup.
-__device__ inline uint32_t chunk_for(uint32_t count) {
-  const uint32_t target = (count + 4 * gridDim.x - 1) / (4 * gridDim.x);
+__device__ inline uint32_t chunk_for(uint32_t count, uint32_t size) {
+  const uint32_t target = (count + 4 * size - 1) / (4 * size);
   uint32_t c = kMinChunk;
   while (c < target && c < kChunk) c <<= 1;
   return c;
@@ -317,11 +326,12 @@ __device__ void phase(const Params& p, uint32_t* t, const Sched& s, WgStats& st,
   const bool from_bin = kLight && s.in_kind == kInBin;
   const uint32_t* list = phase_list(p, s, kLight);
   const uint32_t count = s.in_count;
-  const uint32_t near_end = s.bucket + p.ring;
-  const uint32_t chunk = solo ? kChunk : chunk_for(count);
+  const uint64_t near_end = static_cast<uint64_t>(s.bucket) + p.ring;  // no wrap near 2^32
+  const uint32_t size = grp_size(p);
+  const uint32_t chunk = solo ? kChunk : chunk_for(count, size);
   const uint32_t nchunks = (count + chunk - 1) / chunk;
 
-  for (uint32_t c = solo ? 0u : blockIdx.x; c < nchunks; c = claim_next(p.ctl, c, nchunks, solo, &s_claim)) {
+  for (uint32_t c = solo ? 0u : grp_rank(p); c < nchunks; c = claim_next(p.ctl, c, nchunks, solo, size, &s_claim)) {
     const uint32_t k = c * chunk + threadIdx.x;
     uint32_t beg = 0, deg = 0, tu = W::kInf, u = 0;
     bool take = false;
@@ -329,7 +339,7 @@ __device__ void phase(const Params& p, uint32_t* t, const Sched& s, WgStats& st,
       u = ld_agent(&list[k]);
       tu = ld_agent(&t[u]);
       // a ring slot may hold vertices that have since moved to a lower bucket
-      take = !from_bin || in_bucket<W>(tu, s);
+      take = !from_bin || in_bucket<W>(tu, s, p);
       if (take) {
         const uint4 row = p.rows[u];
         beg = kLight ? row.x : row.y;
@@ -408,8 +418,9 @@ __device__ void hub_step(const Params& p, uint32_t* t, const Sched& s, WgStats& 
   __shared__ uint32_t s_beg, s_end, s_tu, s_claim;
   const bool light = s.hub_parent == kActLight;
   const uint32_t count = s.hub_count < p.hub_cap ? s.hub_count : p.hub_cap;
-  const uint32_t near_end = s.bucket + p.ring;
-  for (uint32_t c = blockIdx.x; c < count; c = claim_next(p.ctl, c, count, false, &s_claim)) {
+  const uint64_t near_end = static_cast<uint64_t>(s.bucket) + p.ring;  // no wrap near 2^32
+  const uint32_t size = grp_size(p);
+  for (uint32_t c = grp_rank(p); c < count; c = claim_next(p.ctl, c, count, false, size, &s_claim)) {
     if (threadIdx.x == 0) {
       const uint64_t rec = ld_agent(&p.hub[c]);
       const uint32_t u = static_cast<uint32_t>(rec);
@@ -451,10 +462,11 @@ __device__ void far_step(const Params& p, uint32_t* t, const Sched& s) {
   const uint32_t count = s.in_count;
   const uint32_t* list = p.far[s.far_cur];
   const uint32_t nxt = 1u - s.far_cur;
-  const uint32_t near_end = s.far_base + p.ring;
-  const uint32_t iters = (count + gridDim.x * kWG - 1) / (gridDim.x * kWG);
+  const uint64_t near_end = static_cast<uint64_t>(s.far_base) + p.ring;
+  const uint32_t size = grp_size(p), rank = grp_rank(p);
+  const uint32_t iters = (count + size * kWG - 1) / (size * kWG);
   for (uint32_t it = 0; it < iters; ++it) {
-    const uint32_t k = (it * gridDim.x + blockIdx.x) * kWG + threadIdx.x;
+    const uint32_t k = (it * size + rank) * kWG + threadIdx.x;
     bool to_ring = false, to_far = false;
     uint32_t v = 0, j = 0;
     if (k < count) {
@@ -479,7 +491,7 @@ __device__ void far_step(const Params& p, uint32_t* t, const Sched& s) {
 // is unrepresentable exactly when no other path reached it.
 template <class W>
 __device__ void overflow_step(const Params& p, uint32_t* t) {
-  for (uint32_t v = blockIdx.x * kWG + threadIdx.x; v < p.n; v += gridDim.x * kWG) {
+  for (uint32_t v = grp_rank(p) * kWG + threadIdx.x; v < p.n; v += grp_size(p) * kWG) {
     if (ld_agent(&p.ovf_at[v])) {
       if (ld_agent(&t[v]) == W::kInf) st_agent(&p.ctl->ovf_real, 1u);
       st_agent(&p.ovf_at[v], 0u);
@@ -496,9 +508,6 @@ __device__ void set_bucket(const Params& p, uint32_t i) {
   if (p.wtype == 0) {
     st_agent(&c->lo_u, static_cast<uint64_t>(i) * p.delta_u);
     st_agent(&c->hi_u, static_cast<uint64_t>(i + 1ull) * p.delta_u);
-  } else {
-    st_agent(&c->lo_d, static_cast<double>(i) * p.delta_d);
-    st_agent(&c->hi_d, static_cast<double>(i) * p.delta_d + p.delta_d);
   }
 }
 
@@ -684,29 +693,79 @@ __device__ void lead(const Params& p, uint32_t* t, Sched* s, WgStats& st, Stage&
   }
 }
 
+// The leader's part of the barrier that starts a source: claim the next source
+// row of the batch and initialise its solve (t(s) = 0, the source is the only
+// member of B_0), or mark the group finished.
 template <class W>
-__global__ __launch_bounds__(kWG) void solver_kernel(Params p, const int32_t* sources, int k, uint32_t* dist) {
+__device__ void leader_claim(const Params& p, uint32_t* t, const int32_t* sources, int k, bool reset_tags, Sched* s,
+                             WgStats& st, Stage& sg) {
+  __shared__ int32_t s_src;
+  Ctl* c = p.ctl;
+  if (threadIdx.x == 0) {
+    if (reset_tags) {  // the group's stamps were cleared before this barrier
+      st_agent(&c->step, 0u);
+      st_agent(&c->round, 0u);
+      st_agent(&c->far_epoch, 1u);
+    }
+    const uint32_t r = atomicAdd(p.next_source, 1u);
+    int32_t src = -1;
+    if (r < static_cast<uint32_t>(k)) {
+      src = sources[r];
+      if (src < 0 || static_cast<uint32_t>(src) >= p.n) {  // the row is left as all-unreachable
+        st_agent(&c->bad_source, 1u);
+        st_agent(&c->action, static_cast<uint32_t>(kActDone));
+        src = -1;
+      }
+    }
+    st_agent(&c->source_index, r < static_cast<uint32_t>(k) ? r : kNone);
+    s_src = src;
+  }
+  __syncthreads();
+  if (s_src >= 0) {
+    leader_start<W>(p, t, p.vid[s_src]);
+    lead<W>(p, t, s, st, sg, false);  // the first phases (around one vertex) are small
+  }
+}
+
+template <class W>
+__global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ params, uint32_t groups,
+                                                     const int32_t* sources, int k, uint32_t* dist) {
   __shared__ Sched s;
   __shared__ Stage sg;
+  __shared__ uint32_t s_row;
+  const Params& p = params[blockIdx.x % groups];
+  const uint32_t rank = grp_rank(p), size = grp_size(p);
+  Ctl* c = p.ctl;
   if (threadIdx.x == 0) sg.n = 0;
   __syncthreads();
   WgStats st{0, 0, 0, 0, 0};
   bool alive = true;
-  for (int r = 0; r < k && alive; ++r) {
-    // distances live in solver ids; consecutive sources alternate buffers so that
-    // copying out source r never races with the initialisation of source r + 1
-    uint32_t* t = p.tbuf[r & 1];
-    for (uint32_t v = blockIdx.x * kWG + threadIdx.x; v < p.n; v += gridDim.x * kWG) {
+  for (uint32_t it = 0; alive; ++it) {
+    // the de-duplication tags grow by one per step and per bucket: long before
+    // they could wrap, the group clears its stamps and restarts the tags (every
+    // workgroup reads the same tags: the leader changes them only after this
+    // barrier's arrival)
+    const bool reset_tags = ld_agent(&c->step) > kEpochLimit || ld_agent(&c->round) > kEpochLimit ||
+                            ld_agent(&c->far_epoch) > kEpochLimit;
+    // distances live in solver ids; a group's consecutive sources alternate
+    // buffers so that copying out one row never races with initialising the next
+    uint32_t* t = p.tbuf[it & 1];
+    for (uint32_t v = rank * kWG + threadIdx.x; v < p.n; v += size * kWG) {
       st_agent(&t[v], W::kInf);
       st_agent(&p.bstamp[v], kNone);
+      if (reset_tags) {
+        st_agent(&p.qstamp[v], 0u);
+        st_agent(&p.sstamp[v], 0u);
+        st_agent(&p.fstamp[v], 0u);
+      }
     }
-    const uint32_t src = p.vid[sources[r]];
-    alive = grid_sync(p.ctl, [&] {
-      leader_start<W>(p, t, src);
-      lead<W>(p, t, &s, st, sg, false);  // the first phases (around one vertex) are small
-    });
+    alive = grid_sync(c, size, rank, [&] { leader_claim<W>(p, t, sources, k, reset_tags, &s, st, sg); });
+    if (threadIdx.x == 0) s_row = ld_agent(&c->source_index);
+    __syncthreads();
+    const uint32_t row = s_row;
+    if (!alive || row == kNone) break;
     while (alive) {
-      load_sched(p.ctl, &s);
+      load_sched(c, &s);
       const uint32_t a = s.action;
       if (a == kActDone) break;
       if (a == kActLight) phase<W, true>(p, t, s, st, sg, false);
@@ -714,17 +773,16 @@ __global__ __launch_bounds__(kWG) void solver_kernel(Params p, const int32_t* so
       else if (a == kActHub) hub_step<W>(p, t, s, st, sg);
       else if (a == kActFar) far_step<W>(p, t, s);
       else if (a == kActOverflowCheck) overflow_step<W>(p, t);
-      else if (threadIdx.x == 0) st_agent(&p.ctl->abort, 1u);
-      trace_step_counts(p.ctl, st);
-      alive = grid_sync(p.ctl, [&] { lead<W>(p, t, &s, st, sg, true); });
+      else if (threadIdx.x == 0) st_agent(&c->abort, 1u);
+      trace_step_counts(c, st);
+      alive = grid_sync(c, size, rank, [&] { lead<W>(p, t, &s, st, sg, true); });
     }
-    if (alive) {  // row r of the output in the caller's vertex numbering
-      uint32_t* out = dist + static_cast<size_t>(r) * p.n;
-      for (uint32_t v = blockIdx.x * kWG + threadIdx.x; v < p.n; v += gridDim.x * kWG)
-        out[v] = ld_agent(&t[p.vid[v]]);
+    if (alive) {  // the source's row of the output, in the caller's vertex numbering
+      uint32_t* out = dist + static_cast<size_t>(row) * p.n;
+      for (uint32_t v = rank * kWG + threadIdx.x; v < p.n; v += size * kWG) out[v] = ld_agent(&t[p.vid[v]]);
     }
   }
-  // fold per-lane counters into the control block
+  // fold per-lane counters into the group's control block
   unsigned long long le = st.light_edges, he = st.heavy_edges, im = st.improvements;
   for (int d = 32; d > 0; d >>= 1) {
     le += __shfl_down(le, d);
@@ -732,25 +790,32 @@ __global__ __launch_bounds__(kWG) void solver_kernel(Params p, const int32_t* so
     im += __shfl_down(im, d);
   }
   if (lane() == 0) {
-    if (le) atomicAdd(&p.ctl->light_edges, le);
-    if (he) atomicAdd(&p.ctl->heavy_edges, he);
-    if (im) atomicAdd(&p.ctl->improvements, im);
+    if (le) atomicAdd(&c->light_edges, le);
+    if (he) atomicAdd(&c->heavy_edges, he);
+    if (im) atomicAdd(&c->improvements, im);
   }
 }
 
-// Prepare the control block for a launch: clear the counters and the abort
-// flag (and the epochs when the de-duplication stamps were just cleared).
-__global__ void ctl_reset_kernel(Ctl* c, int reset_epochs, unsigned long long* trace, uint32_t trace_cap) {
-  if (threadIdx.x != 0) return;
-  c->trace = trace;
-  c->trace_cap = trace_cap;
+// Prepare the control blocks of `groups` groups for a launch: clear the
+// counters, the abort flag and the batch's source counter (and the tags when
+// the de-duplication stamps were just cleared). Only the first group traces.
+__global__ void ctl_reset_kernel(Ctl* ctls, uint32_t groups, int reset_epochs, unsigned long long* trace,
+                                 uint32_t trace_cap) {
+  const uint32_t g = threadIdx.x;
+  if (g >= groups) return;
+  Ctl* c = ctls + g;
+  c->trace = g == 0 ? trace : nullptr;
+  c->trace_cap = g == 0 ? trace_cap : 0u;
   c->trace_len = 0;
   c->tr_edges = 0;
   c->tr_impr = 0;
-  for (uint32_t g = 0; g < kBarGroups; ++g) c->bar_sub[g][0] = 0;
+  for (uint32_t b = 0; b < kBarGroups; ++b) c->bar_sub[b][0] = 0;
   c->bar_arrive = 0;
   c->abort = 0;
   c->ovf_real = 0;
+  c->next_source = 0;
+  c->bad_source = 0;
+  c->source_index = kNone;
   c->sources = c->buckets = c->light_phases = c->heavy_phases = c->far_phases = 0;
   c->light_edges = c->heavy_edges = c->improvements = c->barriers = 0;
   c->adj_released = 0;
@@ -761,12 +826,28 @@ __global__ void ctl_reset_kernel(Ctl* c, int reset_epochs, unsigned long long* t
   }
 }
 
+__global__ void fill_kernel(uint32_t* p, size_t count, uint32_t value) {
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    p[i] = value;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t launch_ctl_reset(Ctl* c, int reset_epochs, unsigned long long* trace, uint32_t trace_cap, hipStream_t s) {
-  hipLaunchKernelGGL(ctl_reset_kernel, dim3(1), dim3(64), 0, s, c, reset_epochs, trace, trace_cap);
+hipError_t launch_ctl_reset(Ctl* c, uint32_t groups, int reset_epochs, unsigned long long* trace, uint32_t trace_cap,
+                            hipStream_t s) {
+  if (groups < 1 || groups > kMaxGroups) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(ctl_reset_kernel, dim3(1), dim3(kMaxGroups), 0, s, c, groups, reset_epochs, trace, trace_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(uint32_t* p, size_t count, uint32_t value, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  size_t blocks = (count + kAuxWG - 1) / kAuxWG;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(kAuxWG), 0, s, p, count, value);
   return hipGetLastError();
 }
 
@@ -775,15 +856,35 @@ hipError_t solver_occupancy(int wtype, int* blocks_per_cu) {
                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solver_kernel<WeightF32>, kWG, 0);
 }
 
-hipError_t launch_solver(const Params& p, const int32_t* sources, int k, uint32_t* dist, int grid, hipStream_t s) {
-  Params pp = p;
+// One cooperative launch (every workgroup co-resident, which the barriers
+// need). While the stream is being captured into a graph, the launch-attribute
+// form records a cooperative kernel node.
+hipError_t launch_solver(const Params* params, uint32_t groups, uint32_t wtype, const int32_t* sources, int k,
+                         uint32_t* dist, int grid, hipStream_t s) {
+  if (groups < 1 || groups > kMaxGroups || grid < 1 || grid % static_cast<int>(groups) != 0) return hipErrorInvalidValue;
+  const Params* pp = params;
+  uint32_t gg = groups;
   const int32_t* src = sources;
   int kk = k;
   uint32_t* d = dist;
-  void* args[] = {&pp, &src, &kk, &d};
-  const void* fn = p.wtype == 0 ? reinterpret_cast<const void*>(solver_kernel<WeightU32>)
-                                : reinterpret_cast<const void*>(solver_kernel<WeightF32>);
-  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kWG), args, 0, s);
+  void* args[] = {&pp, &gg, &src, &kk, &d};
+  const void* fn = wtype == 0 ? reinterpret_cast<const void*>(solver_kernel<WeightU32>)
+                              : reinterpret_cast<const void*>(solver_kernel<WeightF32>);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  const hipError_t e = hipStreamIsCapturing(s, &cap);
+  if (e != hipSuccess) return e;
+  if (cap == hipStreamCaptureStatusNone) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kWG), args, 0, s);
+  hipLaunchAttribute attr[1] = {};
+  attr[0].id = hipLaunchAttributeCooperative;
+  attr[0].val.cooperative = 1;
+  hipLaunchConfig_t cfg{};
+  cfg.gridDim = dim3(static_cast<uint32_t>(grid));
+  cfg.blockDim = dim3(kWG);
+  cfg.dynamicSmemBytes = 0;
+  cfg.stream = s;
+  cfg.attrs = attr;
+  cfg.numAttrs = 1;
+  return hipLaunchKernelExC(&cfg, fn, args);
 }
 
 }  // namespace sssp

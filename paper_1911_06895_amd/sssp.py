@@ -26,8 +26,9 @@ SSSP_ERR_UNSUPPORTED = 7
 SSSP_WEIGHT_U32 = 0
 SSSP_WEIGHT_F32 = 1
 
-EXPORTS = ("sssp_create", "sssp_solve", "sssp_backward", "sssp_set_weights", "sssp_last_stats", "sssp_set_tuning",
-           "sssp_set_trace", "sssp_graph_info", "sssp_destroy", "sssp_status_string")
+EXPORTS = ("sssp_create", "sssp_solve", "sssp_solve_async", "sssp_solve_status", "sssp_backward", "sssp_set_weights",
+           "sssp_last_stats", "sssp_set_tuning", "sssp_set_trace", "sssp_graph_info", "sssp_destroy",
+           "sssp_status_string")
 
 
 class SsspGraph(ctypes.Structure):
@@ -43,7 +44,7 @@ class SsspStats(ctypes.Structure):
 
 class SsspTuning(ctypes.Structure):
     _fields_ = [("workgroups_per_cu", ctypes.c_int32), ("ring_buckets", ctypes.c_int32),
-                ("inline_edges", ctypes.c_int32)]
+                ("inline_edges", ctypes.c_int32), ("concurrent_sources", ctypes.c_int32)]
 
 
 class SsspError(RuntimeError):
@@ -68,6 +69,10 @@ def load_library(path: str = LIBRARY) -> ctypes.CDLL:
     lib.sssp_create.restype = ctypes.c_int
     lib.sssp_solve.argtypes = [P, P, ctypes.c_int32, P, P]
     lib.sssp_solve.restype = ctypes.c_int
+    lib.sssp_solve_async.argtypes = [P, P, ctypes.c_int32, P, P]
+    lib.sssp_solve_async.restype = ctypes.c_int
+    lib.sssp_solve_status.argtypes = [P, P]
+    lib.sssp_solve_status.restype = ctypes.c_int
     lib.sssp_backward.argtypes = [P, P, ctypes.c_int32, P, P, P, P]
     lib.sssp_backward.restype = ctypes.c_int
     lib.sssp_set_weights.argtypes = [P, P, P]
@@ -135,13 +140,40 @@ def sssp_create(row_ptr, col_idx, weights, delta: float, stream=None) -> ctypes.
     return h
 
 
+def _check_rows(handle, dist, k: int) -> None:
+    """The library writes k rows of n 4-byte distances into dist."""
+    n = sssp_graph_info(handle)[0]
+    if dist.element_size() != 4 or dist.numel() < k * n:
+        raise ValueError(f"dist must hold [k={k}, n={n}] 4-byte elements")
+
+
 def sssp_solve(handle, sources, dist, stream=None) -> None:
     """sources: host ints [k]; dist: GPU tensor [k, n] (uint32/int32 or float32), overwritten."""
     src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32).reshape(-1))
     if not dist.is_cuda or not dist.is_contiguous():
         raise ValueError("dist must be a contiguous GPU tensor")
+    _check_rows(handle, dist, src.size)
     _check(load_library().sssp_solve(handle, src.ctypes.data_as(ctypes.c_void_p), int(src.size),
                                      ctypes.c_void_p(dist.data_ptr()), _stream(stream)), "sssp_solve")
+
+
+def sssp_solve_async(handle, sources, dist, stream=None) -> None:
+    """Enqueue only (capturable): sources is a GPU int32 tensor [k], dist a GPU tensor [k, n]."""
+    import torch
+
+    if not sources.is_cuda or sources.dtype != torch.int32 or not sources.is_contiguous():
+        raise ValueError("sources must be a contiguous int32 GPU tensor")
+    if not dist.is_cuda or not dist.is_contiguous():
+        raise ValueError("dist must be a contiguous GPU tensor")
+    k = int(sources.numel())
+    _check_rows(handle, dist, k)
+    _check(load_library().sssp_solve_async(handle, ctypes.c_void_p(sources.data_ptr()), k,
+                                           ctypes.c_void_p(dist.data_ptr()), _stream(stream)), "sssp_solve_async")
+
+
+def sssp_solve_status(handle, stream=None) -> None:
+    """Wait for the last enqueued solve and raise SsspError if it failed."""
+    _check(load_library().sssp_solve_status(handle, _stream(stream)), "sssp_solve_status")
 
 
 def sssp_backward(handle, sources, dist, grad_dist, grad_w, stream=None) -> None:
@@ -169,8 +201,10 @@ def sssp_last_stats(handle) -> dict:
     return {name: int(getattr(st, name)) for name, _ in SsspStats._fields_}
 
 
-def sssp_set_tuning(handle, workgroups_per_cu: int = 0, ring_buckets: int = 0, inline_edges: int = 0) -> None:
-    t = SsspTuning(workgroups_per_cu=workgroups_per_cu, ring_buckets=ring_buckets, inline_edges=inline_edges)
+def sssp_set_tuning(handle, workgroups_per_cu: int = 0, ring_buckets: int = 0, inline_edges: int = 0,
+                    concurrent_sources: int = 0) -> None:
+    t = SsspTuning(workgroups_per_cu=workgroups_per_cu, ring_buckets=ring_buckets, inline_edges=inline_edges,
+                   concurrent_sources=concurrent_sources)
     _check(load_library().sssp_set_tuning(handle, ctypes.byref(t)), "sssp_set_tuning")
 
 

@@ -57,9 +57,20 @@ def test_host_argument_checks_without_device():
     assert lib.sssp_create(ctypes.byref(g), 1.0, None, ctypes.byref(h)) == sssp.SSSP_ERR_UNSUPPORTED
     src = (ctypes.c_int32 * 1)(0)
     assert lib.sssp_solve(None, src, 1, 8, None) == sssp.SSSP_ERR_INVALID_ARGUMENT
+    assert lib.sssp_solve_async(None, src, 1, 8, None) == sssp.SSSP_ERR_INVALID_ARGUMENT
+    assert lib.sssp_solve_status(None, None) == sssp.SSSP_ERR_INVALID_ARGUMENT
+    assert lib.sssp_set_tuning(None, ctypes.byref(sssp.SsspTuning())) == sssp.SSSP_ERR_INVALID_ARGUMENT
     st = sssp.SsspStats()
     assert lib.sssp_last_stats(None, ctypes.byref(st)) == sssp.SSSP_ERR_INVALID_ARGUMENT
     lib.sssp_destroy(None)
+
+
+def test_tuning_struct_matches_header():
+    """The ctypes mirror of sssp_tuning has the header's fields in the header's order."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\} sssp_tuning;", text).group(1)
+    fields = re.findall(r"int32_t\s+(\w+);", body)
+    assert fields == [name for name, _ in sssp.SsspTuning._fields_]
 
 
 def test_product_path_has_no_oracle_dependency():

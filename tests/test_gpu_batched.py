@@ -1,0 +1,159 @@
+"""Concurrent sources (several workgroup groups in one launch), the enqueue-only
+entry point with device-resident sources, and its capture into a HIP graph,
+against the CPU oracle (Dijkstra rows bit-exact, or the O(m) certificate)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_1911_06895_amd import graphs as G  # noqa: E402
+from paper_1911_06895_amd import sssp  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU-only hosts
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def as_host(dist, wdtype):
+    d = dist.cpu().numpy()
+    return d.view(np.uint32) if wdtype == np.uint32 else d
+
+
+def same_bits(a, b):
+    return np.array_equal(np.asarray(a).view(np.uint32), np.asarray(b).view(np.uint32))
+
+
+def check_rows(g, srcs, rows, exact_rows=4):
+    """The first rows against Dijkstra bit for bit, every row by the certificate."""
+    for r, s in enumerate(srcs):
+        if r < exact_rows:
+            want, rc = oracle.dijkstra(g, int(s))
+            assert rc == oracle.OK
+            assert same_bits(rows[r], want), f"row {r} (source {s}) differs from Dijkstra"
+        else:
+            assert oracle.certify(g, int(s), rows[r]) == oracle.CERT_OK, f"row {r} (source {s}) not certified"
+
+
+@pytest.mark.parametrize("groups", [2, 8, 32, 256])
+@pytest.mark.parametrize("kind", ["u32", "f32_loguniform"])
+def test_concurrent_groups_match_oracle(groups, kind):
+    print(f"[batched] groups={groups} kind={kind}", flush=True)
+    if kind == "u32":
+        g, delta = G.rmat_graph(14, 16, cfg=61, weights="u32", wlo=1, whi=255), 32
+    else:
+        g, delta = G.rmat_graph(14, 16, cfg=62, weights="f32_loguniform", wlo=1e-2, whi=1e2), 2.0 ** -5
+    srcs = G.sources_with_outedges(g, 3 * groups // 2 + 5, cfg=61)  # more sources than groups, not a multiple
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, delta)
+    try:
+        solver.set_tuning(concurrent_sources=groups)
+        rows = solver.solve_numpy(srcs)
+        st = solver.stats()
+        assert st["sources"] == len(srcs)
+        check_rows(g, srcs, rows, exact_rows=6)
+        solver.set_tuning(concurrent_sources=1)  # one group: the same rows, bit for bit
+        assert np.array_equal(rows.view(np.uint32), solver.solve_numpy(srcs).view(np.uint32))
+    finally:
+        solver.close()
+
+
+def test_c4a_configuration():
+    """R-MAT scale 18, fp32 log-uniform weights in [1e-2, 1e2], 256 sources, 8 groups."""
+    print("[batched] C4a rmat_s18_f32log k=256 groups=8", flush=True)
+    g = G.workload("rmat_s18_f32log")
+    srcs = G.sources_with_outedges(g, 256, cfg=41)
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, 2.0 ** -5)
+    try:
+        solver.set_tuning(concurrent_sources=8)
+        rows = solver.solve_numpy(srcs)
+        assert solver.stats()["sources"] == 256
+    finally:
+        solver.close()
+    check_rows(g, srcs, rows, exact_rows=3)
+
+
+def test_async_device_sources_and_status():
+    g = G.er_graph(5000, 40000, cfg=63, weights="u32", wlo=1, whi=100)
+    srcs = np.array([0, 17, 4999, 2500, 3], dtype=np.int32)
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, 16)
+    try:
+        solver.set_tuning(concurrent_sources=4)
+        src_dev = torch.from_numpy(srcs).cuda()
+        dist = torch.empty((len(srcs), g.n), dtype=torch.int32, device="cuda")
+        sssp.sssp_solve_async(solver.handle, src_dev, dist)
+        sssp.sssp_solve_status(solver.handle)
+        check_rows(g, srcs, as_host(dist, np.uint32), exact_rows=len(srcs))
+        # a source outside [0, n): its row is all-unreachable, the others are correct, the status says so
+        bad = torch.tensor([5, g.n, 9], dtype=torch.int32, device="cuda")
+        dist2 = torch.empty((3, g.n), dtype=torch.int32, device="cuda")
+        sssp.sssp_solve_async(solver.handle, bad, dist2)
+        with pytest.raises(sssp.SsspError) as e:
+            sssp.sssp_solve_status(solver.handle)
+        assert e.value.status == sssp.SSSP_ERR_INVALID_ARGUMENT
+        d2 = as_host(dist2, np.uint32)
+        assert np.all(d2[1] == np.uint32(0xFFFFFFFF))
+        check_rows(g, [5, 9], d2[[0, 2]], exact_rows=2)
+        # the handle stays usable
+        sssp.sssp_solve_async(solver.handle, src_dev, dist)
+        sssp.sssp_solve_status(solver.handle)
+    finally:
+        solver.close()
+
+
+def test_status_without_enqueue_and_bad_tuning():
+    g = G.er_graph(300, 2000, cfg=64, weights="u32", wlo=1, whi=9)
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, 4)
+    try:
+        with pytest.raises(sssp.SsspError) as e:
+            sssp.sssp_solve_status(solver.handle)
+        assert e.value.status == sssp.SSSP_ERR_NO_FORWARD
+        for bad in (3, 512):  # not a divisor of the workgroup count / above the limit
+            with pytest.raises(sssp.SsspError) as e:
+                solver.set_tuning(concurrent_sources=bad)
+            assert e.value.status == sssp.SSSP_ERR_UNSUPPORTED
+        with pytest.raises(sssp.SsspError) as e:
+            solver.set_tuning(concurrent_sources=-1)
+        assert e.value.status == sssp.SSSP_ERR_INVALID_ARGUMENT
+        rows = solver.solve_numpy([0, 1])  # the failed calls left the handle as it was
+        check_rows(g, [0, 1], rows, exact_rows=2)
+    finally:
+        solver.close()
+
+
+@pytest.mark.parametrize("groups", [1, 8])
+def test_graph_capture_replays(groups):
+    """sssp_solve_async recorded into a HIP graph by stream capture; every replay (with new
+    sources written into the captured buffer, and eager work in between) equals an eager solve."""
+    print(f"[batched] graph capture groups={groups}", flush=True)
+    g = G.rmat_graph(13, 16, cfg=65, weights="f32_loguniform", wlo=1e-2, whi=1e2)
+    cand = G.sources_with_outedges(g, 48, cfg=65)
+    k = 16
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, 2.0 ** -4)
+    try:
+        solver.set_tuning(concurrent_sources=groups)
+        src_static = torch.from_numpy(cand[:k].astype(np.int32)).cuda()
+        out_static = torch.empty((k, g.n), dtype=torch.float32, device="cuda")
+        stream = torch.cuda.Stream()
+        stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(stream):  # warm up on the capture stream
+            sssp.sssp_solve_async(solver.handle, src_static, out_static, stream)
+        sssp.sssp_solve_status(solver.handle, stream)
+        torch.cuda.current_stream().wait_stream(stream)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            sssp.sssp_solve_async(solver.handle, src_static, out_static, stream)
+        for rep in range(3):
+            batch = cand[rep * k:(rep + 1) * k].astype(np.int32)
+            src_static.copy_(torch.from_numpy(batch))
+            graph.replay()
+            torch.cuda.synchronize()
+            sssp.sssp_solve_status(solver.handle, torch.cuda.current_stream())
+            got = out_static.cpu().numpy()
+            eager = solver.solve_numpy(batch)  # eager work between replays
+            assert same_bits(got, eager), f"replay {rep} differs from the eager solve"
+            check_rows(g, batch, got, exact_rows=2)
+        del graph
+    finally:
+        torch.cuda.synchronize()
+        solver.close()

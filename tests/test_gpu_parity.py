@@ -211,8 +211,11 @@ def test_invalid_inputs_rejected():
     assert _create_status(np.array([0, 2, 3, 2], dtype=np.int64), col, ok_w, 2) == sssp.SSSP_ERR_INVALID_ARGUMENT
     assert _create_status(rp, col, ok_w, 2.5) == sssp.SSSP_ERR_INVALID_ARGUMENT
     assert _create_status(rp, col, ok_w, 0) == sssp.SSSP_ERR_INVALID_ARGUMENT
-    # fp32: total weight / delta must keep bucket indices below 2^29
+    # fp32: bucket indices of every possible distance (total weight times the
+    # rounding factor, over delta) must fit 32 bits
     assert _create_status(rp, col, np.array([1e20, 1.0, 1.0], dtype=np.float32), 1e-3) == sssp.SSSP_ERR_UNSUPPORTED
+    assert _create_status(rp, col, np.array([3e9, 2e9, 1.0], dtype=np.float32), 1.0) == sssp.SSSP_ERR_UNSUPPORTED
+    assert _create_status(rp, col, np.array([1e9, 2e9, 1.0], dtype=np.float32), 1.0) == sssp.SSSP_OK
     g = G.workload("er_n1024_m8192")
     solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, 32)
     try:
@@ -224,6 +227,16 @@ def test_invalid_inputs_rejected():
         assert_exact(g, got[0], 3)
     finally:
         solver.close()
+
+
+def test_fp32_bucket_indices_above_2_29():
+    """Bucket indices up to about 3e9 (exact floor(t / delta) by a fused multiply-add sign test)."""
+    g = G.path_graph(5, np.array([1e9, 1e9, 3.0, 1e9], dtype=np.float32))
+    for delta in (1.0, 3.0, 0.75):
+        if 3.0e9 * 1.0000001 / delta >= 2**32 - 256:
+            continue
+        got, _ = gpu_solve(g, delta, [0])
+        assert_exact(g, got[0], 0, f"delta={delta}")
 
 
 def test_tuning_variants_agree():
