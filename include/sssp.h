@@ -152,6 +152,27 @@ sssp_status sssp_solve(sssp_handle *h, const int32_t *sources, int32_t k, void *
 sssp_status sssp_solve_async(sssp_handle *h, const int32_t *sources, int32_t k, void *dist, void *stream);
 
 /*
+ * sssp_solve_multi -- distances from the nearest of k sources, in one solve.
+ *   dist receives d(v) = min over r of d_{sources[r]}(v): delta-stepping with
+ *   every source at distance 0 in the first bucket (Fig. 1 left, initialisation
+ *   t(s) = 0 applied to each source). For a graph that is the disjoint union of
+ *   several graphs (a block-diagonal adjacency matrix) with one source in each,
+ *   this solves every graph of the batch at once: each block's rows of dist are
+ *   its own single-source distances.
+ *   sources: HOST int32 [k], each in [0, n), repeats allowed.  dist: DEVICE [n]
+ *   of the weight type, overwritten.  Synchronises the stream.
+ *   Errors: INVALID_ARGUMENT, OVERFLOW, DEVICE.
+ */
+sssp_status sssp_solve_multi(sssp_handle *h, const int32_t *sources, int32_t k, void *dist, void *stream);
+
+/*
+ * sssp_solve_multi_async -- sssp_solve_multi, enqueued only (sources in DEVICE
+ *   memory, read when the work runs; capturable like sssp_solve_async; outcome
+ *   from sssp_solve_status). Errors before enqueueing: INVALID_ARGUMENT, DEVICE.
+ */
+sssp_status sssp_solve_multi_async(sssp_handle *h, const int32_t *sources, int32_t k, void *dist, void *stream);
+
+/*
  * sssp_solve_status -- wait for the last enqueued solve (sssp_solve_async, or
  *   the last replay of a graph that recorded it) on `stream` and report its
  *   outcome; on success its counters become those of sssp_last_stats and

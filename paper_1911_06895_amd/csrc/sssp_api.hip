@@ -41,7 +41,7 @@ struct sssp_handle {
   int32_t* src_host = nullptr;   // pinned staging for sources
   sssp::Ctl* ctl_host = nullptr;  // pinned copy of the control blocks [kMaxGroups]
   sssp::Ctl* ctls = nullptr;      // [kMaxGroups] control blocks; group g uses ctls[g]
-  sssp::Params* params_dev = nullptr;  // [kMaxGroups] per-group parameters of the solver launch
+  sssp::Params* params_dev = nullptr;  // [kMaxGroups + 1] per-group launch parameters; the last: one group alone
   uint32_t groups = 1;            // concurrent groups of the next launch
   uint32_t enq_groups = 0;        // groups of the last enqueued launch (0: none)
   std::vector<GroupMem> extra;    // working sets of groups 1, 2, ...
@@ -130,6 +130,14 @@ bool f32_buckets_fit(double wsum, int64_t n, float delta) {
   return bound / static_cast<double>(delta) < 4294967040.0;  // 2^32 - 256
 }
 
+// Every weight is light (w <= delta): A_H is empty.
+uint32_t no_heavy_for(const sssp_handle* h, uint32_t wmax_bits) {
+  if (h->wtype == SSSP_WEIGHT_U32) return wmax_bits <= h->delta_u ? 1u : 0u;
+  float wmax;
+  std::memcpy(&wmax, &wmax_bits, sizeof(float));
+  return wmax <= h->delta_f ? 1u : 0u;
+}
+
 // Working set of one more concurrent group: the same arrays as the first
 // group's, with the de-duplication stamps cleared (its tags start at zero).
 sssp_status alloc_group(sssp_handle* h, GroupMem* gm) {
@@ -171,8 +179,13 @@ sssp_status upload_params(sssp_handle* h) {
     q.far[1] = gm.far[1];
     q.hub = gm.hub;
   }
+  sssp::Params single = h->p;  // the whole grid as one group (multi-source solves)
+  single.groups = 1;
+  single.ctl = h->ctls;
+  single.next_source = &h->ctls[0].next_source;
   SSSP_TRY(hipDeviceSynchronize());
   SSSP_TRY(hipMemcpy(h->params_dev, all.data(), sizeof(sssp::Params) * all.size(), hipMemcpyHostToDevice));
+  SSSP_TRY(hipMemcpy(h->params_dev + sssp::kMaxGroups, &single, sizeof(single), hipMemcpyHostToDevice));
   return SSSP_OK;
 }
 
@@ -249,6 +262,7 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   p.ring = ring;
   p.ring_mask = ring - 1;
   p.wtype = static_cast<uint32_t>(g->wtype);
+  p.no_heavy = no_heavy_for(h, h->wmax_bits);
   p.delta_u = h->delta_u;
   p.delta_d = static_cast<double>(h->delta_f);
   p.inv_delta_d = h->delta_f > 0 ? 1.0 / static_cast<double>(h->delta_f) : 0.0;
@@ -285,7 +299,7 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   p.ctl = h->ctls;
   p.next_source = &h->ctls[0].next_source;
   p.groups = 1;
-  SSSP_TRY(dalloc(&h->params_dev, sssp::kMaxGroups));
+  SSSP_TRY(dalloc(&h->params_dev, sssp::kMaxGroups + 1));
   SSSP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->ctl_host), sizeof(sssp::Ctl) * sssp::kMaxGroups,
                          hipHostMallocDefault));
   SSSP_TRY(hipMemsetAsync(p.qstamp, 0, un * sizeof(uint32_t), stream));
@@ -353,7 +367,9 @@ uint32_t ring_for(const sssp_handle* h, uint32_t wmax_bits) {
 
 // Enqueue one solver launch over k sources read from device memory: a reset of
 // the groups' control blocks (a kernel), then the cooperative launch.
-sssp_status enqueue_solve(sssp_handle* h, const int32_t* sources_dev, int32_t k, void* dist, hipStream_t s) {
+sssp_status enqueue_solve(sssp_handle* h, const int32_t* sources_dev, int32_t k, int multi, void* dist,
+                          hipStream_t s) {
+  const uint32_t groups = multi ? 1u : h->groups;
   int reset_epochs = 0;
   if (h->stamps_dirty) {  // an aborted launch may have left stamps and marks behind
     const sssp_status st = clear_stamps(h, s);
@@ -361,10 +377,10 @@ sssp_status enqueue_solve(sssp_handle* h, const int32_t* sources_dev, int32_t k,
     reset_epochs = 1;
     h->stamps_dirty = false;
   }
-  SSSP_TRY(sssp::launch_ctl_reset(h->ctls, h->groups, reset_epochs, h->trace, h->trace_cap, s));
-  SSSP_TRY(sssp::launch_solver(h->params_dev, h->groups, h->p.wtype, sources_dev, k, static_cast<uint32_t*>(dist),
-                               h->grid, s));
-  h->enq_groups = h->groups;
+  SSSP_TRY(sssp::launch_ctl_reset(h->ctls, groups, reset_epochs, h->trace, h->trace_cap, s));
+  SSSP_TRY(sssp::launch_solver(multi ? h->params_dev + sssp::kMaxGroups : h->params_dev, groups, h->p.wtype,
+                               sources_dev, k, multi, static_cast<uint32_t*>(dist), h->grid, s));
+  h->enq_groups = groups;
   return SSSP_OK;
 }
 
@@ -454,7 +470,7 @@ sssp_status sssp_solve(sssp_handle* h, const int32_t* sources, int32_t k, void* 
   hipStream_t s = static_cast<hipStream_t>(stream);
   SSSP_TRY(hipSetDevice(h->device));
   sssp_status st = stage_sources(h, sources, k, s);
-  if (st == SSSP_OK) st = enqueue_solve(h, h->src_dev, k, dist, s);
+  if (st == SSSP_OK) st = enqueue_solve(h, h->src_dev, k, 0, dist, s);
   if (st != SSSP_OK) return st;
   return read_status(h, s);
 }
@@ -462,7 +478,23 @@ sssp_status sssp_solve(sssp_handle* h, const int32_t* sources, int32_t k, void* 
 sssp_status sssp_solve_async(sssp_handle* h, const int32_t* sources, int32_t k, void* dist, void* stream) {
   if (!h || !sources || k < 1 || !dist) return SSSP_ERR_INVALID_ARGUMENT;
   SSSP_TRY(hipSetDevice(h->device));
-  return enqueue_solve(h, sources, k, dist, static_cast<hipStream_t>(stream));
+  return enqueue_solve(h, sources, k, 0, dist, static_cast<hipStream_t>(stream));
+}
+
+sssp_status sssp_solve_multi(sssp_handle* h, const int32_t* sources, int32_t k, void* dist, void* stream) {
+  if (!h || !sources || k < 1 || !dist) return SSSP_ERR_INVALID_ARGUMENT;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SSSP_TRY(hipSetDevice(h->device));
+  sssp_status st = stage_sources(h, sources, k, s);
+  if (st == SSSP_OK) st = enqueue_solve(h, h->src_dev, k, 1, dist, s);
+  if (st != SSSP_OK) return st;
+  return read_status(h, s);
+}
+
+sssp_status sssp_solve_multi_async(sssp_handle* h, const int32_t* sources, int32_t k, void* dist, void* stream) {
+  if (!h || !sources || k < 1 || !dist) return SSSP_ERR_INVALID_ARGUMENT;
+  SSSP_TRY(hipSetDevice(h->device));
+  return enqueue_solve(h, sources, k, 1, dist, static_cast<hipStream_t>(stream));
 }
 
 sssp_status sssp_solve_status(sssp_handle* h, void* stream) {
@@ -587,6 +619,7 @@ sssp_status sssp_set_weights(sssp_handle* h, const void* weights, void* stream) 
   p.edges = edges;
   h->perm = perm;
   h->wmax_bits = res[1];
+  p.no_heavy = no_heavy_for(h, h->wmax_bits);
   h->solved = false;  // distances of earlier solves used the old weights
   return upload_params(h);
 }

@@ -112,6 +112,7 @@ struct Params {
   uint32_t hub_cap;
   uint32_t inline_edges;  // steps with at most this many edges run on the leader workgroup alone
   uint32_t groups;        // workgroup groups of the launch, each solving its own sources
+  uint32_t no_heavy;      // every weight is <= delta: A_H is empty, no S and no heavy phases
   Ctl* ctl;               // this group's control block
   uint32_t* next_source;  // shared by every group: next source row to claim
 };
@@ -158,9 +159,11 @@ hipError_t launch_pack_rows(const uint32_t* off, const uint32_t* split, int64_t 
 hipError_t launch_ctl_reset(Ctl* c, uint32_t groups, int reset_epochs, unsigned long long* trace, uint32_t trace_cap,
                             hipStream_t s);
 hipError_t launch_fill(uint32_t* p, size_t count, uint32_t value, hipStream_t s);
-// `params` is a device array of one Params per group; grid must be a multiple of groups
+// `params` is a device array of one Params per group; grid must be a multiple of
+// groups. multi = 0: row r of dist holds the distances from sources[r]; multi =
+// 1: one row, the distances from the nearest of the k sources.
 hipError_t launch_solver(const Params* params, uint32_t groups, uint32_t wtype, const int32_t* sources, int k,
-                         uint32_t* dist, int grid, hipStream_t s);
+                         int multi, uint32_t* dist, int grid, hipStream_t s);
 
 // validation status bits
 enum : uint32_t {

@@ -346,7 +346,7 @@ __device__ void phase(const Params& p, uint32_t* t, const Sched& s, WgStats& st,
         deg = (kLight ? row.y : row.z) - beg;
       }
     }
-    if (kLight) {  // S = (S + t_Bi) > 0: each expanded vertex joins S once per round
+    if (kLight && !p.no_heavy) {  // S = (S + t_Bi) > 0: each expanded vertex joins S once per round
       bool to_s = false;
       if (take) {
         if (from_bin) {  // the first phase of a round: ring-slot entries are distinct and new to S
@@ -547,8 +547,12 @@ __device__ void choose_next(const Params& p, uint32_t from, uint32_t len) {
   __syncthreads();
 }
 
+// Start a solve: t = inf was set by every workgroup; t(s) = 0 for each seed
+// (Fig. 1 left, initialisation; with several seeds, d(v) is the distance from
+// the nearest one), and the seeds form B_0. Seeds outside [0, n) are reported
+// and skipped; repeated seeds are filed once.
 template <class W>
-__device__ void leader_start(const Params& p, uint32_t* t, uint32_t src) {
+__device__ void leader_start(const Params& p, uint32_t* t, const int32_t* seeds, int nseeds) {
   Ctl* c = p.ctl;
   if (threadIdx.x < kRingMax) st_agent(&c->bincount[threadIdx.x], 0u);
   if (threadIdx.x == 0) {
@@ -566,19 +570,26 @@ __device__ void leader_start(const Params& p, uint32_t* t, uint32_t src) {
     st_agent(&c->chunk_next, 0u);
     st_agent(&c->step, ld_agent(&c->step) + 1u);
     st_agent(&c->round, ld_agent(&c->round) + 1u);
-    // t = inf, t[s] = 0 (Fig. 1 left); the source is the only member of B_0
-    st_agent(&t[src], 0u);
-    st_agent(&p.bstamp[src], 0u);
-    st_agent(&p.bins[0], src);  // ring slot of bucket 0, first entry
+  }
+  drain_stores();
+  __syncthreads();
+  for (int i = threadIdx.x; i < nseeds; i += kWG) {
+    const int32_t src = seeds[i];
+    if (src < 0 || static_cast<uint32_t>(src) >= p.n) {
+      st_agent(&c->bad_source, 1u);
+      continue;
+    }
+    const uint32_t u = p.vid[src];
+    st_agent(&t[u], 0u);
+    if (atomicMin(&p.bstamp[u], 0u) != 0u) st_agent(&p.bins[atomicAdd(&c->bincount[0], 1u)], u);
   }
   drain_stores();
   __syncthreads();
   if (threadIdx.x == 0) {
-    st_agent(&c->bincount[0], 1u);
     set_bucket<W>(p, 0u);
     st_agent(&c->action, static_cast<uint32_t>(kActLight));
     st_agent(&c->in_kind, static_cast<uint32_t>(kInBin));
-    st_agent(&c->in_count, 1u);
+    st_agent(&c->in_count, ld_agent(&c->bincount[0]));
     st_agent(&c->out_buf, 0u);
     atomicAdd(&c->buckets, 1ull);
   }
@@ -613,6 +624,8 @@ __device__ void after_step(const Params& p, const Sched& s) {
           st_agent(&c->in_kind, s.out_buf);
           st_agent(&c->in_count, n_next);
           st_agent(&c->out_buf, 1u - s.out_buf);
+        } else if (p.no_heavy) {  // A_H is empty (every weight <= delta): the bucket is done
+          next = 1;
         } else {  // B_i is empty: one heavy phase over S
           st_agent(&c->action, static_cast<uint32_t>(kActHeavy));
           st_agent(&c->in_count, ld_agent(&c->scount));
@@ -693,13 +706,13 @@ __device__ void lead(const Params& p, uint32_t* t, Sched* s, WgStats& st, Stage&
   }
 }
 
-// The leader's part of the barrier that starts a source: claim the next source
-// row of the batch and initialise its solve (t(s) = 0, the source is the only
-// member of B_0), or mark the group finished.
+// The leader's part of the barrier that starts a solve: claim the next row of
+// the batch and initialise its solve, or mark the group finished. A row is one
+// source, or (multi) all k sources at once in a single row.
 template <class W>
-__device__ void leader_claim(const Params& p, uint32_t* t, const int32_t* sources, int k, bool reset_tags, Sched* s,
-                             WgStats& st, Stage& sg) {
-  __shared__ int32_t s_src;
+__device__ void leader_claim(const Params& p, uint32_t* t, const int32_t* sources, int k, int multi, bool reset_tags,
+                             Sched* s, WgStats& st, Stage& sg) {
+  __shared__ uint32_t s_row;
   Ctl* c = p.ctl;
   if (threadIdx.x == 0) {
     if (reset_tags) {  // the group's stamps were cleared before this barrier
@@ -708,28 +721,20 @@ __device__ void leader_claim(const Params& p, uint32_t* t, const int32_t* source
       st_agent(&c->far_epoch, 1u);
     }
     const uint32_t r = atomicAdd(p.next_source, 1u);
-    int32_t src = -1;
-    if (r < static_cast<uint32_t>(k)) {
-      src = sources[r];
-      if (src < 0 || static_cast<uint32_t>(src) >= p.n) {  // the row is left as all-unreachable
-        st_agent(&c->bad_source, 1u);
-        st_agent(&c->action, static_cast<uint32_t>(kActDone));
-        src = -1;
-      }
-    }
-    st_agent(&c->source_index, r < static_cast<uint32_t>(k) ? r : kNone);
-    s_src = src;
+    const uint32_t rows = multi ? 1u : static_cast<uint32_t>(k);
+    s_row = r < rows ? r : kNone;
+    st_agent(&c->source_index, s_row);
   }
   __syncthreads();
-  if (s_src >= 0) {
-    leader_start<W>(p, t, p.vid[s_src]);
-    lead<W>(p, t, s, st, sg, false);  // the first phases (around one vertex) are small
-  }
+  const uint32_t r = s_row;
+  if (r == kNone) return;
+  leader_start<W>(p, t, multi ? sources : sources + r, multi ? k : 1);
+  lead<W>(p, t, s, st, sg, false);  // the first phases (around the seeds) are usually small
 }
 
 template <class W>
 __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ params, uint32_t groups,
-                                                     const int32_t* sources, int k, uint32_t* dist) {
+                                                     const int32_t* sources, int k, int multi, uint32_t* dist) {
   __shared__ Sched s;
   __shared__ Stage sg;
   __shared__ uint32_t s_row;
@@ -759,7 +764,7 @@ __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ 
         st_agent(&p.fstamp[v], 0u);
       }
     }
-    alive = grid_sync(c, size, rank, [&] { leader_claim<W>(p, t, sources, k, reset_tags, &s, st, sg); });
+    alive = grid_sync(c, size, rank, [&] { leader_claim<W>(p, t, sources, k, multi, reset_tags, &s, st, sg); });
     if (threadIdx.x == 0) s_row = ld_agent(&c->source_index);
     __syncthreads();
     const uint32_t row = s_row;
@@ -860,14 +865,15 @@ hipError_t solver_occupancy(int wtype, int* blocks_per_cu) {
 // need). While the stream is being captured into a graph, the launch-attribute
 // form records a cooperative kernel node.
 hipError_t launch_solver(const Params* params, uint32_t groups, uint32_t wtype, const int32_t* sources, int k,
-                         uint32_t* dist, int grid, hipStream_t s) {
+                         int multi, uint32_t* dist, int grid, hipStream_t s) {
   if (groups < 1 || groups > kMaxGroups || grid < 1 || grid % static_cast<int>(groups) != 0) return hipErrorInvalidValue;
   const Params* pp = params;
   uint32_t gg = groups;
   const int32_t* src = sources;
   int kk = k;
+  int mm = multi;
   uint32_t* d = dist;
-  void* args[] = {&pp, &gg, &src, &kk, &d};
+  void* args[] = {&pp, &gg, &src, &kk, &mm, &d};
   const void* fn = wtype == 0 ? reinterpret_cast<const void*>(solver_kernel<WeightU32>)
                               : reinterpret_cast<const void*>(solver_kernel<WeightF32>);
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;

@@ -162,6 +162,19 @@ def er_pairs(rng: np.random.Generator, n: int, m: int) -> tuple[np.ndarray, np.n
     return keys // n, keys % n
 
 
+def er_pairs_sorted(rng: np.random.Generator, n: int, m: int) -> tuple[np.ndarray, np.ndarray]:
+    """Exactly m distinct ordered pairs (u, v), u != v, uniform, in row-major order: the
+    distinct values of m draws, topped up by fresh draws until there are m."""
+    if m > n * (n - 1):
+        raise ValueError("too many edges for a simple directed graph")
+    keys = np.zeros(0, dtype=np.int64)
+    while keys.size < m:
+        draw = rng.integers(0, n * n, size=m - keys.size, dtype=np.int64)
+        draw = draw[(draw // n) != (draw % n)]
+        keys = np.union1d(keys, draw)
+    return keys // n, keys % n
+
+
 def er_graph(n: int, m: int, *, cfg: int, weights: str = "u32", wlo=1, whi=100, name: str = "") -> Graph:
     rs, rw = rng_for(cfg, S_STRUCT), rng_for(cfg, S_WEIGHT)
     src, dst = er_pairs(rs, n, m)
@@ -251,10 +264,25 @@ def ragged_er_batch(count: int, *, cfg: int, nlo=1_000, nhi=100_000, avg_deg=8, 
     out = []
     for gi, n in enumerate(sizes):
         n = int(n)
-        s, d = er_pairs(rs, n, avg_deg * n)
+        s, d = er_pairs_sorted(rs, n, avg_deg * n)
         w = _draw_weights(rw, s.size, weights, wlo, whi)
-        out.append(csr_from_edges(n, s, d, w, name=f"ragged{gi}_n{n}"))
+        row_ptr = np.zeros(n + 1, dtype=np.int64)
+        np.cumsum(np.bincount(s, minlength=n), out=row_ptr[1:])
+        out.append(Graph(n=n, row_ptr=row_ptr, col=d.astype(np.int32), w=w, name=f"ragged{gi}_n{n}"))
     return out
+
+
+def block_union(graphs: list[Graph], name: str = "") -> tuple[Graph, np.ndarray]:
+    """The disjoint union of graphs (block-diagonal adjacency matrix) and the first
+    vertex of each block (offsets [len(graphs) + 1])."""
+    offs = np.zeros(len(graphs) + 1, dtype=np.int64)
+    np.cumsum([g.n for g in graphs], out=offs[1:])
+    eoffs = np.zeros(len(graphs) + 1, dtype=np.int64)
+    np.cumsum([g.m for g in graphs], out=eoffs[1:])
+    row_ptr = np.concatenate([g.row_ptr[:-1] + eoffs[i] for i, g in enumerate(graphs)] + [eoffs[-1:]])
+    col = np.concatenate([g.col.astype(np.int64) + offs[i] for i, g in enumerate(graphs)]).astype(np.int32)
+    w = np.concatenate([g.w for g in graphs])
+    return Graph(n=int(offs[-1]), row_ptr=row_ptr, col=col, w=w, name=name or f"union{len(graphs)}"), offs
 
 
 def sources_with_outedges(g: Graph, k: int, *, cfg: int) -> np.ndarray:

@@ -26,9 +26,9 @@ SSSP_ERR_UNSUPPORTED = 7
 SSSP_WEIGHT_U32 = 0
 SSSP_WEIGHT_F32 = 1
 
-EXPORTS = ("sssp_create", "sssp_solve", "sssp_solve_async", "sssp_solve_status", "sssp_backward", "sssp_set_weights",
-           "sssp_last_stats", "sssp_set_tuning", "sssp_set_trace", "sssp_graph_info", "sssp_destroy",
-           "sssp_status_string")
+EXPORTS = ("sssp_create", "sssp_solve", "sssp_solve_async", "sssp_solve_multi", "sssp_solve_multi_async",
+           "sssp_solve_status", "sssp_backward", "sssp_set_weights", "sssp_last_stats", "sssp_set_tuning",
+           "sssp_set_trace", "sssp_graph_info", "sssp_destroy", "sssp_status_string")
 
 
 class SsspGraph(ctypes.Structure):
@@ -71,6 +71,10 @@ def load_library(path: str = LIBRARY) -> ctypes.CDLL:
     lib.sssp_solve.restype = ctypes.c_int
     lib.sssp_solve_async.argtypes = [P, P, ctypes.c_int32, P, P]
     lib.sssp_solve_async.restype = ctypes.c_int
+    lib.sssp_solve_multi.argtypes = [P, P, ctypes.c_int32, P, P]
+    lib.sssp_solve_multi.restype = ctypes.c_int
+    lib.sssp_solve_multi_async.argtypes = [P, P, ctypes.c_int32, P, P]
+    lib.sssp_solve_multi_async.restype = ctypes.c_int
     lib.sssp_solve_status.argtypes = [P, P]
     lib.sssp_solve_status.restype = ctypes.c_int
     lib.sssp_backward.argtypes = [P, P, ctypes.c_int32, P, P, P, P]
@@ -169,6 +173,30 @@ def sssp_solve_async(handle, sources, dist, stream=None) -> None:
     _check_rows(handle, dist, k)
     _check(load_library().sssp_solve_async(handle, ctypes.c_void_p(sources.data_ptr()), k,
                                            ctypes.c_void_p(dist.data_ptr()), _stream(stream)), "sssp_solve_async")
+
+
+def sssp_solve_multi(handle, sources, dist, stream=None) -> None:
+    """Distances from the nearest of the host sources into dist (GPU [n] of the weight type)."""
+    src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32).reshape(-1))
+    if not dist.is_cuda or not dist.is_contiguous():
+        raise ValueError("dist must be a contiguous GPU tensor")
+    _check_rows(handle, dist, 1)
+    _check(load_library().sssp_solve_multi(handle, src.ctypes.data_as(ctypes.c_void_p), int(src.size),
+                                           ctypes.c_void_p(dist.data_ptr()), _stream(stream)), "sssp_solve_multi")
+
+
+def sssp_solve_multi_async(handle, sources, dist, stream=None) -> None:
+    """Enqueue only: sources a GPU int32 tensor [k], dist a GPU tensor [n]."""
+    import torch
+
+    if not sources.is_cuda or sources.dtype != torch.int32 or not sources.is_contiguous():
+        raise ValueError("sources must be a contiguous int32 GPU tensor")
+    if not dist.is_cuda or not dist.is_contiguous():
+        raise ValueError("dist must be a contiguous GPU tensor")
+    _check_rows(handle, dist, 1)
+    _check(load_library().sssp_solve_multi_async(handle, ctypes.c_void_p(sources.data_ptr()), int(sources.numel()),
+                                                 ctypes.c_void_p(dist.data_ptr()), _stream(stream)),
+           "sssp_solve_multi_async")
 
 
 def sssp_solve_status(handle, stream=None) -> None:
@@ -270,6 +298,13 @@ class DeltaStepping:
         if out is None:
             out = self.torch.empty((src.size, self.n), dtype=self.out_dtype, device=self.device)
         sssp_solve(self.handle, src, out)
+        return out
+
+    def solve_multi(self, sources, out=None):
+        """Distances from the nearest source (GPU tensor [n])."""
+        if out is None:
+            out = self.torch.empty(self.n, dtype=self.out_dtype, device=self.device)
+        sssp_solve_multi(self.handle, sources, out)
         return out
 
     def solve_numpy(self, sources) -> np.ndarray:

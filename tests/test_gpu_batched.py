@@ -157,3 +157,102 @@ def test_graph_capture_replays(groups):
     finally:
         torch.cuda.synchronize()
         solver.close()
+
+
+@pytest.mark.parametrize("kind", ["u32", "f32_unit"])
+def test_multi_source_is_min_over_sources(kind):
+    """sssp_solve_multi: d(v) = min over the sources of d_s(v) (repeated sources allowed)."""
+    if kind == "u32":
+        g, delta = G.rmat_graph(12, 8, cfg=66, weights="u32", wlo=1, whi=64), 16
+    else:
+        g, delta = G.rmat_graph(12, 8, cfg=67, weights="f32_unit"), 2.0 ** -4
+    srcs = np.concatenate([G.sources_with_outedges(g, 7, cfg=66), [0, 0]]).astype(np.int32)
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, delta)
+    try:
+        got = solver.solve_multi(srcs).cpu().numpy()
+        assert solver.stats()["sources"] == 1
+    finally:
+        solver.close()
+    rows = np.stack([oracle.dijkstra(g, int(s))[0] for s in srcs])
+    want = rows.min(axis=0)
+    assert same_bits(got.view(want.dtype), want)
+
+
+def _check_blocks(graphs, offs, dist, exact_blocks):
+    """Each block's slice of the union's distances against its own graph's oracle."""
+    for i, gi in enumerate(graphs):
+        seg = dist[offs[i]:offs[i + 1]]
+        if i in exact_blocks:
+            want, rc = oracle.dijkstra(gi, 0)
+            assert rc == oracle.OK and same_bits(seg, want), f"block {i} (n={gi.n}) differs from Dijkstra"
+        else:
+            assert oracle.certify(gi, 0, seg) == oracle.CERT_OK, f"block {i} (n={gi.n}) not certified"
+
+
+def test_ragged_batch_small():
+    """64 ER graphs (n log-uniform in [1e3, 1e4], degree 8, fp32 weights in (0, 1]) as one
+    block-diagonal graph, one source per block, one multi-source solve."""
+    graphs = G.ragged_er_batch(64, cfg=68, nlo=1_000, nhi=10_000)
+    u, offs = G.block_union(graphs)
+    solver = sssp.DeltaStepping(u.row_ptr, u.col, u.w, 0.125)
+    try:
+        dist = solver.solve_multi(offs[:-1].astype(np.int32)).cpu().numpy()
+    finally:
+        solver.close()
+    _check_blocks(graphs, offs, dist, exact_blocks=set(range(64)))
+
+
+def test_c4b_configuration():
+    """512 ER graphs, n log-uniform in [1e3, 1e5], degree 8, fp32 weights in (0, 1]: the union
+    solved from the first vertex of every block at once, captured in a graph and replayed."""
+    print("[batched] C4b ragged_er512", flush=True)
+    graphs = G.ragged_er_batch(512, cfg=42)
+    u, offs = G.block_union(graphs)
+    solver = sssp.DeltaStepping(u.row_ptr, u.col, u.w, 0.125)
+    try:
+        src = torch.from_numpy(offs[:-1].astype(np.int32)).cuda()
+        dist = torch.empty(u.n, dtype=torch.float32, device="cuda")
+        stream = torch.cuda.Stream()
+        stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(stream):
+            sssp.sssp_solve_multi_async(solver.handle, src, dist, stream)
+        sssp.sssp_solve_status(solver.handle, stream)
+        first = dist.cpu().numpy()
+        torch.cuda.current_stream().wait_stream(stream)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            sssp.sssp_solve_multi_async(solver.handle, src, dist, stream)
+        for _ in range(2):
+            dist.fill_(0.0)
+            graph.replay()
+            torch.cuda.synchronize()
+            sssp.sssp_solve_status(solver.handle, torch.cuda.current_stream())
+            assert same_bits(dist.cpu().numpy(), first)
+        del graph
+    finally:
+        torch.cuda.synchronize()
+        solver.close()
+    _check_blocks(graphs, offs, first, exact_blocks=set(range(0, 512, 37)))
+
+
+def test_bfs_mode_unit_weights():
+    """Undirected unit weights with delta = 1 (the paper's own experimental setting):
+    distances are BFS hop counts, every edge is light, one light phase per bucket."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import shortest_path
+
+    g = G.symmetrize(G.rmat_graph(14, 8, cfg=69, weights="u32", wlo=1, whi=1))
+    src = int(G.sources_with_outedges(g, 1, cfg=69)[0])
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, 1)
+    try:
+        got = solver.solve_numpy([src])[0]
+        st = solver.stats()
+    finally:
+        solver.close()
+    a = sp.csr_matrix((np.ones(g.m), g.col, g.row_ptr), shape=(g.n, g.n))
+    hops = shortest_path(a, method="D", unweighted=True, indices=src)
+    want = np.where(np.isfinite(hops), hops, 2.0 ** 32 - 1).astype(np.uint32)
+    assert np.array_equal(got, want)
+    assert st["heavy_phases"] == 0 and st["heavy_edges"] == 0
+    assert st["light_phases"] == st["buckets"]  # the level of bucket i only reaches bucket i + 1
+    assert st["buckets"] == int(hops[np.isfinite(hops)].max()) + 1
