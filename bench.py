@@ -11,6 +11,17 @@ graph already resident, every bucket, light and heavy phase of every source).
 Inputs are resident in HBM before the timed region. Throughput is GTEPS =
 sum over sources of m_reached / time, m_reached = out-edges of reached vertices.
 
+Beside the plain solve the line reports the batched and backward modes on the
+same GPU ("modes"), each from the library's autotuner and timed with HIP events:
+  batched_rmat_s18_k256  R-MAT scale 18, fp32 log-uniform [1e-2, 1e2] weights, 256 sources:
+                         concurrent sources in one cooperative launch replayed from a HIP
+                         graph, against 256 looped single-source launches
+  batched_ragged_er512   512 ER graphs (n log-uniform in [1e3, 1e5], degree 8, fp32 (0, 1])
+                         as one block-diagonal graph, one source per block, solved at once
+                         (nearest-source solve) from a HIP graph, against 512 per-graph solves
+  backward_rmat_s18      R-MAT scale 18, fp32 [1, 2) weights, 16 sources, loss over 1024
+                         targets: forward GTEPS and backward GTEPS = k * m / t_backward
+
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -89,20 +100,24 @@ def algorithmic_bytes(g, dist_rows: np.ndarray, improvements: int) -> float:
 
 def reached_edges(g, dist_rows: np.ndarray) -> int:
     outdeg = g.outdeg()
-    return int(sum(int(outdeg[row != np.uint32(0xFFFFFFFF)].sum()) for row in dist_rows))
+    inf = np.uint32(0xFFFFFFFF) if dist_rows.dtype == np.uint32 else np.float32(np.inf)
+    return int(sum(int(outdeg[row != inf].sum()) for row in dist_rows))
 
 
-def cpu_baseline(g, sources, budget_s: float):
-    """The CPU oracle (binary-heap Dijkstra, one core) on a bounded sample of the sources."""
+def cpu_baseline(g, sources, budget_s: float, gpu_rows: np.ndarray):
+    """The CPU oracle (binary-heap Dijkstra, one core) on a bounded sample of the sources. The
+    rows it computes are also compared with the GPU rows of the same sources (bit for bit)."""
     import oracle
 
     done, edges, t_total = 0, 0, 0.0
-    for s in sources:
+    for r, s in enumerate(sources):
         t0 = time.perf_counter()
         d, rc = oracle.dijkstra(g, int(s))
         dt = time.perf_counter() - t0
         if rc != oracle.OK:
             raise RuntimeError("oracle failed")
+        if not np.array_equal(gpu_rows[r].view(np.uint32), d.view(np.uint32)):
+            raise SystemExit(f"bench: GPU distances from source {s} differ from the oracle")
         t_total += dt
         edges += oracle.reached_edges(g, d)
         done += 1
@@ -110,7 +125,159 @@ def cpu_baseline(g, sources, budget_s: float):
             break
     return {"value": edges / t_total / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
             "sample": f"{done} of {len(sources)} sources, binary-heap Dijkstra, single thread, "
-                      f"{t_total:.1f} s"}
+                      f"{t_total:.1f} s (each row also matched the GPU row bit for bit)"}, done
+
+
+def timed_ms(fn, reps: int = 1) -> float:
+    """Mean device milliseconds of fn() on the current stream over reps calls, after one warm-up."""
+    import torch
+
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def device_graph(g, dev):
+    import torch
+
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    ci = torch.from_numpy(g.col).to(dev)
+    wt = torch.from_numpy(g.w.view(np.int32) if g.w.dtype == np.uint32 else g.w).to(dev)
+    return rp, ci, wt
+
+
+def captured(fn):
+    """fn recorded into a HIP graph by stream capture; returns the replay callable."""
+    import torch
+
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        fn(stream)
+    torch.cuda.current_stream().wait_stream(stream)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        fn(stream)
+    return graph
+
+
+def mode_batched_s18(dev, steps: int) -> dict:
+    import torch
+
+    from paper_1911_06895_amd import graphs as G
+    from paper_1911_06895_amd import sssp
+
+    g = G.workload("rmat_s18_f32log")
+    srcs = G.sources_with_outedges(g, 256, cfg=41)
+    rp, ci, wt = device_graph(g, dev)
+    dist = torch.empty((len(srcs), g.n), dtype=torch.float32, device=dev)
+    h, tune = sssp.sssp_autotune(rp, ci, wt, srcs[:64], dist[:64])
+    src_dev = torch.from_numpy(srcs).to(dev)
+    graph = captured(lambda st: sssp.sssp_solve_async(h, src_dev, dist, st))
+    ms = timed_ms(graph.replay, reps=steps)
+    sssp.sssp_solve_status(h)
+    rows = dist.cpu().numpy()
+    m_r = reached_edges(g, rows)
+    sssp.sssp_destroy(h)
+    # looped plain solves: one single-source launch per source, delta tuned for that on 16 sources
+    one = dist[:1]
+    best = None
+    for delta in (0.5, 1.0, 2.0, 4.0, 8.0, 16.0):
+        hd = sssp.sssp_create(rp, ci, wt, delta)
+        t = timed_ms(lambda: [sssp.sssp_solve_async(hd, src_dev[r:r + 1], one) for r in range(16)])
+        sssp.sssp_solve_status(hd)
+        if best is None or t < best[1]:
+            if best is not None:
+                sssp.sssp_destroy(best[0])
+            best = (hd, t, delta)
+        else:
+            sssp.sssp_destroy(hd)
+    hl, _, dl = best
+    outs = [dist[r:r + 1] for r in range(len(srcs))]
+    ms_loop = timed_ms(lambda: [sssp.sssp_solve_async(hl, src_dev[r:r + 1], outs[r]) for r in range(len(srcs))])
+    sssp.sssp_solve_status(hl)
+    sssp.sssp_destroy(hl)
+    if not np.array_equal(dist.cpu().numpy().view(np.uint32), rows.view(np.uint32)):
+        raise SystemExit("bench: batched and looped solves disagree")
+    return {"workload": "R-MAT scale 18 edge factor 16, fp32 log-uniform [1e-2,1e2], 256 sources",
+            "n": g.n, "m": g.m, "m_reached": m_r, "delta": tune["delta"],
+            "concurrent_sources": tune["concurrent_sources"], "autotune_trials": tune["trials"],
+            "ms": round(ms, 3), "gteps": round(m_r / ms / 1e6, 3),
+            "looped": {"delta": dl, "ms": round(ms_loop, 3), "gteps": round(m_r / ms_loop / 1e6, 3)},
+            "speedup_vs_looped": round(ms_loop / ms, 2), "hip_graph": True}
+
+
+def mode_batched_ragged(dev, steps: int) -> dict:
+    import torch
+
+    from paper_1911_06895_amd import graphs as G
+    from paper_1911_06895_amd import sssp
+
+    graphs = G.ragged_er_batch(512, cfg=42)
+    u, offs = G.block_union(graphs)
+    rp, ci, wt = device_graph(u, dev)
+    dist = torch.empty(u.n, dtype=torch.float32, device=dev)
+    starts = offs[:-1].astype(np.int32)
+    h, tune = sssp.sssp_autotune(rp, ci, wt, starts, dist, multi=True)
+    src_dev = torch.from_numpy(starts).to(dev)
+    graph = captured(lambda st: sssp.sssp_solve_multi_async(h, src_dev, dist, st))
+    ms = timed_ms(graph.replay, reps=steps)
+    sssp.sssp_solve_status(h)
+    d = dist.cpu().numpy()
+    m_r = int(u.outdeg()[np.isfinite(d)].sum())
+    sssp.sssp_destroy(h)
+    # looped plain solves: one handle and one single-source launch per graph, same delta
+    handles, outs = [], []
+    zero = torch.zeros(1, dtype=torch.int32, device=dev)
+    for gi in graphs:
+        handles.append(sssp.sssp_create(*device_graph(gi, dev), tune["delta"]))
+        outs.append(torch.empty(gi.n, dtype=torch.float32, device=dev))
+    ms_loop = timed_ms(lambda: [sssp.sssp_solve_async(hh, zero, o) for hh, o in zip(handles, outs)])
+    for hh in handles:
+        sssp.sssp_solve_status(hh)
+        sssp.sssp_destroy(hh)
+    if not np.array_equal(np.concatenate([o.cpu().numpy() for o in outs]).view(np.uint32), d.view(np.uint32)):
+        raise SystemExit("bench: batched and per-graph solves disagree")
+    return {"workload": "512 directed ER graphs, n log-uniform [1e3,1e5], m = 8n, fp32 (0,1], source 0 of each",
+            "n": u.n, "m": u.m, "m_reached": m_r, "delta": tune["delta"], "autotune_trials": tune["trials"],
+            "ms": round(ms, 3), "gteps": round(m_r / ms / 1e6, 3),
+            "looped": {"delta": tune["delta"], "ms": round(ms_loop, 3), "gteps": round(m_r / ms_loop / 1e6, 3)},
+            "speedup_vs_looped": round(ms_loop / ms, 2), "hip_graph": True}
+
+
+def mode_backward(dev, steps: int) -> dict:
+    import torch
+
+    from paper_1911_06895_amd import graphs as G
+    from paper_1911_06895_amd import sssp
+
+    g = G.workload("rmat_s18_f32onetwo")
+    srcs = G.sources_with_outedges(g, 16, cfg=5)
+    targets, coef = G.targets_and_coefs(g.n, 1024, cfg=5)
+    rp, ci, wt = device_graph(g, dev)
+    dist = torch.empty((len(srcs), g.n), dtype=torch.float32, device=dev)
+    h, tune = sssp.sssp_autotune(rp, ci, wt, srcs, dist)
+    grad_rows = np.zeros((len(srcs), g.n), dtype=np.float32)
+    grad_rows[:, targets] = coef
+    gd = torch.from_numpy(grad_rows).to(dev)
+    gw = torch.empty(g.m, dtype=torch.float32, device=dev)
+    ms_f = timed_ms(lambda: sssp.sssp_solve(h, srcs, dist), reps=steps)
+    ms_b = timed_ms(lambda: sssp.sssp_backward(h, srcs, dist, gd, gw), reps=steps)
+    d = dist.cpu().numpy()
+    m_r = reached_edges(g, d)
+    sssp.sssp_destroy(h)
+    return {"workload": "R-MAT scale 18 edge factor 16, fp32 [1,2), 16 sources, 1024 targets, c ~ N(0,1)",
+            "n": g.n, "m": g.m, "m_reached": m_r, "delta": tune["delta"],
+            "concurrent_sources": tune["concurrent_sources"],
+            "forward_ms": round(ms_f, 3), "forward_gteps": round(m_r / ms_f / 1e6, 3),
+            "backward_ms": round(ms_b, 3), "backward_gteps": round(len(srcs) * g.m / ms_b / 1e6, 3)}
 
 
 def main():
@@ -123,7 +290,7 @@ def main():
     ap.add_argument("--deltas", default="8,16,32,64,128")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--check", type=int, default=2, help="sources checked against the oracle after timing")
+    ap.add_argument("--no-modes", action="store_true", help="only the plain R-MAT scale 22 solve")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of this many GiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -215,21 +382,17 @@ def main():
     log(f"[bench] timed: delta={delta:g} {args.steps} steps, {ms_step:.2f} ms/step (wall {t_wall / args.steps * 1e3:.2f}),"
         f" {value:.2f} GTEPS, algorithmic {achieved:.1f} GB/s")
 
-    # correctness of what was timed: sampled sources against the oracle
-    checked = 0
-    if args.check > 0:
-        import oracle
+    modes = {}
+    if not args.no_modes:
+        for name, fn in (("batched_rmat_s18_k256", mode_batched_s18), ("batched_ragged_er512", mode_batched_ragged),
+                         ("backward_rmat_s18", mode_backward)):
+            t0 = time.perf_counter()
+            modes[name] = fn(dev, max(1, args.steps))
+            log(f"[bench] {name}: {modes[name]} ({time.perf_counter() - t0:.1f}s)")
 
-        for r in range(min(args.check, len(sources))):
-            want, rc = oracle.dijkstra(g, int(sources[r]))
-            if rc != oracle.OK or not np.array_equal(rows[r].view(want.dtype), want):
-                raise SystemExit(f"bench: GPU result for source {sources[r]} differs from the oracle")
-            checked += 1
-        log(f"[bench] {checked} sources bit-exact against the oracle")
-
-    cpu = None
+    cpu, checked = None, 0
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(g, sources, args.cpu_budget)
+        cpu, checked = cpu_baseline(g, sources, args.cpu_budget, rows)
         log(f"[bench] cpu baseline: {cpu}")
 
     out = {
@@ -253,6 +416,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": measured_traffic(f"{args.workload}:k{len(sources)}:delta{delta:g}")},
         "cpu_baseline": cpu,
+        "modes": modes,
     }
     print(json.dumps(out), flush=True)
     sssp.sssp_destroy(handle)

@@ -241,6 +241,37 @@ sssp_status sssp_set_tuning(sssp_handle *h, const sssp_tuning *t);
  */
 sssp_status sssp_set_trace(sssp_handle *h, uint64_t *device_buffer, int64_t capacity);
 
+/* Outcome of sssp_autotune. */
+typedef struct {
+  double delta;               /* the chosen delta */
+  int32_t concurrent_sources; /* the chosen number of concurrent groups */
+  int32_t trials;             /* (delta, group count) pairs timed */
+  float ms;                   /* device time of one solve of the sample with the chosen pair */
+} sssp_autotune_result;
+
+/*
+ * sssp_autotune -- create a handle whose delta and concurrent-source count are
+ *   the fastest found for a sample of sources. delta is the method's only
+ *   parameter (bucket width and light/heavy threshold, Sec. III-A and IV-A): a
+ *   small delta means many buckets with small phases, a large one means light
+ *   edges relaxed more than once. For each candidate delta the graph is split
+ *   (as sssp_create) and the sample solved with 1, 8, 16, ... concurrent groups
+ *   (up to k; the search over group counts stops when the time rises), one
+ *   warm-up and one timed solve per pair.
+ *   g: as for sssp_create.  sources: HOST int32 [k], each in [0, n).
+ *   mode: 0 = one row per source (sssp_solve), 1 = nearest-source distances
+ *   (sssp_solve_multi; one group).  deltas: HOST [n_deltas] candidates, or NULL
+ *   and 0 for powers of two around the mean weight (integers >= 1 for uint32
+ *   weights).  dist: DEVICE scratch of the solves ([k][n] for mode 0, [n] for
+ *   mode 1), overwritten.  out: receives the handle (tuned; free with
+ *   sssp_destroy).  result: HOST, may be NULL.  Synchronises the stream.
+ *   Errors: INVALID_ARGUMENT, INVALID_WEIGHT, OUT_OF_MEMORY, DEVICE, and the
+ *   last error of a candidate when no candidate could be timed.
+ */
+sssp_status sssp_autotune(const sssp_graph *g, const int32_t *sources, int32_t k, int32_t mode,
+                          const double *deltas, int32_t n_deltas, void *dist, void *stream, sssp_handle **out,
+                          sssp_autotune_result *result);
+
 /* Vertex and edge counts and the weight type of a handle (host out-pointers, any may be NULL). */
 sssp_status sssp_graph_info(const sssp_handle *h, int64_t *n, int64_t *m, int32_t *wtype);
 

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIBRARY = os.path.join(PKG, "libsssp.so")
-SOURCES = ["sssp_build.hip", "sssp_kernels.hip", "sssp_adjoint.hip", "sssp_api.hip"]
+SOURCES = ["sssp_build.hip", "sssp_kernels.hip", "sssp_adjoint.hip", "sssp_api.hip", "sssp_autotune.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -28,7 +28,7 @@ SSSP_WEIGHT_F32 = 1
 
 EXPORTS = ("sssp_create", "sssp_solve", "sssp_solve_async", "sssp_solve_multi", "sssp_solve_multi_async",
            "sssp_solve_status", "sssp_backward", "sssp_set_weights", "sssp_last_stats", "sssp_set_tuning",
-           "sssp_set_trace", "sssp_graph_info", "sssp_destroy", "sssp_status_string")
+           "sssp_set_trace", "sssp_graph_info", "sssp_destroy", "sssp_status_string", "sssp_autotune")
 
 
 class SsspGraph(ctypes.Structure):
@@ -45,6 +45,11 @@ class SsspStats(ctypes.Structure):
 class SsspTuning(ctypes.Structure):
     _fields_ = [("workgroups_per_cu", ctypes.c_int32), ("ring_buckets", ctypes.c_int32),
                 ("inline_edges", ctypes.c_int32), ("concurrent_sources", ctypes.c_int32)]
+
+
+class SsspAutotuneResult(ctypes.Structure):
+    _fields_ = [("delta", ctypes.c_double), ("concurrent_sources", ctypes.c_int32), ("trials", ctypes.c_int32),
+                ("ms", ctypes.c_float)]
 
 
 class SsspError(RuntimeError):
@@ -92,6 +97,9 @@ def load_library(path: str = LIBRARY) -> ctypes.CDLL:
     lib.sssp_graph_info.restype = ctypes.c_int
     lib.sssp_destroy.argtypes = [P]
     lib.sssp_destroy.restype = None
+    lib.sssp_autotune.argtypes = [ctypes.POINTER(SsspGraph), P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, P,
+                                  P, ctypes.POINTER(P), ctypes.POINTER(SsspAutotuneResult)]
+    lib.sssp_autotune.restype = ctypes.c_int
     lib.sssp_status_string.argtypes = [ctypes.c_int]
     lib.sssp_status_string.restype = ctypes.c_char_p
     _lib = lib
@@ -117,8 +125,7 @@ def sssp_status_string(status: int) -> str:
     return load_library().sssp_status_string(int(status)).decode()
 
 
-def sssp_create(row_ptr, col_idx, weights, delta: float, stream=None) -> ctypes.c_void_p:
-    """row_ptr int64 [n+1], col_idx int32 [m], weights uint32|float32 [m]: torch tensors on the GPU."""
+def _graph(row_ptr, col_idx, weights) -> SsspGraph:
     import torch
 
     if weights.dtype == torch.int32 or weights.dtype == torch.uint32:
@@ -136,12 +143,37 @@ def sssp_create(row_ptr, col_idx, weights, delta: float, stream=None) -> ctypes.
     m = col_idx.numel()
     if weights.numel() != m:
         raise ValueError("weights and col_idx differ in length")
-    g = SsspGraph(n=n, m=m, row_ptr=row_ptr.data_ptr(), col_idx=col_idx.data_ptr() if m else None,
-                  weights=weights.data_ptr() if m else None, wtype=wtype)
+    return SsspGraph(n=n, m=m, row_ptr=row_ptr.data_ptr(), col_idx=col_idx.data_ptr() if m else None,
+                     weights=weights.data_ptr() if m else None, wtype=wtype)
+
+
+def sssp_create(row_ptr, col_idx, weights, delta: float, stream=None) -> ctypes.c_void_p:
+    """row_ptr int64 [n+1], col_idx int32 [m], weights uint32|float32 [m]: torch tensors on the GPU."""
+    g = _graph(row_ptr, col_idx, weights)
     h = ctypes.c_void_p()
     _check(load_library().sssp_create(ctypes.byref(g), float(delta), _stream(stream), ctypes.byref(h)),
            "sssp_create")
     return h
+
+
+def sssp_autotune(row_ptr, col_idx, weights, sources, dist, multi: bool = False, deltas=None, stream=None):
+    """Handle with the fastest (delta, concurrent sources) for a sample of host sources; dist is GPU
+    scratch ([k, n], or [n] when multi). Returns (handle, result dict)."""
+    g = _graph(row_ptr, col_idx, weights)
+    src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32).reshape(-1))
+    if not dist.is_cuda or not dist.is_contiguous() or dist.element_size() != 4:
+        raise ValueError("dist must be a contiguous 4-byte GPU tensor")
+    if dist.numel() < (1 if multi else src.size) * g.n:
+        raise ValueError("dist is too small")
+    d = None if deltas is None else np.ascontiguousarray(np.asarray(deltas, dtype=np.float64))
+    h = ctypes.c_void_p()
+    res = SsspAutotuneResult()
+    _check(load_library().sssp_autotune(ctypes.byref(g), src.ctypes.data_as(ctypes.c_void_p), int(src.size),
+                                        1 if multi else 0,
+                                        d.ctypes.data_as(ctypes.c_void_p) if d is not None else None,
+                                        0 if d is None else int(d.size), ctypes.c_void_p(dist.data_ptr()),
+                                        _stream(stream), ctypes.byref(h), ctypes.byref(res)), "sssp_autotune")
+    return h, {name: getattr(res, name) for name, _ in SsspAutotuneResult._fields_}
 
 
 def _check_rows(handle, dist, k: int) -> None:

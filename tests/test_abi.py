@@ -59,6 +59,17 @@ def test_host_argument_checks_without_device():
     assert lib.sssp_solve(None, src, 1, 8, None) == sssp.SSSP_ERR_INVALID_ARGUMENT
     assert lib.sssp_solve_async(None, src, 1, 8, None) == sssp.SSSP_ERR_INVALID_ARGUMENT
     assert lib.sssp_solve_status(None, None) == sssp.SSSP_ERR_INVALID_ARGUMENT
+    assert lib.sssp_solve_multi(None, src, 1, 8, None) == sssp.SSSP_ERR_INVALID_ARGUMENT
+    assert lib.sssp_solve_multi_async(None, src, 1, 8, None) == sssp.SSSP_ERR_INVALID_ARGUMENT
+    res = sssp.SsspAutotuneResult()
+    assert lib.sssp_autotune(None, src, 1, 0, None, 0, 8, None, ctypes.byref(h), ctypes.byref(res)) == \
+        sssp.SSSP_ERR_INVALID_ARGUMENT
+    g = sssp.SsspGraph(n=4, m=0, row_ptr=8, col_idx=None, weights=None, wtype=0)
+    bad = (ctypes.c_int32 * 1)(4)  # source outside [0, n): rejected on the host
+    assert lib.sssp_autotune(ctypes.byref(g), bad, 1, 0, None, 0, 8, None, ctypes.byref(h), None) == \
+        sssp.SSSP_ERR_INVALID_ARGUMENT
+    assert lib.sssp_autotune(ctypes.byref(g), src, 1, 2, None, 0, 8, None, ctypes.byref(h), None) == \
+        sssp.SSSP_ERR_INVALID_ARGUMENT
     assert lib.sssp_set_tuning(None, ctypes.byref(sssp.SsspTuning())) == sssp.SSSP_ERR_INVALID_ARGUMENT
     st = sssp.SsspStats()
     assert lib.sssp_last_stats(None, ctypes.byref(st)) == sssp.SSSP_ERR_INVALID_ARGUMENT

@@ -256,3 +256,32 @@ def test_bfs_mode_unit_weights():
     assert st["heavy_phases"] == 0 and st["heavy_edges"] == 0
     assert st["light_phases"] == st["buckets"]  # the level of bucket i only reaches bucket i + 1
     assert st["buckets"] == int(hops[np.isfinite(hops)].max()) + 1
+
+
+def test_autotune_returns_a_correct_tuned_handle():
+    g = G.rmat_graph(13, 16, cfg=70, weights="f32_loguniform", wlo=1e-2, whi=1e2)
+    srcs = G.sources_with_outedges(g, 32, cfg=70)
+    rp, ci = torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(g.col).cuda()
+    wt = torch.from_numpy(g.w).cuda()
+    scratch = torch.empty((len(srcs), g.n), dtype=torch.float32, device="cuda")
+    h, res = sssp.sssp_autotune(rp, ci, wt, srcs, scratch)
+    try:
+        assert res["trials"] >= 2 and res["ms"] > 0
+        mean = float(g.w.astype(np.float64).mean())
+        assert mean / 64 <= res["delta"] <= mean * 8 and np.log2(res["delta"]).is_integer()
+        assert res["concurrent_sources"] in (1, 8, 16, 32)
+        dist = torch.empty((4, g.n), dtype=torch.float32, device="cuda")
+        sssp.sssp_solve(h, srcs[:4], dist)
+        check_rows(g, srcs[:4], dist.cpu().numpy(), exact_rows=4)
+    finally:
+        sssp.sssp_destroy(h)
+    # nearest-source mode with explicit candidates
+    h, res = sssp.sssp_autotune(rp, ci, wt, srcs[:3], scratch[0], multi=True, deltas=[0.5, 2.0])
+    try:
+        assert res["delta"] in (0.5, 2.0) and res["concurrent_sources"] == 1 and res["trials"] == 2
+        d = torch.empty(g.n, dtype=torch.float32, device="cuda")
+        sssp.sssp_solve_multi(h, srcs[:3], d)
+        want = np.stack([oracle.dijkstra(g, int(s))[0] for s in srcs[:3]]).min(axis=0)
+        assert same_bits(d.cpu().numpy(), want)
+    finally:
+        sssp.sssp_destroy(h)
