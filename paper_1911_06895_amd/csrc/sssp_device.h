@@ -9,13 +9,50 @@ namespace {
 
 // ------------------------------------------------------------------ helpers
 
+// Every pointer the kernels dereference here points to device (global) memory:
+// accesses through these views compile to global_* instructions rather than
+// flat ones (no LDS-aperture check, and no LDS wait counter to drain).
+template <typename T>
+__device__ inline __attribute__((address_space(1))) T* gp(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ inline const __attribute__((address_space(1))) T* gp(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
+// plain (cached) load
+template <typename T>
+__device__ inline T ldg(const T* p) {
+  return *gp(p);
+}
+
+__device__ inline uint4 ldg(const uint4* p) {
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  const v4u v = *(const __attribute__((address_space(1))) v4u*)p;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// device-scope (coherent across the XCDs) load, store and atomics
 template <typename T>
 __device__ inline T ld_agent(const T* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gp(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <typename T>
 __device__ inline void st_agent(T* p, T v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T, typename U>
+__device__ inline T g_add(T* p, U v) {
+  return __hip_atomic_fetch_add(gp(p), static_cast<T>(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T, typename U>
+__device__ inline T g_min(T* p, U v) {
+  return __hip_atomic_fetch_min(gp(p), static_cast<T>(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T, typename U>
+__device__ inline T g_exch(T* p, U v) {
+  return __hip_atomic_exchange(gp(p), static_cast<T>(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // number of set bits of `mask` in lanes below this one
@@ -34,7 +71,7 @@ __device__ inline void push_wave(uint32_t* list, uint32_t* count, bool pred, uin
   if (mask == 0) return;
   const int leader = first_lane(mask);
   uint32_t base = 0;
-  if (static_cast<int>(lane()) == leader) base = atomicAdd(count, static_cast<uint32_t>(__popcll(mask)));
+  if (static_cast<int>(lane()) == leader) base = g_add(count, static_cast<uint32_t>(__popcll(mask)));
   base = __shfl(base, leader);
   if (pred) st_agent(&list[base + lanes_below(mask)], v);
 }
@@ -115,15 +152,15 @@ __device__ inline void drain_stores() {
 
 __device__ inline void record_trace(Ctl* c, uint32_t flags) {
   if (!c->trace) return;
-  const uint32_t idx = atomicAdd(&c->trace_len, 1u);
+  const uint32_t idx = g_add(&c->trace_len, 1u);
   if (idx < c->trace_cap) {
     const unsigned long long what = static_cast<unsigned long long>(ld_agent(&c->in_count)) << 32 |
                                     static_cast<unsigned long long>(ld_agent(&c->bucket) & 0xFFFFFFu) << 8 |
                                     (ld_agent(&c->action) | flags);
     st_agent(&c->trace[4 * idx], static_cast<unsigned long long>(wall_clock64()));
     st_agent(&c->trace[4 * idx + 1], what);
-    st_agent(&c->trace[4 * idx + 2], __hip_atomic_exchange(&c->tr_edges, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    st_agent(&c->trace[4 * idx + 3], __hip_atomic_exchange(&c->tr_impr, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    st_agent(&c->trace[4 * idx + 2], g_exch(&c->tr_edges, 0ull));
+    st_agent(&c->trace[4 * idx + 3], g_exch(&c->tr_impr, 0ull));
   }
 }
 
@@ -146,10 +183,10 @@ __device__ bool grid_sync(Ctl* c, uint32_t size, uint32_t rank, F&& leader) {
     const uint32_t gsize = (size - g + groups - 1) / groups;
     gen = ld_agent(&c->bar_gen);
     bool last = false;
-    const uint32_t prev = atomicAdd(&c->bar_sub[g][0], 1u);
+    const uint32_t prev = g_add(&c->bar_sub[g][0], 1u);
     if (prev == gsize - 1) {
       st_agent(&c->bar_sub[g][0], 0u);  // the whole group has arrived; nobody re-arrives before the release
-      last = atomicAdd(&c->bar_arrive, 1u) == groups - 1;
+      last = g_add(&c->bar_arrive, 1u) == groups - 1;
       if (last) st_agent(&c->bar_arrive, 0u);
     }
     s_is_leader = last ? 1u : 0u;
@@ -173,7 +210,7 @@ __device__ bool grid_sync(Ctl* c, uint32_t size, uint32_t rank, F&& leader) {
     drain_stores();
     __syncthreads();
     if (threadIdx.x == 0) {
-      atomicAdd(&c->barriers, 1ull);
+      g_add(&c->barriers, 1ull);
       record_trace(c, 0u);
       drain_stores();
       st_agent(&c->bar_gen, gen + 1u);

@@ -51,22 +51,75 @@ __device__ inline bool in_bucket<WeightF32>(uint32_t x, const Sched& s, const Pa
   return WeightF32::bucket(x, p) == s.bucket;
 }
 
+// Every workgroup's copy of the schedule the leader published. The loads are
+// independent and issued together (one round trip to the coherent level).
 __device__ inline void load_sched(Ctl* c, Sched* s) {
   if (threadIdx.x == 0) {
-    s->action = ld_agent(&c->action);
-    s->bucket = ld_agent(&c->bucket);
-    s->in_kind = ld_agent(&c->in_kind);
-    s->in_count = ld_agent(&c->in_count);
-    s->out_buf = ld_agent(&c->out_buf);
-    s->step = ld_agent(&c->step);
-    s->round = ld_agent(&c->round);
-    s->far_epoch = ld_agent(&c->far_epoch);
-    s->far_cur = ld_agent(&c->far_cur);
-    s->far_base = ld_agent(&c->far_base);
-    s->hub_count = ld_agent(&c->hub_count);
-    s->hub_parent = ld_agent(&c->hub_parent);
-    s->lo_u = ld_agent(&c->lo_u);
-    s->hi_u = ld_agent(&c->hi_u);
+    const uint32_t action = ld_agent(&c->action), bucket = ld_agent(&c->bucket), in_kind = ld_agent(&c->in_kind),
+                   in_count = ld_agent(&c->in_count), out_buf = ld_agent(&c->out_buf), step = ld_agent(&c->step),
+                   round = ld_agent(&c->round), far_epoch = ld_agent(&c->far_epoch),
+                   far_cur = ld_agent(&c->far_cur), far_base = ld_agent(&c->far_base),
+                   hub_count = ld_agent(&c->hub_count), hub_parent = ld_agent(&c->hub_parent);
+    const uint64_t lo_u = ld_agent(&c->lo_u), hi_u = ld_agent(&c->hi_u);
+    s->action = action;
+    s->bucket = bucket;
+    s->in_kind = in_kind;
+    s->in_count = in_count;
+    s->out_buf = out_buf;
+    s->step = step;
+    s->round = round;
+    s->far_epoch = far_epoch;
+    s->far_cur = far_cur;
+    s->far_base = far_base;
+    s->hub_count = hub_count;
+    s->hub_parent = hub_parent;
+    s->lo_u = lo_u;
+    s->hi_u = hi_u;
+  }
+  __syncthreads();
+}
+
+// The leader publishes a new schedule (stores only; drained before the release).
+__device__ inline void publish_sched(Ctl* c, const Sched& s) {
+  st_agent(&c->action, s.action);
+  st_agent(&c->bucket, s.bucket);
+  st_agent(&c->in_kind, s.in_kind);
+  st_agent(&c->in_count, s.in_count);
+  st_agent(&c->out_buf, s.out_buf);
+  st_agent(&c->far_base, s.far_base);
+  st_agent(&c->step, s.step);
+  st_agent(&c->round, s.round);
+  st_agent(&c->far_epoch, s.far_epoch);
+  st_agent(&c->far_cur, s.far_cur);
+  st_agent(&c->hub_parent, s.hub_parent);
+  st_agent(&c->lo_u, s.lo_u);
+  st_agent(&c->hi_u, s.hi_u);
+}
+
+// Counters the leader's decision reads after a step, loaded together: the
+// ring slots by the lanes of wave 0, the rest by lanes of wave 1.
+enum : uint32_t { kCHubs, kCF0, kCF1, kCS, kCFar0, kCFar1, kCFarMin, kCFarMinNext, kCOvf, kCounters };
+struct Counters {
+  uint32_t bins[kRingMax];
+  uint32_t w[kCounters];
+};
+
+__device__ inline void load_counters(Ctl* c, Counters* k) {
+  const uint32_t t = threadIdx.x;
+  if (t < kRingMax) {
+    k->bins[t] = ld_agent(&c->bincount[t]);
+  } else if (t >= 64 && t < 64 + kCounters) {
+    const uint32_t j = t - 64;
+    const uint32_t* src = j == kCHubs        ? &c->hub_count
+                          : j == kCF0        ? &c->fcount[0]
+                          : j == kCF1        ? &c->fcount[1]
+                          : j == kCS         ? &c->scount
+                          : j == kCFar0      ? &c->farcount[0]
+                          : j == kCFar1      ? &c->farcount[1]
+                          : j == kCFarMin    ? &c->far_min
+                          : j == kCFarMinNext ? &c->far_min_next
+                                             : &c->ovf_seen;
+    k->w[j] = ld_agent(src);
   }
   __syncthreads();
 }
@@ -107,8 +160,8 @@ __device__ inline void trace_step_counts(Ctl* c, WgStats& st) {
       te += s_e[w];
       ti += s_i[w];
     }
-    if (te) atomicAdd(&c->tr_edges, te);
-    if (ti) atomicAdd(&c->tr_impr, ti);
+    if (te) g_add(&c->tr_edges, te);
+    if (ti) g_add(&c->tr_impr, ti);
   }
   __syncthreads();
 }
@@ -135,7 +188,7 @@ __device__ inline void push_ring(const Params& p, bool pred, uint32_t j, uint32_
   }
   uint32_t base = 0;
   if (pred && lane() == my_leader)
-    base = atomicAdd(&p.ctl->bincount[j & p.ring_mask], static_cast<uint32_t>(__popcll(my_group)));
+    base = g_add(&p.ctl->bincount[j & p.ring_mask], static_cast<uint32_t>(__popcll(my_group)));
   base = __shfl(base, static_cast<int>(my_leader));
   if (pred) st_agent(&p.bins[static_cast<size_t>(j & p.ring_mask) * p.n + base + lanes_below(my_group)], v);
 }
@@ -211,7 +264,7 @@ __device__ void stage_flush(const Params& p, const Sched& s, Stage& sg, bool for
                     : k == kSlotFront ? &p.ctl->fcount[s.out_buf]
                     : k == kSlotFar   ? &p.ctl->farcount[s.far_cur]
                                       : &p.ctl->scount;
-    sg.base[k] = c ? atomicAdd(ctr, c) : 0u;
+    sg.base[k] = c ? g_add(ctr, c) : 0u;
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < n; i += kWG) {
@@ -246,10 +299,10 @@ __device__ inline void relax_batch(const Params& p, uint32_t* t, const Sched& s,
       st_agent(&p.ovf_at[v[q]], 1u);
       st_agent(&p.ctl->ovf_seen, 1u);
     }
-    tv[q] = ok[q] ? t[v[q]] : 0u;  // may be stale, but never below the current value
+    tv[q] = ok[q] ? ldg(&t[v[q]]) : 0u;  // may be stale, but never below the current value
   }
 #pragma unroll
-  for (uint32_t q = 0; q < kILP; ++q) win[q] = ok[q] && cand[q] < tv[q] && cand[q] < atomicMin(&t[v[q]], cand[q]);
+  for (uint32_t q = 0; q < kILP; ++q) win[q] = ok[q] && cand[q] < tv[q] && cand[q] < g_min(&t[v[q]], cand[q]);
   uint32_t slot[kILP];
 #pragma unroll
   for (uint32_t q = 0; q < kILP; ++q) {
@@ -257,12 +310,12 @@ __device__ inline void relax_batch(const Params& p, uint32_t* t, const Sched& s,
     if (win[q]) {
       const uint32_t j = W::bucket(cand[q], p);
       if (j <= s.bucket) {
-        if (atomicExch(&p.qstamp[v[q]], s.step + 1u) != s.step + 1u) slot[q] = kSlotFront;
+        if (g_exch(&p.qstamp[v[q]], s.step + 1u) != s.step + 1u) slot[q] = kSlotFront;
       } else if (j < near_end) {
-        if (atomicMin(&p.bstamp[v[q]], j) > j) slot[q] = j & p.ring_mask;
+        if (g_min(&p.bstamp[v[q]], j) > j) slot[q] = j & p.ring_mask;
       } else {
-        atomicMin(&p.ctl->far_min, j);
-        if (atomicExch(&p.fstamp[v[q]], s.far_epoch) != s.far_epoch) slot[q] = kSlotFar;
+        g_min(&p.ctl->far_min, j);
+        if (g_exch(&p.fstamp[v[q]], s.far_epoch) != s.far_epoch) slot[q] = kSlotFar;
       }
     }
   }
@@ -286,7 +339,7 @@ __device__ inline uint32_t claim_next(Ctl* c, uint32_t prev, uint32_t nitems, bo
   if (solo) return prev + 1;
   if (nitems <= size) return nitems;  // every item was taken statically
   __syncthreads();
-  if (threadIdx.x == 0) *s_claim = size + atomicAdd(&c->chunk_next, 1u);
+  if (threadIdx.x == 0) *s_claim = size + g_add(&c->chunk_next, 1u);
   __syncthreads();
   return *s_claim;
 }
@@ -294,7 +347,7 @@ __device__ inline uint32_t claim_next(Ctl* c, uint32_t prev, uint32_t nitems, bo
 // Queue the pieces of one high-degree vertex (kHub or more edges in this phase).
 __device__ inline void queue_hub(const Params& p, uint32_t u, uint32_t deg) {
   const uint32_t pieces = (deg + kPiece - 1) / kPiece;
-  const uint32_t base = atomicAdd(&p.ctl->hub_count, pieces);
+  const uint32_t base = g_add(&p.ctl->hub_count, pieces);
   for (uint32_t k = 0; k < pieces && base + k < p.hub_cap; ++k)
     st_agent(&p.hub[base + k], static_cast<uint64_t>(u) | (static_cast<uint64_t>(k) << 32));
 }
@@ -315,8 +368,16 @@ __device__ inline uint32_t chunk_for(uint32_t count, uint32_t size) {
   return c;
 }
 
+// Entry threadIdx.x of a step's input list, already loaded by the leader
+// (steps it runs alone): the vertex, its tentative distance and its row.
+struct Entry {
+  uint32_t u, tu;
+  uint4 row;
+};
+
 template <class W, bool kLight>
-__device__ void phase(const Params& p, uint32_t* t, const Sched& s, WgStats& st, Stage& sg, bool solo) {
+__device__ void phase(const Params& p, uint32_t* t, const Sched& s, WgStats& st, Stage& sg, bool solo,
+                      bool preloaded = false, Entry pre = Entry{}) {
   __shared__ uint32_t s_pref[kChunk];
   __shared__ uint32_t s_beg[kChunk];
   __shared__ uint32_t s_tu[kChunk];
@@ -336,12 +397,12 @@ __device__ void phase(const Params& p, uint32_t* t, const Sched& s, WgStats& st,
     uint32_t beg = 0, deg = 0, tu = W::kInf, u = 0;
     bool take = false;
     if (threadIdx.x < chunk && k < count) {
-      u = ld_agent(&list[k]);
-      tu = ld_agent(&t[u]);
+      u = preloaded ? pre.u : ld_agent(&list[k]);
+      tu = preloaded ? pre.tu : ld_agent(&t[u]);
       // a ring slot may hold vertices that have since moved to a lower bucket
       take = !from_bin || in_bucket<W>(tu, s, p);
       if (take) {
-        const uint4 row = p.rows[u];
+        const uint4 row = preloaded ? pre.row : ldg(&p.rows[u]);
         beg = kLight ? row.x : row.y;
         deg = (kLight ? row.y : row.z) - beg;
       }
@@ -353,7 +414,7 @@ __device__ void phase(const Params& p, uint32_t* t, const Sched& s, WgStats& st,
           st_agent(&p.sstamp[u], s.round);
           to_s = true;
         } else if (ld_agent(&p.sstamp[u]) != s.round) {
-          to_s = atomicExch(&p.sstamp[u], s.round) != s.round;
+          to_s = g_exch(&p.sstamp[u], s.round) != s.round;
         }
       }
       stage_push(sg, to_s, kSlotS, u);
@@ -397,7 +458,7 @@ __device__ void phase(const Params& p, uint32_t* t, const Sched& s, WgStats& st,
             if (s_pref[mid] <= e) lo = mid;
             else hi = mid - 1;
           }
-          const uint64_t ed = p.edges[s_beg[lo] + (e - s_pref[lo])];
+          const uint64_t ed = ldg(&p.edges[s_beg[lo] + (e - s_pref[lo])]);
           v[q] = static_cast<uint32_t>(ed);
           w[q] = static_cast<uint32_t>(ed >> 32);
           tw[q] = s_tu[lo];
@@ -425,7 +486,7 @@ __device__ void hub_step(const Params& p, uint32_t* t, const Sched& s, WgStats& 
       const uint64_t rec = ld_agent(&p.hub[c]);
       const uint32_t u = static_cast<uint32_t>(rec);
       const uint32_t piece = static_cast<uint32_t>(rec >> 32);
-      const uint4 row = p.rows[u];
+      const uint4 row = ldg(&p.rows[u]);
       const uint32_t b = light ? row.x : row.y;
       const uint32_t e = light ? row.y : row.z;
       const uint32_t pb = b + piece * kPiece;
@@ -444,7 +505,7 @@ __device__ void hub_step(const Params& p, uint32_t* t, const Sched& s, WgStats& 
       w[q] = 0;
       tw[q] = s_tu;
       if (active[q]) {
-        const uint64_t ed = p.edges[e];
+        const uint64_t ed = ldg(&p.edges[e]);
         v[q] = static_cast<uint32_t>(ed);
         w[q] = static_cast<uint32_t>(ed >> 32);
       }
@@ -475,10 +536,10 @@ __device__ void far_step(const Params& p, uint32_t* t, const Sched& s) {
       if (ld_agent(&p.bstamp[v]) == kNone) {
         j = W::bucket(ld_agent(&t[v]), p);
         if (j < near_end) {
-          to_ring = atomicMin(&p.bstamp[v], j) > j;
+          to_ring = g_min(&p.bstamp[v], j) > j;
         } else {
-          atomicMin(&p.ctl->far_min_next, j);
-          to_far = atomicExch(&p.fstamp[v], s.far_epoch + 1u) != s.far_epoch + 1u;
+          g_min(&p.ctl->far_min_next, j);
+          to_far = g_exch(&p.fstamp[v], s.far_epoch + 1u) != s.far_epoch + 1u;
         }
       }
     }
@@ -501,47 +562,43 @@ __device__ void overflow_step(const Params& p, uint32_t* t) {
 
 // ------------------------------------------------------------------ leader decisions
 
+// Bucket i: [i*delta, (i+1)*delta) as integer bounds (integer weights).
 template <class W>
-__device__ void set_bucket(const Params& p, uint32_t i) {
-  Ctl* c = p.ctl;
-  st_agent(&c->bucket, i);
-  if (p.wtype == 0) {
-    st_agent(&c->lo_u, static_cast<uint64_t>(i) * p.delta_u);
-    st_agent(&c->hi_u, static_cast<uint64_t>(i + 1ull) * p.delta_u);
-  }
+__device__ inline void set_bucket(const Params& p, Sched* s, uint32_t i) {
+  s->bucket = i;
+  s->lo_u = static_cast<uint64_t>(i) * p.delta_u;
+  s->hi_u = static_cast<uint64_t>(i + 1ull) * p.delta_u;
 }
 
 // Next bucket to process: the first non-empty ring slot among the `len`
-// buckets starting at `from`, unless far-future vertices may come first.
+// buckets starting at `from`, unless far-future vertices (fc of them, none
+// below bucket fmin) may come first. Wave 0 scans the slots; thread 0 decides.
 template <class W>
-__device__ void choose_next(const Params& p, uint32_t from, uint32_t len) {
-  Ctl* c = p.ctl;
+__device__ void choose_next(const Params& p, Sched* s, const Counters& k, uint32_t from, uint32_t len, uint32_t fc,
+                            uint32_t fmin) {
   __shared__ uint32_t s_jn;
   if (threadIdx.x < 64) {
     const uint32_t l = threadIdx.x;
-    bool nonempty = false;
-    if (l < len) nonempty = ld_agent(&c->bincount[(from + l) & p.ring_mask]) != 0u;
+    const bool nonempty = l < len && k.bins[(from + l) & p.ring_mask] != 0u;
     const uint64_t m = __ballot(nonempty);
     if (l == 0) s_jn = m ? from + static_cast<uint32_t>(first_lane(m)) : kNone;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     const uint32_t jn = s_jn;
-    const uint32_t fc = ld_agent(&c->farcount[ld_agent(&c->far_cur)]);
-    const uint32_t fmin = ld_agent(&c->far_min);
     if (fc > 0 && (jn == kNone || fmin <= jn)) {
-      st_agent(&c->action, static_cast<uint32_t>(kActFar));
-      st_agent(&c->far_base, jn == kNone ? fmin : min(jn, fmin));
-      st_agent(&c->in_count, fc);
+      s->action = kActFar;
+      s->far_base = jn == kNone ? fmin : min(jn, fmin);
+      s->in_count = fc;
     } else if (jn == kNone) {
-      st_agent(&c->action, static_cast<uint32_t>(ld_agent(&c->ovf_seen) ? kActOverflowCheck : kActDone));
+      s->action = k.w[kCOvf] ? kActOverflowCheck : kActDone;
     } else {  // B_i = {v : i*delta <= t(v) < (i+1)*delta} for the smallest non-empty i
-      set_bucket<W>(p, jn);
-      st_agent(&c->action, static_cast<uint32_t>(kActLight));
-      st_agent(&c->in_kind, static_cast<uint32_t>(kInBin));
-      st_agent(&c->in_count, ld_agent(&c->bincount[jn & p.ring_mask]));
-      st_agent(&c->out_buf, 0u);
-      atomicAdd(&c->buckets, 1ull);
+      set_bucket<W>(p, s, jn);
+      s->action = kActLight;
+      s->in_kind = kInBin;
+      s->in_count = k.bins[jn & p.ring_mask];
+      s->out_buf = 0u;
+      g_add(&p.ctl->buckets, 1ull);
     }
   }
   __syncthreads();
@@ -550,134 +607,161 @@ __device__ void choose_next(const Params& p, uint32_t from, uint32_t len) {
 // Start a solve: t = inf was set by every workgroup; t(s) = 0 for each seed
 // (Fig. 1 left, initialisation; with several seeds, d(v) is the distance from
 // the nearest one), and the seeds form B_0. Seeds outside [0, n) are reported
-// and skipped; repeated seeds are filed once.
+// and skipped; repeated seeds are filed once. The schedule of the first step
+// is left in *s and published. `reset_tags`: the group's stamps were just
+// cleared, so the de-duplication tags restart.
 template <class W>
-__device__ void leader_start(const Params& p, uint32_t* t, const int32_t* seeds, int nseeds) {
+__device__ void leader_start(const Params& p, uint32_t* t, const int32_t* seeds, int nseeds, bool reset_tags,
+                             Sched* s) {
   Ctl* c = p.ctl;
   if (threadIdx.x < kRingMax) st_agent(&c->bincount[threadIdx.x], 0u);
   if (threadIdx.x == 0) {
-    atomicAdd(&c->sources, 1ull);
+    uint32_t step = 0, round = 0, far_epoch = 1;
+    if (!reset_tags) {
+      step = ld_agent(&c->step);
+      round = ld_agent(&c->round);
+      far_epoch = ld_agent(&c->far_epoch);
+    }
+    g_add(&c->sources, 1ull);
     st_agent(&c->fcount[0], 0u);
     st_agent(&c->fcount[1], 0u);
     st_agent(&c->scount, 0u);
     st_agent(&c->farcount[0], 0u);
     st_agent(&c->farcount[1], 0u);
-    st_agent(&c->far_cur, 0u);
     st_agent(&c->far_min, kNone);
     st_agent(&c->far_min_next, kNone);
     st_agent(&c->ovf_seen, 0u);
     st_agent(&c->hub_count, 0u);
     st_agent(&c->chunk_next, 0u);
-    st_agent(&c->step, ld_agent(&c->step) + 1u);
-    st_agent(&c->round, ld_agent(&c->round) + 1u);
+    Sched n{};
+    n.step = step + 1u;
+    n.round = round + 1u;
+    n.far_epoch = far_epoch;
+    *s = n;
   }
   drain_stores();
   __syncthreads();
   for (int i = threadIdx.x; i < nseeds; i += kWG) {
-    const int32_t src = seeds[i];
+    const int32_t src = ldg(&seeds[i]);
     if (src < 0 || static_cast<uint32_t>(src) >= p.n) {
       st_agent(&c->bad_source, 1u);
       continue;
     }
-    const uint32_t u = p.vid[src];
+    const uint32_t u = ldg(&p.vid[src]);
     st_agent(&t[u], 0u);
-    if (atomicMin(&p.bstamp[u], 0u) != 0u) st_agent(&p.bins[atomicAdd(&c->bincount[0], 1u)], u);
+    if (g_min(&p.bstamp[u], 0u) != 0u) st_agent(&p.bins[g_add(&c->bincount[0], 1u)], u);
   }
   drain_stores();
   __syncthreads();
   if (threadIdx.x == 0) {
-    set_bucket<W>(p, 0u);
-    st_agent(&c->action, static_cast<uint32_t>(kActLight));
-    st_agent(&c->in_kind, static_cast<uint32_t>(kInBin));
-    st_agent(&c->in_count, ld_agent(&c->bincount[0]));
-    st_agent(&c->out_buf, 0u);
-    atomicAdd(&c->buckets, 1ull);
+    set_bucket<W>(p, s, 0u);
+    s->action = kActLight;
+    s->in_kind = kInBin;
+    s->in_count = ld_agent(&c->bincount[0]);
+    s->out_buf = 0u;
+    g_add(&c->buckets, 1ull);
+    publish_sched(c, *s);
   }
   drain_stores();
   __syncthreads();
 }
 
-// Schedule the step that follows the completed step `s`.
+// Schedule the step that follows the completed step *s (the leader's copy in
+// LDS, replaced by the new schedule, which is also published). The counters
+// are read in one round trip; the rest is stores, which the caller drains
+// before anything reads them back (the barrier release does).
 template <class W>
-__device__ void after_step(const Params& p, const Sched& s) {
+__device__ void after_step(const Params& p, Sched* s) {
   Ctl* c = p.ctl;
-  __shared__ uint32_t s_next;  // 0: decided, 1: choose the next bucket after s.bucket, 2: after a far step
+  __shared__ Counters k;
+  __shared__ uint32_t s_next, s_fc, s_fmin;  // s_next 0: decided; 1: next bucket after s.bucket; 2: after a far step
+  load_counters(c, &k);
   if (threadIdx.x == 0) {
-    st_agent(&c->chunk_next, 0u);
+    const Sched o = *s;
+    Sched n = o;
     uint32_t next = 0;
-    const uint32_t hubs = ld_agent(&c->hub_count);
-    const bool phase_done = s.action == kActLight || s.action == kActHeavy;
+    st_agent(&c->chunk_next, 0u);
+    const uint32_t hubs = k.w[kCHubs];
+    const bool phase_done = o.action == kActLight || o.action == kActHeavy;
     if (phase_done && hubs > 0) {  // finish the phase: its high-degree vertices
-      st_agent(&c->hub_parent, s.action);
-      st_agent(&c->action, static_cast<uint32_t>(kActHub));
+      n.hub_parent = o.action;
+      n.hub_count = hubs;
+      n.action = kActHub;
     } else {
-      const uint32_t parent = s.action == kActHub ? s.hub_parent : s.action;
+      const uint32_t parent = o.action == kActHub ? o.hub_parent : o.action;
       st_agent(&c->hub_count, 0u);
+      n.hub_count = 0;
       if (parent == kActLight) {
-        atomicAdd(&c->light_phases, 1ull);
-        st_agent(&c->step, s.step + 1u);
-        const uint32_t n_next = ld_agent(&c->fcount[s.out_buf]);
-        if (s.in_kind == kInBin) st_agent(&c->bincount[s.bucket & p.ring_mask], 0u);
-        else st_agent(&c->fcount[s.in_kind], 0u);
+        g_add(&c->light_phases, 1ull);
+        n.step = o.step + 1u;
+        const uint32_t n_next = k.w[o.out_buf ? kCF1 : kCF0];
+        if (o.in_kind == kInBin) st_agent(&c->bincount[o.bucket & p.ring_mask], 0u);
+        else st_agent(&c->fcount[o.in_kind], 0u);
         if (n_next > 0) {  // while t_Bi != 0: another light phase on the re-inserted vertices
-          st_agent(&c->action, static_cast<uint32_t>(kActLight));
-          st_agent(&c->in_kind, s.out_buf);
-          st_agent(&c->in_count, n_next);
-          st_agent(&c->out_buf, 1u - s.out_buf);
+          n.action = kActLight;
+          n.in_kind = o.out_buf;
+          n.in_count = n_next;
+          n.out_buf = 1u - o.out_buf;
         } else if (p.no_heavy) {  // A_H is empty (every weight <= delta): the bucket is done
           next = 1;
         } else {  // B_i is empty: one heavy phase over S
-          st_agent(&c->action, static_cast<uint32_t>(kActHeavy));
-          st_agent(&c->in_count, ld_agent(&c->scount));
+          n.action = kActHeavy;
+          n.in_count = k.w[kCS];
         }
       } else if (parent == kActHeavy) {
-        atomicAdd(&c->heavy_phases, 1ull);
-        st_agent(&c->step, s.step + 1u);
-        st_agent(&c->round, s.round + 1u);
+        g_add(&c->heavy_phases, 1ull);
+        n.step = o.step + 1u;
+        n.round = o.round + 1u;
         st_agent(&c->scount, 0u);
         // A heavy request can only fall back into bucket i through fp32 rounding
         // (t(u) + w > (i+1)*delta in exact arithmetic); such vertices restart bucket i.
-        const uint32_t n_redo = ld_agent(&c->fcount[s.out_buf]);
+        const uint32_t n_redo = k.w[o.out_buf ? kCF1 : kCF0];
         if (n_redo > 0) {
-          st_agent(&c->action, static_cast<uint32_t>(kActLight));
-          st_agent(&c->in_kind, s.out_buf);
-          st_agent(&c->in_count, n_redo);
-          st_agent(&c->out_buf, 1u - s.out_buf);
+          n.action = kActLight;
+          n.in_kind = o.out_buf;
+          n.in_count = n_redo;
+          n.out_buf = 1u - o.out_buf;
         } else {
           next = 1;
         }
       } else if (parent == kActFar) {
-        atomicAdd(&c->far_phases, 1ull);
-        st_agent(&c->step, s.step + 1u);
-        st_agent(&c->farcount[s.far_cur], 0u);
-        st_agent(&c->far_cur, 1u - s.far_cur);
-        st_agent(&c->far_min, ld_agent(&c->far_min_next));
+        g_add(&c->far_phases, 1ull);
+        n.step = o.step + 1u;
+        st_agent(&c->farcount[o.far_cur], 0u);
+        n.far_cur = 1u - o.far_cur;
+        st_agent(&c->far_min, k.w[kCFarMinNext]);
         st_agent(&c->far_min_next, kNone);
-        st_agent(&c->far_epoch, s.far_epoch + 1u);
+        n.far_epoch = o.far_epoch + 1u;
         next = 2;
       } else {  // overflow check
-        st_agent(&c->action, static_cast<uint32_t>(kActDone));
+        n.action = kActDone;
       }
     }
+    // far lists as the next-bucket choice sees them (after a far step: the other list)
+    s_fc = k.w[n.far_cur ? kCFar1 : kCFar0];
+    s_fmin = next == 2 ? k.w[kCFarMinNext] : k.w[kCFarMin];
+    *s = n;
     s_next = next;
   }
   __syncthreads();
   const uint32_t next = s_next;
-  if (next == 1) choose_next<W>(p, s.bucket + 1u, p.ring - 1u);
-  else if (next == 2) choose_next<W>(p, s.far_base, p.ring);
-  drain_stores();
+  if (next == 1) choose_next<W>(p, s, k, s->bucket + 1u, p.ring - 1u, s_fc, s_fmin);
+  else if (next == 2) choose_next<W>(p, s, k, s->far_base, p.ring, s_fc, s_fmin);
+  if (threadIdx.x == 0) publish_sched(c, *s);
   __syncthreads();
 }
 
-// Edges a light or heavy step would scan (its list has at most kWG entries).
+// Edges a light or heavy step would scan (its list has at most kWG entries);
+// each thread keeps its entry for the phase that may follow on this workgroup.
 template <bool kLight>
-__device__ uint32_t step_edges(const Params& p, const Sched& s, uint32_t* s_wsum) {
+__device__ uint32_t step_edges(const Params& p, const uint32_t* t, const Sched& s, uint32_t* s_wsum, Entry* e) {
   const uint32_t* list = phase_list(p, s, kLight);
   uint32_t deg = 0;
   if (threadIdx.x < s.in_count) {
-    const uint32_t u = ld_agent(&list[threadIdx.x]);
-    const uint4 row = p.rows[u];
-    deg = kLight ? row.y - row.x : row.z - row.y;
+    e->u = ld_agent(&list[threadIdx.x]);
+    e->tu = ld_agent(&t[e->u]);
+    e->row = ldg(&p.rows[e->u]);
+    deg = kLight ? e->row.y - e->row.x : e->row.z - e->row.y;
   }
   uint32_t total;
   (void)block_exclusive_scan(deg, &total, s_wsum);
@@ -689,20 +773,22 @@ __device__ uint32_t step_edges(const Params& p, const Sched& s, uint32_t* s_wsum
 template <class W>
 __device__ void lead(const Params& p, uint32_t* t, Sched* s, WgStats& st, Stage& sg, bool schedule_first) {
   __shared__ uint32_t s_wsum[kWG / 64];
-  if (schedule_first) after_step<W>(p, *s);
-  for (;;) {
-    load_sched(p.ctl, s);
+  if (schedule_first) after_step<W>(p, s);
+  for (;;) {  // *s is the current schedule (set by leader_start or after_step)
     const bool light = s->action == kActLight;
     if (!(light || s->action == kActHeavy) || s->in_count > static_cast<uint32_t>(kChunk)) break;
-    const uint32_t edges = light ? step_edges<true>(p, *s, s_wsum) : step_edges<false>(p, *s, s_wsum);
+    Entry e{};
+    const uint32_t edges = light ? step_edges<true>(p, t, *s, s_wsum, &e) : step_edges<false>(p, t, *s, s_wsum, &e);
     if (edges > p.inline_edges) break;
+    drain_stores();  // the counter resets of after_step land before this step's appends
+    __syncthreads();
     if (threadIdx.x == 0) record_trace(p.ctl, 0x80u);
-    if (light) phase<W, true>(p, t, *s, st, sg, true);
-    else phase<W, false>(p, t, *s, st, sg, true);
+    if (light) phase<W, true>(p, t, *s, st, sg, true, true, e);
+    else phase<W, false>(p, t, *s, st, sg, true, true, e);
     trace_step_counts(p.ctl, st);
     drain_stores();
     __syncthreads();
-    after_step<W>(p, *s);
+    after_step<W>(p, s);
   }
 }
 
@@ -715,12 +801,7 @@ __device__ void leader_claim(const Params& p, uint32_t* t, const int32_t* source
   __shared__ uint32_t s_row;
   Ctl* c = p.ctl;
   if (threadIdx.x == 0) {
-    if (reset_tags) {  // the group's stamps were cleared before this barrier
-      st_agent(&c->step, 0u);
-      st_agent(&c->round, 0u);
-      st_agent(&c->far_epoch, 1u);
-    }
-    const uint32_t r = atomicAdd(p.next_source, 1u);
+    const uint32_t r = g_add(p.next_source, 1u);
     const uint32_t rows = multi ? 1u : static_cast<uint32_t>(k);
     s_row = r < rows ? r : kNone;
     st_agent(&c->source_index, s_row);
@@ -728,7 +809,7 @@ __device__ void leader_claim(const Params& p, uint32_t* t, const int32_t* source
   __syncthreads();
   const uint32_t r = s_row;
   if (r == kNone) return;
-  leader_start<W>(p, t, multi ? sources : sources + r, multi ? k : 1);
+  leader_start<W>(p, t, multi ? sources : sources + r, multi ? k : 1, reset_tags, s);
   lead<W>(p, t, s, st, sg, false);  // the first phases (around the seeds) are usually small
 }
 
@@ -784,7 +865,7 @@ __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ 
     }
     if (alive) {  // the source's row of the output, in the caller's vertex numbering
       uint32_t* out = dist + static_cast<size_t>(row) * p.n;
-      for (uint32_t v = rank * kWG + threadIdx.x; v < p.n; v += size * kWG) out[v] = ld_agent(&t[p.vid[v]]);
+      for (uint32_t v = rank * kWG + threadIdx.x; v < p.n; v += size * kWG) *gp(&out[v]) = ld_agent(&t[ldg(&p.vid[v])]);
     }
   }
   // fold per-lane counters into the group's control block
@@ -795,9 +876,9 @@ __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ 
     im += __shfl_down(im, d);
   }
   if (lane() == 0) {
-    if (le) atomicAdd(&c->light_edges, le);
-    if (he) atomicAdd(&c->heavy_edges, he);
-    if (im) atomicAdd(&c->improvements, im);
+    if (le) g_add(&c->light_edges, le);
+    if (he) g_add(&c->heavy_edges, he);
+    if (im) g_add(&c->improvements, im);
   }
 }
 
