@@ -45,6 +45,8 @@ typedef enum {
 typedef enum {
   SSSP_WEIGHT_U32 = 0, /* uint32 weights >= 1; distances uint32, UINT32_MAX = unreachable */
   SSSP_WEIGHT_F32 = 1, /* float weights, finite and > 0; distances float, +inf = unreachable */
+  SSSP_WEIGHT_F64 = 2, /* double weights, finite and > 0; distances double, +inf = unreachable
+                          (the paper's own precision, GrB_FP64 in Fig. 4) */
 } sssp_weight_type;
 
 /*
@@ -105,7 +107,8 @@ typedef struct sssp_handle sssp_handle;
  *   delta: for SSSP_WEIGHT_U32 an integer in [1, 2^32-1]; for SSSP_WEIGHT_F32 the
  *   threshold is (float)delta, which must be finite and > 0, and the total weight
  *   times exp((n-1) * 2^-24) (a bound on any rounded path sum) divided by delta
- *   must stay below 2^32 - 256 (bucket indices fit 32 bits).
+ *   must stay below 2^32 - 256 (bucket indices fit 32 bits); for SSSP_WEIGHT_F64
+ *   delta itself, finite and > 0, with the same bound using 2^-53.
  *   stream: enqueue work here; the call synchronises it before returning.
  *   out: host pointer receiving the new handle (library-owned; free with
  *   sssp_destroy), NULL on error.
@@ -122,12 +125,12 @@ sssp_status sssp_create(const sssp_graph *g, double delta, void *stream, sssp_ha
  *   i*delta <= t < (i+1)*delta, light phases t_Req = A_L^T (t o t_Bi) repeated
  *   while vertices re-enter B_i, then one heavy phase t_Req = A_H^T (t o S).
  *   Path weights add left to right in the weight type: exact integers for u32
- *   (a distance above 2^32-2 is SSSP_ERR_OVERFLOW), binary32 round-to-nearest-even
- *   for f32 (a sum that rounds to +inf is SSSP_ERR_OVERFLOW). The result does not
- *   depend on the order of relaxations.
+ *   (a distance above 2^32-2 is SSSP_ERR_OVERFLOW), binary32 (binary64)
+ *   round-to-nearest-even for f32 (f64) (a sum that rounds to +inf is
+ *   SSSP_ERR_OVERFLOW). The result does not depend on the order of relaxations.
  *   sources: HOST int32 [k], each in [0, n).  k >= 1.
- *   dist: DEVICE, caller-owned, [k][n] of the weight type (uint32 or float),
- *   row-major; fully overwritten. d(s) = 0; unreachable = UINT32_MAX / +inf.
+ *   dist: DEVICE, caller-owned, [k][n] of the weight type (uint32, float or
+ *   double), row-major; fully overwritten. d(s) = 0; unreachable = UINT32_MAX / +inf.
  *   stream: the call synchronises it before returning (to report overflow).
  *   Errors: INVALID_ARGUMENT, OVERFLOW, DEVICE.
  */
@@ -199,7 +202,7 @@ sssp_status sssp_solve_status(sssp_handle *h, void *stream);
  *   [k][n] float.  grad_w: DEVICE [m] float, caller edge order, overwritten.
  *   The call synchronises the stream.
  *   Errors: INVALID_ARGUMENT (pointers, sources, or dist not a shortest-path
- *   vector of this graph), UNSUPPORTED (uint32 handles), NO_FORWARD (no
+ *   vector of this graph), UNSUPPORTED (uint32 and double handles), NO_FORWARD (no
  *   successful sssp_solve since the handle's weights were set), DEVICE.
  */
 sssp_status sssp_backward(sssp_handle *h, const int32_t *sources, int32_t k, const void *dist,

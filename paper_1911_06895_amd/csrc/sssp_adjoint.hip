@@ -153,9 +153,9 @@ __global__ __launch_bounds__(kAuxWG) void count_reached_kernel(const uint32_t* d
 // records (light first, then heavy; each group keeps the records' current
 // order) with the new weight of each record's caller edge.
 __global__ __launch_bounds__(kAuxWG) void resplit_kernel(uint32_t n, const uint4* rows_in, const uint64_t* edges_in,
-                                                         const uint32_t* perm_in, const uint32_t* wbits, int wtype,
-                                                         uint32_t delta_u, float delta_f, uint4* rows_out,
-                                                         uint64_t* edges_out, uint32_t* perm_out) {
+                                                         const uint32_t* perm_in, const void* w, Threshold th,
+                                                         uint4* rows_out, uint64_t* w64_out, uint64_t* edges_out,
+                                                         uint32_t* perm_out) {
   const uint32_t wave = (blockIdx.x * kAuxWG + threadIdx.x) >> 6;
   const uint32_t nwaves = (gridDim.x * kAuxWG) >> 6;
   const uint32_t l = lane();
@@ -164,10 +164,7 @@ __global__ __launch_bounds__(kAuxWG) void resplit_kernel(uint32_t n, const uint4
     uint32_t nlight = 0;
     for (uint32_t p = row.x; p < row.z; p += 64) {
       bool light = false;
-      if (p + l < row.z) {
-        const uint32_t wb = wbits[perm_in[p + l]];
-        light = wtype == 0 ? wb <= delta_u : __uint_as_float(wb) <= delta_f;
-      }
+      if (p + l < row.z) light = is_light(weight_bits(w, th.wtype, perm_in[p + l]), th);
       nlight += static_cast<uint32_t>(__popcll(__ballot(light)));
     }
     if (l == 0) rows_out[x] = make_uint4(row.x, row.x + nlight, row.z, 0u);
@@ -175,18 +172,24 @@ __global__ __launch_bounds__(kAuxWG) void resplit_kernel(uint32_t n, const uint4
     for (uint32_t p = row.x; p < row.z; p += 64) {
       const bool in = p + l < row.z;
       bool light = false;
-      uint32_t wb = 0, y = 0, ce = 0;
+      uint64_t wb = 0;
+      uint32_t y = 0, ce = 0;
       if (in) {
         ce = perm_in[p + l];
         y = static_cast<uint32_t>(edges_in[p + l]);
-        wb = wbits[ce];
-        light = wtype == 0 ? wb <= delta_u : __uint_as_float(wb) <= delta_f;
+        wb = weight_bits(w, th.wtype, ce);
+        light = is_light(wb, th);
       }
       const uint64_t ml = __ballot(in && light);
       const uint64_t mh = __ballot(in && !light);
       if (in) {
         const uint32_t pos = light ? lpos + lanes_below(ml) : hpos + lanes_below(mh);
-        edges_out[pos] = static_cast<uint64_t>(y) | (static_cast<uint64_t>(wb) << 32);
+        if (th.wtype == kWF64) {
+          edges_out[pos] = static_cast<uint64_t>(y);
+          w64_out[pos] = wb;
+        } else {
+          edges_out[pos] = static_cast<uint64_t>(y) | (wb << 32);
+        }
         perm_out[pos] = ce;
       }
       lpos += static_cast<uint32_t>(__popcll(ml));
@@ -230,14 +233,13 @@ hipError_t launch_count_reached(const uint32_t* dist, uint32_t n, int k, int wty
 }
 
 hipError_t launch_resplit(uint32_t n, const uint4* rows_in, const uint64_t* edges_in, const uint32_t* perm_in,
-                          const void* w, int wtype, uint32_t delta_u, float delta_f, uint4* rows_out,
+                          const void* w, const Threshold& th, uint4* rows_out, uint64_t* w64_out,
                           uint64_t* edges_out, uint32_t* perm_out, hipStream_t s) {
   size_t blocks = (static_cast<size_t>(n) * 64 + kAuxWG - 1) / kAuxWG;
   if (blocks > 16384) blocks = 16384;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(resplit_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kAuxWG), 0, s, n, rows_in, edges_in,
-                     perm_in, static_cast<const uint32_t*>(w), wtype, delta_u, delta_f, rows_out, edges_out,
-                     perm_out);
+                     perm_in, w, th, rows_out, w64_out, edges_out, perm_out);
   return hipGetLastError();
 }
 

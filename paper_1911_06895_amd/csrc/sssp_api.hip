@@ -11,7 +11,7 @@
 
 // Working set of one extra concurrent group (the first group's lives in Params).
 struct GroupMem {
-  uint32_t* tbuf[2] = {nullptr, nullptr};
+  void* tbuf[2] = {nullptr, nullptr};
   uint32_t *qstamp = nullptr, *sstamp = nullptr, *bstamp = nullptr, *fstamp = nullptr, *ovf_at = nullptr;
   uint32_t* front[2] = {nullptr, nullptr};
   uint32_t* slist = nullptr;
@@ -27,7 +27,9 @@ struct sssp_handle {
   double delta = 0;
   uint32_t delta_u = 0;
   float delta_f = 0;
-  uint32_t wmax_bits = 0;
+  double delta_d = 0;
+  uint64_t wmax_bits = 0;
+  uint64_t* w64 = nullptr;  // [m] fp64 weights at the split positions (fp64 handles)
   int grid = 0;
   int cus = 0;
   int occupancy = 0;
@@ -86,7 +88,7 @@ hipError_t dalloc(T** p, size_t count) {
 void free_handle(sssp_handle* h) {
   if (!h) return;
   sssp::Params& p = h->p;
-  void* extra[] = {h->inv, h->adj_d, h->adj_parent, h->adj_cnt, h->adj_g, h->adj_grad64, h->aux, h->params_dev};
+  void* extra[] = {h->inv, h->adj_d, h->adj_parent, h->adj_cnt, h->adj_g, h->adj_grad64, h->aux, h->params_dev, h->w64};
   for (void* q : extra)
     if (q) (void)hipFree(q);
   for (GroupMem& gm : h->extra) {
@@ -120,31 +122,91 @@ sssp_status configure_grid(sssp_handle* h) {
   return SSSP_OK;
 }
 
-// fp32 bucket indices floor(t / delta) of every distance the solver can
-// produce stay below 2^32 - 1 (the "none" tag). A tentative distance that wins
-// an update is the rounded left-to-right sum along a simple path (a walk with a
-// cycle never beats the value it had at the cycle's start), so it is at most
-// the total weight times (1 + 2^-24)^(n-1), one rounding per edge.
-bool f32_buckets_fit(double wsum, int64_t n, float delta) {
-  const double bound = wsum * std::exp(static_cast<double>(n - 1) * 0x1p-24) * (1.0 + 0x1p-40);
-  return bound / static_cast<double>(delta) < 4294967040.0;  // 2^32 - 256
+// Bytes of one distance (and one weight) of the handle's type.
+size_t dist_bytes(int32_t wtype) { return wtype == SSSP_WEIGHT_F64 ? 8 : 4; }
+
+// A weight (as bits) and delta as doubles (exact for every type).
+double weight_of(const sssp_handle* h, uint64_t bits) {
+  if (h->wtype == SSSP_WEIGHT_U32) return static_cast<double>(bits);
+  if (h->wtype == SSSP_WEIGHT_F32) {
+    float f;
+    const uint32_t b = static_cast<uint32_t>(bits);
+    std::memcpy(&f, &b, sizeof(f));
+    return static_cast<double>(f);
+  }
+  double d;
+  std::memcpy(&d, &bits, sizeof(d));
+  return d;
+}
+double delta_of(const sssp_handle* h) {
+  if (h->wtype == SSSP_WEIGHT_U32) return static_cast<double>(h->delta_u);
+  if (h->wtype == SSSP_WEIGHT_F32) return static_cast<double>(h->delta_f);
+  return h->delta_d;
+}
+
+sssp::Threshold threshold_of(const sssp_handle* h) {
+  sssp::Threshold th{};
+  th.wtype = h->wtype;
+  th.delta_u = h->delta_u;
+  th.delta_f = h->delta_f;
+  th.delta_d = h->delta_d;
+  return th;
+}
+
+// Floating-point bucket indices floor(t / delta) of every distance the solver
+// can produce stay below 2^32 - 1 (the "none" tag). A tentative distance that
+// wins an update is the rounded left-to-right sum along a simple path (a walk
+// with a cycle never beats the value it had at the cycle's start), so it is
+// at most the total weight times (1 + u)^(n-1), one rounding per edge (u =
+// 2^-24 in fp32, 2^-53 in fp64). Integer distances fit by construction.
+bool buckets_fit(const sssp_handle* h, double wsum) {
+  if (h->wtype == SSSP_WEIGHT_U32) return true;
+  const double u = h->wtype == SSSP_WEIGHT_F32 ? 0x1p-24 : 0x1p-53;
+  const double bound = wsum * std::exp(static_cast<double>(h->n - 1) * u) * (1.0 + 0x1p-40);
+  return bound / delta_of(h) < 4294967040.0;  // 2^32 - 256
 }
 
 // Every weight is light (w <= delta): A_H is empty.
-uint32_t no_heavy_for(const sssp_handle* h, uint32_t wmax_bits) {
-  if (h->wtype == SSSP_WEIGHT_U32) return wmax_bits <= h->delta_u ? 1u : 0u;
-  float wmax;
-  std::memcpy(&wmax, &wmax_bits, sizeof(float));
-  return wmax <= h->delta_f ? 1u : 0u;
+uint32_t no_heavy_for(const sssp_handle* h, uint64_t wmax_bits) {
+  return weight_of(h, wmax_bits) <= delta_of(h) ? 1u : 0u;
+}
+
+// Validation on the device: status bits, the largest weight (bits) and the
+// weight total. With row_ptr == nullptr only the weights are checked.
+struct WeightStats {
+  uint32_t status;
+  uint64_t wmax_bits;
+  double wsum;
+};
+sssp_status validate_on_device(const int64_t* row_ptr, const int32_t* col, const void* w, int32_t wtype, int64_t n,
+                               int64_t m, hipStream_t s, WeightStats* out) {
+  uint32_t* scratch = nullptr;  // [0] status, [2..3] max weight bits, [4..5] fp64 weight total
+  SSSP_TRY(dalloc(&scratch, 6));
+  hipError_t e = hipMemsetAsync(scratch, 0, 6 * sizeof(uint32_t), s);
+  auto* wmax = reinterpret_cast<unsigned long long*>(scratch + 2);
+  auto* wsum = reinterpret_cast<double*>(scratch + 4);
+  if (e == hipSuccess)
+    e = row_ptr ? sssp::launch_validate(row_ptr, col, w, wtype, n, m, scratch, wmax, wsum, s)
+                : sssp::launch_validate_weights(w, wtype, m, scratch, wmax, wsum, s);
+  uint32_t res[6] = {0, 0, 0, 0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(res, scratch, sizeof(res), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(scratch);
+  SSSP_TRY(e);
+  out->status = res[0];
+  std::memcpy(&out->wmax_bits, res + 2, sizeof(uint64_t));
+  std::memcpy(&out->wsum, res + 4, sizeof(double));
+  return SSSP_OK;
 }
 
 // Working set of one more concurrent group: the same arrays as the first
 // group's, with the de-duplication stamps cleared (its tags start at zero).
 sssp_status alloc_group(sssp_handle* h, GroupMem* gm) {
   const size_t un = static_cast<size_t>(h->n);
-  uint32_t** words[] = {&gm->tbuf[0], &gm->tbuf[1], &gm->qstamp, &gm->sstamp, &gm->bstamp, &gm->fstamp, &gm->ovf_at,
+  uint32_t** words[] = {&gm->qstamp, &gm->sstamp, &gm->bstamp, &gm->fstamp, &gm->ovf_at,
                         &gm->front[0], &gm->front[1], &gm->slist, &gm->far[0], &gm->far[1]};
   for (uint32_t** q : words) SSSP_TRY(dalloc(q, un));
+  for (void** q : {&gm->tbuf[0], &gm->tbuf[1]}) SSSP_TRY(hipMalloc(q, un * dist_bytes(h->wtype)));
   SSSP_TRY(dalloc(&gm->bins, un * h->p.ring));
   SSSP_TRY(dalloc(&gm->hub, h->p.hub_cap));
   uint32_t* zero[] = {gm->qstamp, gm->sstamp, gm->fstamp, gm->ovf_at};
@@ -220,37 +282,20 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   h->wtype = g->wtype;
   h->delta = delta;
   if (g->wtype == SSSP_WEIGHT_U32) h->delta_u = static_cast<uint32_t>(delta);
-  else h->delta_f = static_cast<float>(delta);
+  else if (g->wtype == SSSP_WEIGHT_F32) h->delta_f = static_cast<float>(delta);
+  else h->delta_d = delta;
 
   // 1. validate the CSR and the weights on the device
-  uint32_t* scratch = nullptr;  // [0] status, [1] max weight bits, [2..3] fp64 weight total
-  SSSP_TRY(dalloc(&scratch, 4));
-  hipError_t e = hipMemsetAsync(scratch, 0, 4 * sizeof(uint32_t), stream);
-  if (e == hipSuccess)
-    e = sssp::launch_validate(g->row_ptr, g->col_idx, g->weights, g->wtype, n, m, scratch, scratch + 1,
-                              reinterpret_cast<double*>(scratch + 2), stream);
-  uint32_t res[4] = {0, 0, 0, 0};
-  if (e == hipSuccess) e = hipMemcpyAsync(res, scratch, sizeof(res), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  (void)hipFree(scratch);
-  SSSP_TRY(e);
-  if (res[0] & (sssp::kBadRowPtr | sssp::kBadCol)) return SSSP_ERR_INVALID_ARGUMENT;
-  if (res[0] & sssp::kBadWeight) return SSSP_ERR_INVALID_WEIGHT;
-  h->wmax_bits = res[1];
-  double wsum;
-  std::memcpy(&wsum, res + 2, sizeof(double));
+  WeightStats ws{};
+  const sssp_status vs = validate_on_device(g->row_ptr, g->col_idx, g->weights, g->wtype, n, m, stream, &ws);
+  if (vs != SSSP_OK) return vs;
+  if (ws.status & (sssp::kBadRowPtr | sssp::kBadCol)) return SSSP_ERR_INVALID_ARGUMENT;
+  if (ws.status & sssp::kBadWeight) return SSSP_ERR_INVALID_WEIGHT;
+  h->wmax_bits = ws.wmax_bits;
 
   // 2. bucket geometry: ring large enough that one relaxation never jumps past it
-  double span;  // max weight / delta
-  if (g->wtype == SSSP_WEIGHT_U32) {
-    span = static_cast<double>(h->wmax_bits) / static_cast<double>(h->delta_u);
-  } else {
-    float wmax;
-    std::memcpy(&wmax, &h->wmax_bits, sizeof(float));
-    const double dd = static_cast<double>(h->delta_f);
-    span = static_cast<double>(wmax) / dd;
-    if (!f32_buckets_fit(wsum, n, h->delta_f)) return SSSP_ERR_UNSUPPORTED;
-  }
+  const double span = weight_of(h, h->wmax_bits) / delta_of(h);  // max weight / delta
+  if (!buckets_fit(h, ws.wsum)) return SSSP_ERR_UNSUPPORTED;
   uint32_t ring = h->tuning.ring_buckets > 0 ? static_cast<uint32_t>(h->tuning.ring_buckets)
                                               : pow2_at_least(static_cast<uint32_t>(std::min(span + 2.0, 64.0)));
   if (ring < 2) ring = 2;
@@ -264,8 +309,8 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   p.wtype = static_cast<uint32_t>(g->wtype);
   p.no_heavy = no_heavy_for(h, h->wmax_bits);
   p.delta_u = h->delta_u;
-  p.delta_d = static_cast<double>(h->delta_f);
-  p.inv_delta_d = h->delta_f > 0 ? 1.0 / static_cast<double>(h->delta_f) : 0.0;
+  p.delta_d = g->wtype == SSSP_WEIGHT_U32 ? 0.0 : delta_of(h);
+  p.inv_delta_d = p.delta_d > 0 ? 1.0 / p.delta_d : 0.0;
   const size_t un = static_cast<size_t>(n), um = static_cast<size_t>(m);
   uint32_t *off = nullptr, *split = nullptr;
   uint64_t* edges = nullptr;
@@ -313,12 +358,14 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   uint32_t* vid = nullptr;
   SSSP_TRY(dalloc(&vid, un));
   p.vid = vid;
-  SSSP_TRY(dalloc(&p.tbuf[0], un));
-  SSSP_TRY(dalloc(&p.tbuf[1], un));
+  SSSP_TRY(hipMalloc(&p.tbuf[0], un * dist_bytes(g->wtype)));
+  SSSP_TRY(hipMalloc(&p.tbuf[1], un * dist_bytes(g->wtype)));
+  if (g->wtype == SSSP_WEIGHT_F64) SSSP_TRY(dalloc(&h->w64, um));
+  p.w64 = h->w64;
   uint32_t* build = nullptr;
   SSSP_TRY(dalloc(&build, sssp::build_scratch_words(n)));
-  hipError_t be = sssp::launch_relabel_and_split(g->row_ptr, g->col_idx, g->weights, g->wtype, n, m, h->delta_u,
-                                                 h->delta_f, build, vid, off, split, edges, h->perm, stream);
+  hipError_t be = sssp::launch_relabel_and_split(g->row_ptr, g->col_idx, g->weights, threshold_of(h), n, m, build, vid,
+                                                 off, split, edges, h->w64, h->perm, stream);
   if (be == hipSuccess) be = sssp::launch_pack_rows(off, split, n, rows, stream);
   if (be == hipSuccess) be = dalloc(&h->inv, un);
   if (be == hipSuccess) be = sssp::launch_inverse(vid, n, h->inv, stream);
@@ -351,16 +398,9 @@ sssp_status stage_sources(sssp_handle* h, const int32_t* sources, int32_t k, hip
   return SSSP_OK;
 }
 
-// fp32 bucket-range and ring-size rule shared by create and set_weights
-uint32_t ring_for(const sssp_handle* h, uint32_t wmax_bits) {
-  double span;
-  if (h->wtype == SSSP_WEIGHT_U32) {
-    span = static_cast<double>(wmax_bits) / static_cast<double>(h->delta_u);
-  } else {
-    float wmax;
-    std::memcpy(&wmax, &wmax_bits, sizeof(float));
-    span = static_cast<double>(wmax) / static_cast<double>(h->delta_f);
-  }
+// ring-size rule of set_weights (as in create)
+uint32_t ring_for(const sssp_handle* h, uint64_t wmax_bits) {
+  const double span = weight_of(h, wmax_bits) / delta_of(h);
   uint32_t ring = pow2_at_least(static_cast<uint32_t>(std::min(span + 2.0, 64.0)));
   return ring < 2 ? 2 : ring;
 }
@@ -442,14 +482,15 @@ sssp_status sssp_create(const sssp_graph* g, double delta, void* stream, sssp_ha
   if (!out) return SSSP_ERR_INVALID_ARGUMENT;
   *out = nullptr;
   if (!g || !g->row_ptr) return SSSP_ERR_INVALID_ARGUMENT;
-  if (g->wtype != SSSP_WEIGHT_U32 && g->wtype != SSSP_WEIGHT_F32) return SSSP_ERR_INVALID_ARGUMENT;
+  if (g->wtype != SSSP_WEIGHT_U32 && g->wtype != SSSP_WEIGHT_F32 && g->wtype != SSSP_WEIGHT_F64)
+    return SSSP_ERR_INVALID_ARGUMENT;
   if (g->n < 1 || g->m < 0) return SSSP_ERR_INVALID_ARGUMENT;
   if (g->n >= (int64_t(1) << 31) || g->m >= (int64_t(1) << 32) - 1) return SSSP_ERR_UNSUPPORTED;
   if (g->m > 0 && (!g->col_idx || !g->weights)) return SSSP_ERR_INVALID_ARGUMENT;
   if (!std::isfinite(delta) || !(delta > 0)) return SSSP_ERR_INVALID_ARGUMENT;
   if (g->wtype == SSSP_WEIGHT_U32) {
     if (delta != std::floor(delta) || delta < 1.0 || delta > 4294967295.0) return SSSP_ERR_INVALID_ARGUMENT;
-  } else {
+  } else if (g->wtype == SSSP_WEIGHT_F32) {
     const float df = static_cast<float>(delta);
     if (!std::isfinite(df) || !(df > 0.0f)) return SSSP_ERR_INVALID_ARGUMENT;
   }
@@ -561,26 +602,14 @@ sssp_status sssp_set_weights(sssp_handle* h, const void* weights, void* stream) 
   hipStream_t s = static_cast<hipStream_t>(stream);
   SSSP_TRY(hipSetDevice(h->device));
   if (h->m == 0) return SSSP_OK;
-  uint32_t* scratch = nullptr;  // [0] status, [1] max weight bits, [2..3] fp64 weight total
-  SSSP_TRY(dalloc(&scratch, 4));
-  hipError_t e = hipMemsetAsync(scratch, 0, 4 * sizeof(uint32_t), s);
-  if (e == hipSuccess)
-    e = sssp::launch_validate_weights(weights, h->wtype, h->m, scratch, scratch + 1,
-                                      reinterpret_cast<double*>(scratch + 2), s);
-  uint32_t res[4] = {0, 0, 0, 0};
-  if (e == hipSuccess) e = hipMemcpyAsync(res, scratch, sizeof(res), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(scratch);
-  SSSP_TRY(e);
-  if (res[0] & sssp::kBadWeight) return SSSP_ERR_INVALID_WEIGHT;
-  if (h->wtype == SSSP_WEIGHT_F32) {
-    double wsum;
-    std::memcpy(&wsum, res + 2, sizeof(double));
-    if (!f32_buckets_fit(wsum, h->n, h->delta_f)) return SSSP_ERR_UNSUPPORTED;
-  }
+  WeightStats ws{};
+  const sssp_status vs = validate_on_device(nullptr, nullptr, weights, h->wtype, h->n, h->m, s, &ws);
+  if (vs != SSSP_OK) return vs;
+  if (ws.status & sssp::kBadWeight) return SSSP_ERR_INVALID_WEIGHT;
+  if (!buckets_fit(h, ws.wsum)) return SSSP_ERR_UNSUPPORTED;
   sssp::Params& p = h->p;
   const size_t un = static_cast<size_t>(h->n), um = static_cast<size_t>(h->m);
-  const uint32_t ring = ring_for(h, res[1]);
+  const uint32_t ring = ring_for(h, ws.wmax_bits);
   if (ring > p.ring) {  // a larger weight spread needs more near buckets (in every group)
     SSSP_TRY(hipDeviceSynchronize());
     uint32_t* bins = nullptr;
@@ -598,27 +627,31 @@ sssp_status sssp_set_weights(sssp_handle* h, const void* weights, void* stream) 
   uint4* rows = nullptr;
   uint64_t* edges = nullptr;
   uint32_t* perm = nullptr;
-  if (dalloc(&rows, un) != hipSuccess || dalloc(&edges, um) != hipSuccess || dalloc(&perm, um) != hipSuccess) {
-    if (rows) (void)hipFree(rows);
-    if (edges) (void)hipFree(edges);
-    return SSSP_ERR_OUT_OF_MEMORY;
-  }
-  e = sssp::launch_resplit(static_cast<uint32_t>(h->n), p.rows, p.edges, h->perm, weights, h->wtype, h->delta_u,
-                           h->delta_f, rows, edges, perm, s);
+  uint64_t* w64 = nullptr;
+  hipError_t e = dalloc(&rows, un);
+  if (e == hipSuccess) e = dalloc(&edges, um);
+  if (e == hipSuccess) e = dalloc(&perm, um);
+  if (e == hipSuccess && h->wtype == SSSP_WEIGHT_F64) e = dalloc(&w64, um);
+  if (e == hipSuccess)
+    e = sssp::launch_resplit(static_cast<uint32_t>(h->n), p.rows, p.edges, h->perm, weights, threshold_of(h), rows,
+                             w64, edges, perm, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
-    (void)hipFree(rows);
-    (void)hipFree(edges);
-    (void)hipFree(perm);
+    void* mem[] = {rows, edges, perm, w64};
+    for (void* q : mem)
+      if (q) (void)hipFree(q);
     return from_hip(e);
   }
   (void)hipFree(const_cast<uint4*>(p.rows));
   (void)hipFree(const_cast<uint64_t*>(p.edges));
   (void)hipFree(h->perm);
+  if (h->w64) (void)hipFree(h->w64);
   p.rows = rows;
   p.edges = edges;
+  p.w64 = w64;
+  h->w64 = w64;
   h->perm = perm;
-  h->wmax_bits = res[1];
+  h->wmax_bits = ws.wmax_bits;
   p.no_heavy = no_heavy_for(h, h->wmax_bits);
   h->solved = false;  // distances of earlier solves used the old weights
   return upload_params(h);

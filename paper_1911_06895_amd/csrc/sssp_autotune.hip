@@ -16,13 +16,14 @@ namespace {
 // integer >= 1 for integer weights). Small deltas mean many buckets with
 // small phases; large ones mean light edges relaxed again and again.
 sssp_status derive_deltas(const sssp_graph* g, hipStream_t s, std::vector<double>* out) {
-  uint32_t* scratch = nullptr;  // [0] status, [1] max weight bits, [2..3] fp64 weight total
-  if (hipMalloc(reinterpret_cast<void**>(&scratch), 4 * sizeof(uint32_t)) != hipSuccess) return SSSP_ERR_OUT_OF_MEMORY;
-  hipError_t e = hipMemsetAsync(scratch, 0, 4 * sizeof(uint32_t), s);
+  uint32_t* scratch = nullptr;  // [0] status, [2..3] max weight bits, [4..5] fp64 weight total
+  if (hipMalloc(reinterpret_cast<void**>(&scratch), 6 * sizeof(uint32_t)) != hipSuccess) return SSSP_ERR_OUT_OF_MEMORY;
+  hipError_t e = hipMemsetAsync(scratch, 0, 6 * sizeof(uint32_t), s);
   if (e == hipSuccess)
-    e = sssp::launch_validate(g->row_ptr, g->col_idx, g->weights, g->wtype, g->n, g->m, scratch, scratch + 1,
-                              reinterpret_cast<double*>(scratch + 2), s);
-  uint32_t res[4] = {0, 0, 0, 0};
+    e = sssp::launch_validate(g->row_ptr, g->col_idx, g->weights, g->wtype, g->n, g->m, scratch,
+                              reinterpret_cast<unsigned long long*>(scratch + 2), reinterpret_cast<double*>(scratch + 4),
+                              s);
+  uint32_t res[6] = {0, 0, 0, 0, 0, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(res, scratch, sizeof(res), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(scratch);
@@ -30,12 +31,14 @@ sssp_status derive_deltas(const sssp_graph* g, hipStream_t s, std::vector<double
   if (res[0] & (sssp::kBadRowPtr | sssp::kBadCol)) return SSSP_ERR_INVALID_ARGUMENT;
   if (res[0] & sssp::kBadWeight) return SSSP_ERR_INVALID_WEIGHT;
   double wsum;
-  std::memcpy(&wsum, res + 2, sizeof(double));
+  std::memcpy(&wsum, res + 4, sizeof(double));
   const double mean = g->m > 0 ? wsum / static_cast<double>(g->m) : 1.0;
   const int c = static_cast<int>(std::floor(std::log2(mean)));
   out->clear();
   if (g->wtype == SSSP_WEIGHT_U32) {
-    const double wmax = static_cast<double>(res[1]);
+    uint64_t wmax_bits;
+    std::memcpy(&wmax_bits, res + 2, sizeof(wmax_bits));
+    const double wmax = static_cast<double>(wmax_bits);
     for (int j = c - 4; j <= c + 1; ++j) {
       const double d = std::ldexp(1.0, j);
       if (d >= 1.0 && (d <= wmax || out->empty())) out->push_back(d);

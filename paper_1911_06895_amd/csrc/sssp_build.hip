@@ -51,34 +51,9 @@ __device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t* total) {
   return before + inc - x;
 }
 
-// CSR and weight validation; max weight (as bits: positive floats order like
-// their bit patterns) and the fp32 weight total for the bucket-range check.
-__global__ __launch_bounds__(kB) void validate_kernel(const int64_t* rp, const int32_t* col, const uint32_t* wbits,
-                                                      int wtype, int64_t n, int64_t m, uint32_t* status,
-                                                      uint32_t* wmax_bits, double* wsum) {
-  uint32_t bad = 0, wmax = 0;
-  double sum = 0.0;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kB;
-  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
-  for (int64_t u = i0; u <= n; u += stride) {
-    const int64_t a = rp[u];
-    if (u == 0 && a != 0) bad |= kBadRowPtr;
-    if (u == n && a != m) bad |= kBadRowPtr;
-    if (u < n && rp[u + 1] < a) bad |= kBadRowPtr;
-  }
-  for (int64_t e = i0; e < m; e += stride) {
-    const int32_t c = col[e];
-    if (c < 0 || c >= n) bad |= kBadCol;
-    const uint32_t wb = wbits[e];
-    if (wtype == 0) {
-      if (wb == 0) bad |= kBadWeight;
-    } else {
-      // reject -0.0 and negatives (sign bit), +0.0, and inf/NaN (exponent all ones)
-      if ((wb & 0x80000000u) || wb == 0 || (wb & 0x7F800000u) == 0x7F800000u) bad |= kBadWeight;
-      else sum += static_cast<double>(__uint_as_float(wb));
-    }
-    wmax = max(wmax, wb);
-  }
+// Per-wave fold of the weight checks into the outputs.
+__device__ inline void fold_weights(uint32_t bad, unsigned long long wmax, double sum, uint32_t* status,
+                                    unsigned long long* wmax_bits, double* wsum) {
   for (int d = 32; d > 0; d >>= 1) {
     bad |= __shfl_down(bad, d);
     wmax = max(wmax, __shfl_down(wmax, d));
@@ -91,32 +66,47 @@ __global__ __launch_bounds__(kB) void validate_kernel(const int64_t* rp, const i
   }
 }
 
+// CSR and weight validation; the largest weight (as bits: positive floats
+// order like their bit patterns) and the weight total, for the bucket-range check.
+__global__ __launch_bounds__(kB) void validate_kernel(const int64_t* rp, const int32_t* col, const void* w,
+                                                      int wtype, int64_t n, int64_t m, uint32_t* status,
+                                                      unsigned long long* wmax_bits, double* wsum) {
+  uint32_t bad = 0;
+  unsigned long long wmax = 0;
+  double sum = 0.0;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kB;
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  for (int64_t u = i0; u <= n; u += stride) {
+    const int64_t a = rp[u];
+    if (u == 0 && a != 0) bad |= kBadRowPtr;
+    if (u == n && a != m) bad |= kBadRowPtr;
+    if (u < n && rp[u + 1] < a) bad |= kBadRowPtr;
+  }
+  for (int64_t e = i0; e < m; e += stride) {
+    const int32_t c = col[e];
+    if (c < 0 || c >= n) bad |= kBadCol;
+    const uint64_t wb = weight_bits(w, wtype, e);
+    if (!weight_ok(wb, wtype)) bad |= kBadWeight;
+    else sum += weight_value(wb, wtype);
+    wmax = max(wmax, static_cast<unsigned long long>(wb));
+  }
+  fold_weights(bad, wmax, sum, status, wmax_bits, wsum);
+}
+
 // weights only (used when a handle's weights are replaced)
-__global__ __launch_bounds__(kB) void validate_weights_kernel(const uint32_t* wbits, int wtype, int64_t m,
-                                                              uint32_t* status, uint32_t* wmax_bits, double* wsum) {
-  uint32_t bad = 0, wmax = 0;
+__global__ __launch_bounds__(kB) void validate_weights_kernel(const void* w, int wtype, int64_t m, uint32_t* status,
+                                                              unsigned long long* wmax_bits, double* wsum) {
+  uint32_t bad = 0;
+  unsigned long long wmax = 0;
   double sum = 0.0;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kB;
   for (int64_t e = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x; e < m; e += stride) {
-    const uint32_t wb = wbits[e];
-    if (wtype == 0) {
-      if (wb == 0) bad |= kBadWeight;
-    } else {
-      if ((wb & 0x80000000u) || wb == 0 || (wb & 0x7F800000u) == 0x7F800000u) bad |= kBadWeight;
-      else sum += static_cast<double>(__uint_as_float(wb));
-    }
-    wmax = max(wmax, wb);
+    const uint64_t wb = weight_bits(w, wtype, e);
+    if (!weight_ok(wb, wtype)) bad |= kBadWeight;
+    else sum += weight_value(wb, wtype);
+    wmax = max(wmax, static_cast<unsigned long long>(wb));
   }
-  for (int d = 32; d > 0; d >>= 1) {
-    bad |= __shfl_down(bad, d);
-    wmax = max(wmax, __shfl_down(wmax, d));
-    sum += __shfl_down(sum, d);
-  }
-  if (lane_id() == 0) {
-    if (bad) atomicOr(status, bad);
-    if (wmax) atomicMax(wmax_bits, wmax);
-    if (sum != 0.0) atomicAdd(wsum, sum);
-  }
+  fold_weights(bad, wmax, sum, status, wmax_bits, wsum);
 }
 
 __global__ __launch_bounds__(kB) void inverse_kernel(const uint32_t* vid, int64_t n, uint32_t* inv) {
@@ -256,12 +246,12 @@ __global__ __launch_bounds__(kB) void scan_apply_kernel(const uint32_t* in, int6
 // Light/heavy split (Sec. IV-A) with relabelling: one wave per original row u
 // writes row new_id[u] of the solver's CSR -- light edges (w <= delta) first,
 // heavy edges (w > delta) after, each group in the caller's order -- as packed
-// (new destination id | weight bits << 32) records; perm maps a position back
-// to the caller's edge index.
-__global__ __launch_bounds__(kB) void split_kernel(const int64_t* rp, const int32_t* col, const uint32_t* wbits,
-                                                   int wtype, int64_t n, uint32_t delta_u, float delta_f,
-                                                   const uint32_t* new_id, const uint32_t* off, uint32_t* split,
-                                                   uint64_t* edges, uint32_t* perm) {
+// (new destination id | weight bits << 32) records (fp64: the destination,
+// and the weight at the same position of w64); perm maps a position back to
+// the caller's edge index.
+__global__ __launch_bounds__(kB) void split_kernel(const int64_t* rp, const int32_t* col, const void* w, Threshold th,
+                                                   int64_t n, const uint32_t* new_id, const uint32_t* off,
+                                                   uint32_t* split, uint64_t* edges, uint64_t* w64, uint32_t* perm) {
   const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x) >> 6;
   const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * kB) >> 6;
   const uint32_t l = lane_id();
@@ -272,10 +262,7 @@ __global__ __launch_bounds__(kB) void split_kernel(const int64_t* rp, const int3
     uint32_t nlight = 0;
     for (int64_t x = b; x < e; x += 64) {
       bool light = false;
-      if (x + l < e) {
-        const uint32_t wb = wbits[x + l];
-        light = wtype == 0 ? wb <= delta_u : __uint_as_float(wb) <= delta_f;
-      }
+      if (x + l < e) light = is_light(weight_bits(w, th.wtype, x + l), th);
       nlight += static_cast<uint32_t>(__popcll(__ballot(light)));
     }
     if (l == 0) split[nu] = base + nlight;
@@ -283,17 +270,23 @@ __global__ __launch_bounds__(kB) void split_kernel(const int64_t* rp, const int3
     for (int64_t x = b; x < e; x += 64) {
       const bool in = x + l < e;
       bool light = false;
-      uint32_t wb = 0, c = 0;
+      uint64_t wb = 0;
+      uint32_t c = 0;
       if (in) {
-        wb = wbits[x + l];
+        wb = weight_bits(w, th.wtype, x + l);
         c = new_id[col[x + l]];
-        light = wtype == 0 ? wb <= delta_u : __uint_as_float(wb) <= delta_f;
+        light = is_light(wb, th);
       }
       const uint64_t ml = __ballot(in && light);
       const uint64_t mh = __ballot(in && !light);
       if (in) {
         const uint32_t pos = light ? lpos + lanes_below(ml) : hpos + lanes_below(mh);
-        edges[pos] = static_cast<uint64_t>(c) | (static_cast<uint64_t>(wb) << 32);
+        if (th.wtype == kWF64) {
+          edges[pos] = static_cast<uint64_t>(c);
+          w64[pos] = wb;
+        } else {
+          edges[pos] = static_cast<uint64_t>(c) | (wb << 32);
+        }
         perm[pos] = static_cast<uint32_t>(x + l);
       }
       lpos += static_cast<uint32_t>(__popcll(ml));
@@ -320,9 +313,9 @@ unsigned grid_for(int64_t work, int64_t cap) {
 }  // namespace
 
 hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, const void* w, int wtype, int64_t n,
-                           int64_t m, uint32_t* status, uint32_t* wmax_bits, double* wsum, hipStream_t s) {
-  hipLaunchKernelGGL(validate_kernel, dim3(grid_for(m > n + 1 ? m : n + 1, 8192)), dim3(kB), 0, s, row_ptr, col,
-                     static_cast<const uint32_t*>(w), wtype, n, m, status, wmax_bits, wsum);
+                           int64_t m, uint32_t* status, unsigned long long* wmax_bits, double* wsum, hipStream_t s) {
+  hipLaunchKernelGGL(validate_kernel, dim3(grid_for(m > n + 1 ? m : n + 1, 8192)), dim3(kB), 0, s, row_ptr, col, w,
+                     wtype, n, m, status, wmax_bits, wsum);
   return hipGetLastError();
 }
 
@@ -331,10 +324,10 @@ hipError_t launch_pack_rows(const uint32_t* off, const uint32_t* split, int64_t 
   return hipGetLastError();
 }
 
-hipError_t launch_validate_weights(const void* w, int wtype, int64_t m, uint32_t* status, uint32_t* wmax_bits,
-                                   double* wsum, hipStream_t s) {
-  hipLaunchKernelGGL(validate_weights_kernel, dim3(grid_for(m, 8192)), dim3(kB), 0, s,
-                     static_cast<const uint32_t*>(w), wtype, m, status, wmax_bits, wsum);
+hipError_t launch_validate_weights(const void* w, int wtype, int64_t m, uint32_t* status,
+                                   unsigned long long* wmax_bits, double* wsum, hipStream_t s) {
+  hipLaunchKernelGGL(validate_weights_kernel, dim3(grid_for(m, 8192)), dim3(kB), 0, s, w, wtype, m, status, wmax_bits,
+                     wsum);
   return hipGetLastError();
 }
 
@@ -348,10 +341,9 @@ size_t build_scratch_words(int64_t n) {
   return static_cast<size_t>(n) /* indeg, then renumbered out-degree */ + kDegClasses * 2 + tiles;
 }
 
-hipError_t launch_relabel_and_split(const int64_t* row_ptr, const int32_t* col, const void* w, int wtype, int64_t n,
-                                    int64_t m, uint32_t delta_u, float delta_f, uint32_t* scratch,
-                                    uint32_t* new_id, uint32_t* off, uint32_t* split, uint64_t* edges,
-                                    uint32_t* perm, hipStream_t s) {
+hipError_t launch_relabel_and_split(const int64_t* row_ptr, const int32_t* col, const void* w, const Threshold& th,
+                                    int64_t n, int64_t m, uint32_t* scratch, uint32_t* new_id, uint32_t* off,
+                                    uint32_t* split, uint64_t* edges, uint64_t* w64, uint32_t* perm, hipStream_t s) {
   uint32_t* indeg = scratch;               // [n]
   uint32_t* hist = scratch + n;            // [kDegClasses]
   uint32_t* cursor = hist + kDegClasses;   // [kDegClasses]
@@ -370,8 +362,7 @@ hipError_t launch_relabel_and_split(const int64_t* row_ptr, const int32_t* col, 
   hipLaunchKernelGGL(scan_apply_kernel, dim3(ntiles), dim3(kB), 0, s, indeg, n, tiles, off);
   const int64_t waves_blocks = (n * 64 + kB - 1) / kB;
   hipLaunchKernelGGL(split_kernel, dim3(static_cast<unsigned>(waves_blocks > 16384 ? 16384 : waves_blocks)),
-                     dim3(kB), 0, s, row_ptr, col, static_cast<const uint32_t*>(w), wtype, n, delta_u, delta_f,
-                     new_id, off, split, edges, perm);
+                     dim3(kB), 0, s, row_ptr, col, w, th, n, new_id, off, split, edges, w64, perm);
   (void)m;
   return hipGetLastError();
 }

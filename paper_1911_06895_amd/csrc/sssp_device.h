@@ -107,20 +107,29 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t* total, uin
 
 // ------------------------------------------------------------------ weights
 
-// x (+) w in the weight type, and the bucket index floor(x / delta).
+// x (+) w in the weight type, the bucket index floor(x / delta), and the
+// weight of the edge record at position pos. T: the distance bits; Wt: the
+// weight bits.
 struct WeightU32 {
-  static constexpr uint32_t kInf = kInfU32;
-  __device__ static bool add(uint32_t t, uint32_t w, uint32_t* out) {
+  static constexpr bool kInteger = true;
+  using T = uint32_t;
+  using Wt = uint32_t;
+  static constexpr T kInf = kInfU32;
+  __device__ static bool add(T t, Wt w, T* out) {
     const uint64_t s = static_cast<uint64_t>(t) + static_cast<uint64_t>(w);
     *out = static_cast<uint32_t>(s);
     return s <= 0xFFFFFFFEull;  // 2^32-1 is reserved for "unreachable"
   }
-  __device__ static uint32_t bucket(uint32_t x, const Params& p) { return x / p.delta_u; }
+  __device__ static uint32_t bucket(T x, const Params& p) { return x / p.delta_u; }
+  __device__ static Wt weight(const Params&, uint64_t rec, uint32_t) { return static_cast<Wt>(rec >> 32); }
 };
 
 struct WeightF32 {
-  static constexpr uint32_t kInf = kInfF32;
-  __device__ static bool add(uint32_t t, uint32_t w, uint32_t* out) {
+  static constexpr bool kInteger = false;
+  using T = uint32_t;
+  using Wt = uint32_t;
+  static constexpr T kInf = kInfF32;
+  __device__ static bool add(T t, Wt w, T* out) {
     const float s = __fadd_rn(__uint_as_float(t), __uint_as_float(w));
     *out = __float_as_uint(s);
     return *out < kInfF32;  // non-negative operands: the sum is finite or +inf
@@ -129,13 +138,37 @@ struct WeightF32 {
   // estimate from one rounded product is off by at most one, and the sign of
   // j*delta - x is exact in a fused multiply-add (one rounding of an exact
   // value, which is zero only when the value is), for every j below 2^32.
-  __device__ static uint32_t bucket(uint32_t x, const Params& p) {
+  __device__ static uint32_t bucket(T x, const Params& p) {
     const double d = static_cast<double>(__uint_as_float(x));
     double j = floor(d * p.inv_delta_d);
     if (fma(j, p.delta_d, -d) > 0.0) j -= 1.0;
     else if (fma(j + 1.0, p.delta_d, -d) <= 0.0) j += 1.0;
     return static_cast<uint32_t>(j);
   }
+  __device__ static Wt weight(const Params&, uint64_t rec, uint32_t) { return static_cast<Wt>(rec >> 32); }
+};
+
+struct WeightF64 {
+  static constexpr bool kInteger = false;
+  using T = uint64_t;
+  using Wt = uint64_t;
+  static constexpr T kInf = kInfF64;
+  __device__ static bool add(T t, Wt w, T* out) {
+    const double s = __dadd_rn(__longlong_as_double(static_cast<long long>(t)),
+                               __longlong_as_double(static_cast<long long>(w)));
+    *out = static_cast<uint64_t>(__double_as_longlong(s));
+    return *out < kInfF64;
+  }
+  // floor(x / delta) exactly, as for fp32 (the sign of the fused j*delta - x
+  // is exact: subnormals keep any nonzero difference of doubles nonzero)
+  __device__ static uint32_t bucket(T x, const Params& p) {
+    const double d = __longlong_as_double(static_cast<long long>(x));
+    double j = floor(d * p.inv_delta_d);
+    if (fma(j, p.delta_d, -d) > 0.0) j -= 1.0;
+    else if (fma(j + 1.0, p.delta_d, -d) <= 0.0) j += 1.0;
+    return static_cast<uint32_t>(j);
+  }
+  __device__ static Wt weight(const Params& p, uint64_t, uint32_t pos) { return ldg(&p.w64[pos]); }
 };
 
 // ------------------------------------------------------------------ barrier

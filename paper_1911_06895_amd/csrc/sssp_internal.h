@@ -21,11 +21,49 @@ constexpr uint32_t kMaxGroups = 256;   // concurrent sources of one launch (work
 constexpr uint32_t kEpochLimit = 1u << 30;  // de-duplication tags are reset before they pass this
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
-// Tentative distances are kept as 32-bit patterns: uint32 values for integer
-// weights, and for fp32 weights the IEEE bits of non-negative floats, which
-// order exactly like the floats themselves (+0.0 = 0, +inf = 0x7F800000).
+// Tentative distances are kept as unsigned bit patterns: uint32 values for
+// integer weights, and for fp32 (fp64) weights the IEEE bits of non-negative
+// floats, which order exactly like the floats themselves (+0.0 = 0, +inf =
+// 0x7F800000, resp. 0x7FF0000000000000).
 constexpr uint32_t kInfU32 = 0xFFFFFFFFu;
 constexpr uint32_t kInfF32 = 0x7F800000u;
+constexpr uint64_t kInfF64 = 0x7FF0000000000000ull;
+
+enum WeightType : int { kWU32 = 0, kWF32 = 1, kWF64 = 2 };
+
+// The light/heavy threshold delta in the weight type's own terms.
+struct Threshold {
+  int wtype;
+  uint32_t delta_u;  // integer weights
+  float delta_f;     // fp32 weights
+  double delta_d;    // fp64 weights
+};
+
+// Weight e of a caller array as bits (zero-extended for 32-bit types).
+__device__ inline uint64_t weight_bits(const void* w, int wtype, int64_t e) {
+  return wtype == kWF64 ? static_cast<const uint64_t*>(w)[e] : static_cast<uint64_t>(static_cast<const uint32_t*>(w)[e]);
+}
+
+// A usable weight: integers >= 1; floats finite and > 0 (no sign bit, not
+// +0.0, exponent not all ones).
+__device__ inline bool weight_ok(uint64_t wb, int wtype) {
+  if (wtype == kWU32) return wb != 0;
+  if (wtype == kWF32) return !((wb & 0x80000000u) || wb == 0 || (wb & 0x7F800000u) == 0x7F800000u);
+  return !((wb >> 63) || wb == 0 || ((wb >> 52) & 0x7FFu) == 0x7FFu);
+}
+
+__device__ inline double weight_value(uint64_t wb, int wtype) {
+  if (wtype == kWU32) return static_cast<double>(wb);
+  if (wtype == kWF32) return static_cast<double>(__uint_as_float(static_cast<uint32_t>(wb)));
+  return __longlong_as_double(static_cast<long long>(wb));
+}
+
+// light: w <= delta (A_L = A o (0 < A <= delta), Sec. IV-A)
+__device__ inline bool is_light(uint64_t wb, const Threshold& th) {
+  if (th.wtype == kWU32) return wb <= th.delta_u;
+  if (th.wtype == kWF32) return __uint_as_float(static_cast<uint32_t>(wb)) <= th.delta_f;
+  return __longlong_as_double(static_cast<long long>(wb)) <= th.delta_d;
+}
 
 enum Action : uint32_t {
   kActLight = 1,  // light phase over the current frontier
@@ -93,12 +131,13 @@ struct Params {
   uint32_t ring_mask;
   uint32_t wtype;       // 0 = u32, 1 = f32
   uint32_t delta_u;     // u32 delta
-  double delta_d;       // f32: (double)(float)delta
-  double inv_delta_d;   // f32: 1 / delta_d (an estimate; bucket indices are corrected exactly)
+  double delta_d;       // f32: (double)(float)delta; f64: delta
+  double inv_delta_d;   // 1 / delta_d (an estimate; bucket indices are corrected exactly)
   const uint32_t* vid;    // [n] solver id of each caller vertex (decreasing in-degree order)
-  uint32_t* tbuf[2];      // [n] tentative distances in solver ids (alternating between sources)
+  void* tbuf[2];          // [n] tentative distances (32- or 64-bit) in solver ids (alternating between sources)
   const uint4* rows;      // [n] row u of the split copy: (start, end of light edges, end, 0)
-  const uint64_t* edges;  // [m] (destination | weight bits << 32)
+  const uint64_t* edges;  // [m] (destination | weight bits << 32); fp64: destination only
+  const uint64_t* w64;    // [m] fp64 weight bits at the same positions (fp64 handles)
   uint32_t* qstamp;       // [n] frontier tag of the last push
   uint32_t* sstamp;       // [n] round tag of the last S insertion
   uint32_t* bstamp;       // [n] lowest bucket a vertex was filed under (this solve)
@@ -142,18 +181,18 @@ hipError_t launch_adjoint(const AdjParams& a, const int32_t* sources, int k, con
 hipError_t launch_count_reached(const uint32_t* dist, uint32_t n, int k, int wtype, unsigned long long* out,
                                 hipStream_t s);
 hipError_t launch_resplit(uint32_t n, const uint4* rows_in, const uint64_t* edges_in, const uint32_t* perm_in,
-                          const void* w, int wtype, uint32_t delta_u, float delta_f, uint4* rows_out,
+                          const void* w, const Threshold& th, uint4* rows_out, uint64_t* w64_out,
                           uint64_t* edges_out, uint32_t* perm_out, hipStream_t s);
 hipError_t launch_inverse(const uint32_t* vid, int64_t n, uint32_t* inv, hipStream_t s);
-hipError_t launch_validate_weights(const void* w, int wtype, int64_t m, uint32_t* status, uint32_t* wmax_bits,
+hipError_t launch_validate_weights(const void* w, int wtype, int64_t m, uint32_t* status, unsigned long long* wmax_bits,
                                    double* wsum, hipStream_t s);
 hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, const void* w, int wtype, int64_t n,
-                           int64_t m, uint32_t* status, uint32_t* wmax_bits, double* wsum, hipStream_t s);
+                           int64_t m, uint32_t* status, unsigned long long* wmax_bits, double* wsum, hipStream_t s);
 size_t build_scratch_words(int64_t n);
-hipError_t launch_relabel_and_split(const int64_t* row_ptr, const int32_t* col, const void* w, int wtype, int64_t n,
-                                    int64_t m, uint32_t delta_u, float delta_f, uint32_t* scratch,
+hipError_t launch_relabel_and_split(const int64_t* row_ptr, const int32_t* col, const void* w, const Threshold& th,
+                                    int64_t n, int64_t m, uint32_t* scratch,
                                     uint32_t* new_id, uint32_t* off, uint32_t* split, uint64_t* edges,
-                                    uint32_t* perm, hipStream_t s);
+                                    uint64_t* w64, uint32_t* perm, hipStream_t s);
 hipError_t solver_occupancy(int wtype, int* blocks_per_cu);
 hipError_t launch_pack_rows(const uint32_t* off, const uint32_t* split, int64_t n, uint4* rows, hipStream_t s);
 hipError_t launch_ctl_reset(Ctl* c, uint32_t groups, int reset_epochs, unsigned long long* trace, uint32_t trace_cap,
@@ -163,7 +202,7 @@ hipError_t launch_fill(uint32_t* p, size_t count, uint32_t value, hipStream_t s)
 // groups. multi = 0: row r of dist holds the distances from sources[r]; multi =
 // 1: one row, the distances from the nearest of the k sources.
 hipError_t launch_solver(const Params* params, uint32_t groups, uint32_t wtype, const int32_t* sources, int k,
-                         int multi, uint32_t* dist, int grid, hipStream_t s);
+                         int multi, void* dist, int grid, hipStream_t s);
 
 // validation status bits
 enum : uint32_t {

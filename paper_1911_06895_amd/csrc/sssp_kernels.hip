@@ -41,14 +41,9 @@ struct Sched {
 
 // i*delta <= x < (i+1)*delta for the current bucket i
 template <class W>
-__device__ inline bool in_bucket(uint32_t x, const Sched& s, const Params& p);
-template <>
-__device__ inline bool in_bucket<WeightU32>(uint32_t x, const Sched& s, const Params&) {
-  return x >= s.lo_u && x < s.hi_u;
-}
-template <>
-__device__ inline bool in_bucket<WeightF32>(uint32_t x, const Sched& s, const Params& p) {
-  return WeightF32::bucket(x, p) == s.bucket;
+__device__ inline bool in_bucket(typename W::T x, const Sched& s, const Params& p) {
+  if constexpr (W::kInteger) return x >= s.lo_u && x < s.hi_u;
+  else return W::bucket(x, p) == s.bucket;
 }
 
 // Every workgroup's copy of the schedule the leader published. The loads are
@@ -287,10 +282,10 @@ __device__ void stage_flush(const Params& p, const Sched& s, Stage& sg, bool for
 // Sec. IV-C), into the ring of near buckets, or into the far list. The loads and
 // atomics of the kILP requests are independent and overlap in flight.
 template <class W>
-__device__ inline void relax_batch(const Params& p, uint32_t* t, const Sched& s, const bool (&active)[kILP],
-                                   const uint32_t (&tu)[kILP], const uint32_t (&v)[kILP],
-                                   const uint32_t (&w)[kILP], uint64_t near_end, WgStats& st, Stage& sg) {
-  uint32_t cand[kILP], tv[kILP];
+__device__ inline void relax_batch(const Params& p, typename W::T* t, const Sched& s, const bool (&active)[kILP],
+                                   const typename W::T (&tu)[kILP], const uint32_t (&v)[kILP],
+                                   const typename W::Wt (&w)[kILP], uint64_t near_end, WgStats& st, Stage& sg) {
+  typename W::T cand[kILP], tv[kILP];
   bool ok[kILP], win[kILP];
 #pragma unroll
   for (uint32_t q = 0; q < kILP; ++q) {
@@ -299,7 +294,7 @@ __device__ inline void relax_batch(const Params& p, uint32_t* t, const Sched& s,
       st_agent(&p.ovf_at[v[q]], 1u);
       st_agent(&p.ctl->ovf_seen, 1u);
     }
-    tv[q] = ok[q] ? ldg(&t[v[q]]) : 0u;  // may be stale, but never below the current value
+    tv[q] = ok[q] ? ldg(&t[v[q]]) : typename W::T(0);  // may be stale, but never below the current value
   }
 #pragma unroll
   for (uint32_t q = 0; q < kILP; ++q) win[q] = ok[q] && cand[q] < tv[q] && cand[q] < g_min(&t[v[q]], cand[q]);
@@ -370,17 +365,20 @@ __device__ inline uint32_t chunk_for(uint32_t count, uint32_t size) {
 
 // Entry threadIdx.x of a step's input list, already loaded by the leader
 // (steps it runs alone): the vertex, its tentative distance and its row.
+template <class T>
 struct Entry {
-  uint32_t u, tu;
+  uint32_t u;
+  T tu;
   uint4 row;
 };
 
 template <class W, bool kLight>
-__device__ void phase(const Params& p, uint32_t* t, const Sched& s, WgStats& st, Stage& sg, bool solo,
-                      bool preloaded = false, Entry pre = Entry{}) {
+__device__ void phase(const Params& p, typename W::T* t, const Sched& s, WgStats& st, Stage& sg, bool solo,
+                      bool preloaded = false, Entry<typename W::T> pre = Entry<typename W::T>{}) {
+  using T = typename W::T;
   __shared__ uint32_t s_pref[kChunk];
   __shared__ uint32_t s_beg[kChunk];
-  __shared__ uint32_t s_tu[kChunk];
+  __shared__ T s_tu[kChunk];
   __shared__ uint32_t s_wsum[kWG / 64];
   __shared__ uint32_t s_claim;
 
@@ -394,7 +392,8 @@ __device__ void phase(const Params& p, uint32_t* t, const Sched& s, WgStats& st,
 
   for (uint32_t c = solo ? 0u : grp_rank(p); c < nchunks; c = claim_next(p.ctl, c, nchunks, solo, size, &s_claim)) {
     const uint32_t k = c * chunk + threadIdx.x;
-    uint32_t beg = 0, deg = 0, tu = W::kInf, u = 0;
+    uint32_t beg = 0, deg = 0, u = 0;
+    T tu = W::kInf;
     bool take = false;
     if (threadIdx.x < chunk && k < count) {
       u = preloaded ? pre.u : ld_agent(&list[k]);
@@ -443,7 +442,9 @@ __device__ void phase(const Params& p, uint32_t* t, const Sched& s, WgStats& st,
     const uint32_t rounds = (total + kWG * kILP - 1) / (kWG * kILP);
     for (uint32_t r = 0; r < rounds; ++r) {
       bool active[kILP];
-      uint32_t v[kILP], w[kILP], tw[kILP];
+      uint32_t v[kILP];
+      typename W::Wt w[kILP];
+      T tw[kILP];
 #pragma unroll
       for (uint32_t q = 0; q < kILP; ++q) {
         const uint32_t e = (r * kILP + q) * kWG + threadIdx.x;
@@ -458,9 +459,10 @@ __device__ void phase(const Params& p, uint32_t* t, const Sched& s, WgStats& st,
             if (s_pref[mid] <= e) lo = mid;
             else hi = mid - 1;
           }
-          const uint64_t ed = ldg(&p.edges[s_beg[lo] + (e - s_pref[lo])]);
+          const uint32_t pos = s_beg[lo] + (e - s_pref[lo]);
+          const uint64_t ed = ldg(&p.edges[pos]);
           v[q] = static_cast<uint32_t>(ed);
-          w[q] = static_cast<uint32_t>(ed >> 32);
+          w[q] = W::weight(p, ed, pos);
           tw[q] = s_tu[lo];
         }
       }
@@ -475,8 +477,10 @@ __device__ void phase(const Params& p, uint32_t* t, const Sched& s, WgStats& st,
 // Hub step: pieces of kPiece consecutive edges of the high-degree vertices
 // queued by the previous phase, spread over all workgroups.
 template <class W>
-__device__ void hub_step(const Params& p, uint32_t* t, const Sched& s, WgStats& st, Stage& sg) {
-  __shared__ uint32_t s_beg, s_end, s_tu, s_claim;
+__device__ void hub_step(const Params& p, typename W::T* t, const Sched& s, WgStats& st, Stage& sg) {
+  using T = typename W::T;
+  __shared__ uint32_t s_beg, s_end, s_claim;
+  __shared__ T s_tu;
   const bool light = s.hub_parent == kActLight;
   const uint32_t count = s.hub_count < p.hub_cap ? s.hub_count : p.hub_cap;
   const uint64_t near_end = static_cast<uint64_t>(s.bucket) + p.ring;  // no wrap near 2^32
@@ -496,7 +500,9 @@ __device__ void hub_step(const Params& p, uint32_t* t, const Sched& s, WgStats& 
     }
     __syncthreads();
     bool active[kILP];
-    uint32_t v[kILP], w[kILP], tw[kILP];
+    uint32_t v[kILP];
+    typename W::Wt w[kILP];
+    T tw[kILP];
 #pragma unroll
     for (uint32_t q = 0; q < kILP; ++q) {
       const uint32_t e = s_beg + q * kWG + threadIdx.x;
@@ -507,7 +513,7 @@ __device__ void hub_step(const Params& p, uint32_t* t, const Sched& s, WgStats& 
       if (active[q]) {
         const uint64_t ed = ldg(&p.edges[e]);
         v[q] = static_cast<uint32_t>(ed);
-        w[q] = static_cast<uint32_t>(ed >> 32);
+        w[q] = W::weight(p, ed, e);
       }
     }
     relax_batch<W>(p, t, s, active, tw, v, w, near_end, st, sg);
@@ -519,7 +525,7 @@ __device__ void hub_step(const Params& p, uint32_t* t, const Sched& s, WgStats& 
 // Far-list redistribution: far vertices whose bucket is now within the ring
 // move into it; the rest move to the other far list.
 template <class W>
-__device__ void far_step(const Params& p, uint32_t* t, const Sched& s) {
+__device__ void far_step(const Params& p, typename W::T* t, const Sched& s) {
   const uint32_t count = s.in_count;
   const uint32_t* list = p.far[s.far_cur];
   const uint32_t nxt = 1u - s.far_cur;
@@ -551,7 +557,7 @@ __device__ void far_step(const Params& p, uint32_t* t, const Sched& s) {
 // A candidate that did not fit marked its target; the distance of that target
 // is unrepresentable exactly when no other path reached it.
 template <class W>
-__device__ void overflow_step(const Params& p, uint32_t* t) {
+__device__ void overflow_step(const Params& p, typename W::T* t) {
   for (uint32_t v = grp_rank(p) * kWG + threadIdx.x; v < p.n; v += grp_size(p) * kWG) {
     if (ld_agent(&p.ovf_at[v])) {
       if (ld_agent(&t[v]) == W::kInf) st_agent(&p.ctl->ovf_real, 1u);
@@ -611,7 +617,7 @@ __device__ void choose_next(const Params& p, Sched* s, const Counters& k, uint32
 // is left in *s and published. `reset_tags`: the group's stamps were just
 // cleared, so the de-duplication tags restart.
 template <class W>
-__device__ void leader_start(const Params& p, uint32_t* t, const int32_t* seeds, int nseeds, bool reset_tags,
+__device__ void leader_start(const Params& p, typename W::T* t, const int32_t* seeds, int nseeds, bool reset_tags,
                              Sched* s) {
   Ctl* c = p.ctl;
   if (threadIdx.x < kRingMax) st_agent(&c->bincount[threadIdx.x], 0u);
@@ -648,7 +654,7 @@ __device__ void leader_start(const Params& p, uint32_t* t, const int32_t* seeds,
       continue;
     }
     const uint32_t u = ldg(&p.vid[src]);
-    st_agent(&t[u], 0u);
+    st_agent(&t[u], typename W::T(0));
     if (g_min(&p.bstamp[u], 0u) != 0u) st_agent(&p.bins[g_add(&c->bincount[0], 1u)], u);
   }
   drain_stores();
@@ -753,8 +759,8 @@ __device__ void after_step(const Params& p, Sched* s) {
 
 // Edges a light or heavy step would scan (its list has at most kWG entries);
 // each thread keeps its entry for the phase that may follow on this workgroup.
-template <bool kLight>
-__device__ uint32_t step_edges(const Params& p, const uint32_t* t, const Sched& s, uint32_t* s_wsum, Entry* e) {
+template <bool kLight, class T>
+__device__ uint32_t step_edges(const Params& p, const T* t, const Sched& s, uint32_t* s_wsum, Entry<T>* e) {
   const uint32_t* list = phase_list(p, s, kLight);
   uint32_t deg = 0;
   if (threadIdx.x < s.in_count) {
@@ -771,13 +777,13 @@ __device__ uint32_t step_edges(const Params& p, const uint32_t* t, const Sched& 
 // The leader's part of a barrier: schedule the step after `s`; while that step
 // is a small light or heavy phase, run it on this workgroup alone and schedule again.
 template <class W>
-__device__ void lead(const Params& p, uint32_t* t, Sched* s, WgStats& st, Stage& sg, bool schedule_first) {
+__device__ void lead(const Params& p, typename W::T* t, Sched* s, WgStats& st, Stage& sg, bool schedule_first) {
   __shared__ uint32_t s_wsum[kWG / 64];
   if (schedule_first) after_step<W>(p, s);
   for (;;) {  // *s is the current schedule (set by leader_start or after_step)
     const bool light = s->action == kActLight;
     if (!(light || s->action == kActHeavy) || s->in_count > static_cast<uint32_t>(kChunk)) break;
-    Entry e{};
+    Entry<typename W::T> e{};
     const uint32_t edges = light ? step_edges<true>(p, t, *s, s_wsum, &e) : step_edges<false>(p, t, *s, s_wsum, &e);
     if (edges > p.inline_edges) break;
     drain_stores();  // the counter resets of after_step land before this step's appends
@@ -796,7 +802,7 @@ __device__ void lead(const Params& p, uint32_t* t, Sched* s, WgStats& st, Stage&
 // the batch and initialise its solve, or mark the group finished. A row is one
 // source, or (multi) all k sources at once in a single row.
 template <class W>
-__device__ void leader_claim(const Params& p, uint32_t* t, const int32_t* sources, int k, int multi, bool reset_tags,
+__device__ void leader_claim(const Params& p, typename W::T* t, const int32_t* sources, int k, int multi, bool reset_tags,
                              Sched* s, WgStats& st, Stage& sg) {
   __shared__ uint32_t s_row;
   Ctl* c = p.ctl;
@@ -815,7 +821,8 @@ __device__ void leader_claim(const Params& p, uint32_t* t, const int32_t* source
 
 template <class W>
 __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ params, uint32_t groups,
-                                                     const int32_t* sources, int k, int multi, uint32_t* dist) {
+                                                     const int32_t* sources, int k, int multi, void* dist) {
+  using T = typename W::T;
   __shared__ Sched s;
   __shared__ Stage sg;
   __shared__ uint32_t s_row;
@@ -835,7 +842,7 @@ __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ 
                             ld_agent(&c->far_epoch) > kEpochLimit;
     // distances live in solver ids; a group's consecutive sources alternate
     // buffers so that copying out one row never races with initialising the next
-    uint32_t* t = p.tbuf[it & 1];
+    T* t = static_cast<T*>(p.tbuf[it & 1]);
     for (uint32_t v = rank * kWG + threadIdx.x; v < p.n; v += size * kWG) {
       st_agent(&t[v], W::kInf);
       st_agent(&p.bstamp[v], kNone);
@@ -864,7 +871,7 @@ __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ 
       alive = grid_sync(c, size, rank, [&] { lead<W>(p, t, &s, st, sg, true); });
     }
     if (alive) {  // the source's row of the output, in the caller's vertex numbering
-      uint32_t* out = dist + static_cast<size_t>(row) * p.n;
+      T* out = static_cast<T*>(dist) + static_cast<size_t>(row) * p.n;
       for (uint32_t v = rank * kWG + threadIdx.x; v < p.n; v += size * kWG) *gp(&out[v]) = ld_agent(&t[ldg(&p.vid[v])]);
     }
   }
@@ -938,25 +945,27 @@ hipError_t launch_fill(uint32_t* p, size_t count, uint32_t value, hipStream_t s)
 }
 
 hipError_t solver_occupancy(int wtype, int* blocks_per_cu) {
-  return wtype == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solver_kernel<WeightU32>, kWG, 0)
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solver_kernel<WeightF32>, kWG, 0);
+  if (wtype == kWU32) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solver_kernel<WeightU32>, kWG, 0);
+  if (wtype == kWF32) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solver_kernel<WeightF32>, kWG, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solver_kernel<WeightF64>, kWG, 0);
 }
 
 // One cooperative launch (every workgroup co-resident, which the barriers
 // need). While the stream is being captured into a graph, the launch-attribute
 // form records a cooperative kernel node.
 hipError_t launch_solver(const Params* params, uint32_t groups, uint32_t wtype, const int32_t* sources, int k,
-                         int multi, uint32_t* dist, int grid, hipStream_t s) {
+                         int multi, void* dist, int grid, hipStream_t s) {
   if (groups < 1 || groups > kMaxGroups || grid < 1 || grid % static_cast<int>(groups) != 0) return hipErrorInvalidValue;
   const Params* pp = params;
   uint32_t gg = groups;
   const int32_t* src = sources;
   int kk = k;
   int mm = multi;
-  uint32_t* d = dist;
+  void* d = dist;
   void* args[] = {&pp, &gg, &src, &kk, &mm, &d};
-  const void* fn = wtype == 0 ? reinterpret_cast<const void*>(solver_kernel<WeightU32>)
-                              : reinterpret_cast<const void*>(solver_kernel<WeightF32>);
+  const void* fn = wtype == kWU32   ? reinterpret_cast<const void*>(solver_kernel<WeightU32>)
+                   : wtype == kWF32 ? reinterpret_cast<const void*>(solver_kernel<WeightF32>)
+                                    : reinterpret_cast<const void*>(solver_kernel<WeightF64>);
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   const hipError_t e = hipStreamIsCapturing(s, &cap);
   if (e != hipSuccess) return e;

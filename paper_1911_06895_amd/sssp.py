@@ -25,6 +25,7 @@ SSSP_ERR_UNSUPPORTED = 7
 
 SSSP_WEIGHT_U32 = 0
 SSSP_WEIGHT_F32 = 1
+SSSP_WEIGHT_F64 = 2
 
 EXPORTS = ("sssp_create", "sssp_solve", "sssp_solve_async", "sssp_solve_multi", "sssp_solve_multi_async",
            "sssp_solve_status", "sssp_backward", "sssp_set_weights", "sssp_last_stats", "sssp_set_tuning",
@@ -132,8 +133,10 @@ def _graph(row_ptr, col_idx, weights) -> SsspGraph:
         wtype = SSSP_WEIGHT_U32
     elif weights.dtype == torch.float32:
         wtype = SSSP_WEIGHT_F32
+    elif weights.dtype == torch.float64:
+        wtype = SSSP_WEIGHT_F64
     else:
-        raise TypeError(f"weights must be uint32 (or int32 bit patterns) or float32, got {weights.dtype}")
+        raise TypeError(f"weights must be uint32 (or int32 bit patterns), float32 or float64, got {weights.dtype}")
     if row_ptr.dtype != torch.int64 or col_idx.dtype != torch.int32:
         raise TypeError("row_ptr must be int64 and col_idx int32")
     for t in (row_ptr, col_idx, weights):
@@ -161,8 +164,8 @@ def sssp_autotune(row_ptr, col_idx, weights, sources, dist, multi: bool = False,
     scratch ([k, n], or [n] when multi). Returns (handle, result dict)."""
     g = _graph(row_ptr, col_idx, weights)
     src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32).reshape(-1))
-    if not dist.is_cuda or not dist.is_contiguous() or dist.element_size() != 4:
-        raise ValueError("dist must be a contiguous 4-byte GPU tensor")
+    if not dist.is_cuda or not dist.is_contiguous() or dist.element_size() != (8 if g.wtype == SSSP_WEIGHT_F64 else 4):
+        raise ValueError("dist must be a contiguous GPU tensor of the weights' element size")
     if dist.numel() < (1 if multi else src.size) * g.n:
         raise ValueError("dist is too small")
     d = None if deltas is None else np.ascontiguousarray(np.asarray(deltas, dtype=np.float64))
@@ -177,10 +180,11 @@ def sssp_autotune(row_ptr, col_idx, weights, sources, dist, multi: bool = False,
 
 
 def _check_rows(handle, dist, k: int) -> None:
-    """The library writes k rows of n 4-byte distances into dist."""
-    n = sssp_graph_info(handle)[0]
-    if dist.element_size() != 4 or dist.numel() < k * n:
-        raise ValueError(f"dist must hold [k={k}, n={n}] 4-byte elements")
+    """The library writes k rows of n distances (4 bytes, 8 for float64 graphs) into dist."""
+    n, _, wtype = sssp_graph_info(handle)
+    size = 8 if wtype == SSSP_WEIGHT_F64 else 4
+    if dist.element_size() != size or dist.numel() < k * n:
+        raise ValueError(f"dist must hold [k={k}, n={n}] {size}-byte elements")
 
 
 def sssp_solve(handle, sources, dist, stream=None) -> None:
@@ -312,9 +316,9 @@ class DeltaStepping:
         if w.dtype == np.uint32:
             wt = torch.from_numpy(w.view(np.int32)).to(device)
             self.out_dtype = torch.int32  # uint32 bit patterns
-        elif w.dtype == np.float32:
+        elif w.dtype in (np.float32, np.float64):
             wt = torch.from_numpy(w).to(device)
-            self.out_dtype = torch.float32
+            self.out_dtype = wt.dtype
         else:
             raise TypeError(f"unsupported weight dtype {w.dtype}")
         rp = torch.from_numpy(np.ascontiguousarray(row_ptr, dtype=np.int64)).to(device)

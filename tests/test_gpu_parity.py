@@ -21,7 +21,11 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU-only hosts
 
 
 def _bits(a):
-    return a.view(np.uint32) if a.dtype == np.float32 else a
+    if a.dtype == np.float32:
+        return a.view(np.uint32)
+    if a.dtype == np.float64:
+        return a.view(np.uint64)
+    return a
 
 
 def gpu_solve(g, delta, sources, tuning=None):
@@ -279,3 +283,56 @@ def test_grid_4096_many_buckets():
     assert oracle.certify(g, 0, got[0]) == oracle.CERT_OK
     assert_exact(g, got[0], 0, "grid4096 delta=400")
     assert st["buckets"] >= len(np.unique(got[0] // 400))
+
+
+# ---------------------------------------------------------------- fp64 weights (the paper's GrB_FP64)
+
+@pytest.mark.parametrize("delta", [0.25, 1.0, 7.5])
+def test_fp64_rmat_exact(delta):
+    """fp64 weights uniform in [0.1, 10): distances equal Dijkstra's in binary64, bit for bit."""
+    g = G.rmat_graph(13, 16, cfg=91, weights="f64", wlo=0.1, whi=10.0)
+    srcs = G.sources_with_outedges(g, 3, cfg=91)
+    got, st = gpu_solve(g, delta, srcs)
+    assert got.dtype == np.float64
+    for r, s in enumerate(srcs):
+        assert_exact(g, got[r], s, f"f64 delta={delta}")
+    assert st["sources"] == len(srcs)
+
+
+def test_fp64_groups_multi_and_weights():
+    g = G.er_graph(4000, 32000, cfg=92, weights="f64", wlo=1e-3, whi=1.0)
+    srcs = G.sources_with_outedges(g, 12, cfg=92)
+    got, _ = gpu_solve(g, 2.0 ** -5, srcs, tuning={"concurrent_sources": 8})
+    for r, s in enumerate(srcs):
+        assert_exact(g, got[r], s, "f64 groups")
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, 0.1)
+    try:
+        d = solver.solve_multi(srcs[:4]).cpu().numpy()
+        want = np.stack([oracle.dijkstra(g, int(s))[0] for s in srcs[:4]]).min(axis=0)
+        assert np.array_equal(_bits(d), _bits(want))
+        w2 = (g.w * 3.0 + 0.5).astype(np.float64)  # new weights: larger spread, same structure
+        solver.set_weights(w2)
+        g2 = G.Graph(n=g.n, row_ptr=g.row_ptr, col=g.col, w=w2)
+        d2 = solver.solve_numpy(srcs[:2])
+        for r, s in enumerate(srcs[:2]):
+            assert_exact(g2, d2[r], s, "f64 set_weights")
+        with pytest.raises(sssp.SsspError) as e:  # the adjoint is fp32 only
+            solver.backward(srcs[:1], torch.from_numpy(d2[:1]).cuda(), torch.ones((1, g.n), device="cuda"))
+        assert e.value.status == sssp.SSSP_ERR_UNSUPPORTED
+    finally:
+        solver.close()
+
+
+def test_fp64_invalid_weights_and_overflow():
+    rp = np.array([0, 2, 3, 3], dtype=np.int64)
+    col = np.array([1, 2, 0], dtype=np.int32)
+    for bad in (0.0, -1.0, np.nan, np.inf, -0.0, -np.inf):
+        w = np.array([1.0, bad, 2.0], dtype=np.float64)
+        assert _create_status(rp, col, w, 2.0) == sssp.SSSP_ERR_INVALID_WEIGHT, bad
+    assert _create_status(rp, col, np.array([1.0, 5e-324, 2.0]), 1.0) == sssp.SSSP_OK  # subnormal is positive
+    assert _create_status(rp, col, np.array([1e300, 1.0, 1.0]), 1e-300) == sssp.SSSP_ERR_UNSUPPORTED
+    # a total weight beyond the fp64 range fails the bucket-range bound, so no fp64 path sum can overflow
+    assert _create_status(rp, col, np.array([1.7e308, 1.7e308, 1.0]), 1e300) == sssp.SSSP_ERR_UNSUPPORTED
+    g = G.path_graph(3, np.array([1.7e308, 1.0], dtype=np.float64))
+    got, _ = gpu_solve(g, 1e300, [0])
+    assert got[0].tolist() == [0.0, 1.7e308, 1.7e308]
