@@ -13,6 +13,7 @@ sum over sources of m_reached / time, m_reached = out-edges of reached vertices.
 
 Beside the plain solve the line reports the batched and backward modes on the
 same GPU ("modes"), each from the library's autotuner and timed with HIP events:
+  concurrent_rmat_s22_k64  the plain workload with several sources in flight (concurrent groups)
   batched_rmat_s18_k256  R-MAT scale 18, fp32 log-uniform [1e-2, 1e2] weights, 256 sources:
                          concurrent sources in one cooperative launch replayed from a HIP
                          graph, against 256 looped single-source launches
@@ -166,6 +167,29 @@ def captured(fn):
     with torch.cuda.graph(graph, stream=stream):
         fn(stream)
     return graph
+
+
+def mode_concurrent_s22(g, sources, dev, steps: int, plain_rows: np.ndarray) -> dict:
+    """The headline graph and sources with several sources in flight (concurrent groups), the
+    delta and group count from the library's autotuner on 16 of the sources."""
+    import torch
+
+    from paper_1911_06895_amd import sssp
+
+    rp, ci, wt = device_graph(g, dev)
+    dist = torch.empty((len(sources), g.n), dtype=torch.int32, device=dev)
+    h, tune = sssp.sssp_autotune(rp, ci, wt, sources[:16], dist[:16], deltas=[16, 32, 64, 128])
+    src_dev = torch.from_numpy(np.asarray(sources, dtype=np.int32)).to(dev)
+    ms = timed_ms(lambda: sssp.sssp_solve_async(h, src_dev, dist), reps=steps)
+    sssp.sssp_solve_status(h)
+    rows = dist.cpu().numpy().view(np.uint32)
+    sssp.sssp_destroy(h)
+    if not np.array_equal(rows, plain_rows):
+        raise SystemExit("bench: concurrent and one-at-a-time solves disagree")
+    m_r = reached_edges(g, rows)
+    return {"workload": "R-MAT scale 22 (the plain workload), 64 sources, several in flight",
+            "delta": tune["delta"], "concurrent_sources": tune["concurrent_sources"],
+            "autotune_trials": tune["trials"], "ms": round(ms, 3), "gteps": round(m_r / ms / 1e6, 3)}
 
 
 def mode_batched_s18(dev, steps: int) -> dict:
@@ -383,6 +407,14 @@ def main():
         f" {value:.2f} GTEPS, algorithmic {achieved:.1f} GB/s")
 
     modes = {}
+    if not args.no_modes and args.workload == "rmat_s22_u32":
+        t0 = time.perf_counter()
+        del dist
+        sssp.sssp_destroy(handle)
+        handle = None
+        torch.cuda.empty_cache()
+        modes["concurrent_rmat_s22_k64"] = mode_concurrent_s22(g, sources, dev, max(1, args.steps), rows)
+        log(f"[bench] concurrent_rmat_s22_k64: {modes['concurrent_rmat_s22_k64']} ({time.perf_counter() - t0:.1f}s)")
     if not args.no_modes:
         for name, fn in (("batched_rmat_s18_k256", mode_batched_s18), ("batched_ragged_er512", mode_batched_ragged),
                          ("backward_rmat_s18", mode_backward)):
@@ -419,7 +451,8 @@ def main():
         "modes": modes,
     }
     print(json.dumps(out), flush=True)
-    sssp.sssp_destroy(handle)
+    if handle is not None:
+        sssp.sssp_destroy(handle)
 
 
 if __name__ == "__main__":

@@ -200,7 +200,8 @@ sssp_status sssp_solve_status(sssp_handle *h, void *stream);
  *   at the source is ignored. Sums run in fp64; grad_w is written in fp32.
  *   sources: HOST int32 [k].  dist: DEVICE [k][n] float.  grad_dist: DEVICE
  *   [k][n] float.  grad_w: DEVICE [m] float, caller edge order, overwritten.
- *   The call synchronises the stream.
+ *   With concurrent_sources = G (sssp_set_tuning), G sources are processed at
+ *   the same time, as in the forward solve. The call synchronises the stream.
  *   Errors: INVALID_ARGUMENT (pointers, sources, or dist not a shortest-path
  *   vector of this graph), UNSUPPORTED (uint32 and double handles), NO_FORWARD (no
  *   successful sssp_solve since the handle's weights were set), DEVICE.

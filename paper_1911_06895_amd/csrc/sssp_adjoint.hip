@@ -29,34 +29,45 @@ __device__ void adjoint_leader_level(Ctl* c, uint32_t cur) {
 }
 
 template <class W>
-__global__ __launch_bounds__(kWG) void adjoint_kernel(AdjParams a, const int32_t* sources, int k,
-                                                      const uint32_t* dist, const float* grad_dist, float* grad_w) {
+__global__ __launch_bounds__(kWG) void adjoint_kernel(const AdjParams* __restrict__ params, uint32_t groups,
+                                                      const int32_t* sources, int k, const uint32_t* dist,
+                                                      const float* grad_dist) {
+  // workgroup b belongs to group b % groups; each group handles one source at a time
+  const AdjParams& a = params[blockIdx.x % groups];
+  const uint32_t rank = blockIdx.x / groups, size = gridDim.x / groups;
   Ctl* c = a.ctl;
   const uint32_t n = a.n;
-  const uint32_t tid = blockIdx.x * kWG + threadIdx.x;
-  const uint32_t nthreads = gridDim.x * kWG;
-  __shared__ uint32_t s_count, s_cur;
+  const uint32_t tid = rank * kWG + threadIdx.x;
+  const uint32_t nthreads = size * kWG;
+  __shared__ uint32_t s_count, s_cur, s_row;
   bool alive = true;
-  for (uint64_t e = tid; e < a.m; e += nthreads) st_agent(&a.grad64[e], 0.0);
-  for (int r = 0; r < k && alive; ++r) {
-    const uint32_t* drow = dist + static_cast<size_t>(r) * n;
-    const float* grow = grad_dist + static_cast<size_t>(r) * n;
-    const uint32_t s = a.vid[sources[r]];
-    // distances and coefficients in solver ids
-    for (uint32_t x = tid; x < n; x += nthreads) {
-      const uint32_t v = a.inv[x];
-      const uint32_t dx = drow[v];
-      st_agent(&a.d[x], dx);
-      st_agent(&a.parent[x], kNoParent);
-      st_agent(&a.cnt[x], 0u);
-      st_agent(&a.g[x], (dx < W::kInf && x != s) ? static_cast<double>(grow[v]) : 0.0);
-    }
-    alive = grid_sync(c, gridDim.x, blockIdx.x, [&] {
+  while (alive) {
+    // claim the next source row for this group
+    alive = grid_sync(c, size, rank, [&] {
       if (threadIdx.x == 0) {
+        const uint32_t r = g_add(a.next_source, 1u);
+        st_agent(&c->source_index, r < static_cast<uint32_t>(k) ? r : kNone);
         st_agent(&c->fcount[0], 0u);
         st_agent(&c->fcount[1], 0u);
       }
     });
+    if (threadIdx.x == 0) s_row = ld_agent(&c->source_index);
+    __syncthreads();
+    const uint32_t r = s_row;
+    if (!alive || r == kNone) break;
+    const uint32_t* drow = dist + static_cast<size_t>(r) * n;
+    const float* grow = grad_dist + static_cast<size_t>(r) * n;
+    const uint32_t s = ldg(&a.vid[ldg(&sources[r])]);
+    // distances and coefficients in solver ids
+    for (uint32_t x = tid; x < n; x += nthreads) {
+      const uint32_t v = ldg(&a.inv[x]);
+      const uint32_t dx = ldg(&drow[v]);
+      st_agent(&a.d[x], dx);
+      st_agent(&a.parent[x], kNoParent);
+      st_agent(&a.cnt[x], 0u);
+      st_agent(&a.g[x], (dx < W::kInf && x != s) ? static_cast<double>(ldg(&grow[v])) : 0.0);
+    }
+    alive = grid_sync(c, size, rank, [] {});
     if (!alive) break;
     // 1. parents: one wave per row, lanes over the row's edges
     {
@@ -64,26 +75,26 @@ __global__ __launch_bounds__(kWG) void adjoint_kernel(AdjParams a, const int32_t
       for (uint32_t x = wave; x < n; x += nwaves) {
         const uint32_t dx = ld_agent(&a.d[x]);
         if (dx >= W::kInf) continue;
-        const uint4 row = a.rows[x];
+        const uint4 row = ldg(&a.rows[x]);
         for (uint32_t p = row.x + l; p < row.z; p += 64) {
-          const uint64_t ed = a.edges[p];
+          const uint64_t ed = ldg(&a.edges[p]);
           const uint32_t y = static_cast<uint32_t>(ed);
           uint32_t cand;
           if (y != s && W::add(dx, static_cast<uint32_t>(ed >> 32), &cand) && cand == ld_agent(&a.d[y]))
-            atomicMin(&a.parent[y], static_cast<unsigned long long>(a.perm[p]) << 32 | x);
+            g_min(&a.parent[y], static_cast<unsigned long long>(ldg(&a.perm[p])) << 32 | x);
         }
       }
     }
-    alive = grid_sync(c, gridDim.x, blockIdx.x, [] {});
+    alive = grid_sync(c, size, rank, [] {});
     if (!alive) break;
     // 2. children per vertex; a reached vertex other than s must have a parent
     for (uint32_t y = tid; y < n; y += nthreads) {
       if (y == s || ld_agent(&a.d[y]) >= W::kInf) continue;
       const unsigned long long pe = ld_agent(&a.parent[y]);
       if (pe == kNoParent) st_agent(&c->ovf_real, 1u);  // not a shortest-path vector
-      else atomicAdd(&a.cnt[static_cast<uint32_t>(pe)], 1u);
+      else g_add(&a.cnt[static_cast<uint32_t>(pe)], 1u);
     }
-    alive = grid_sync(c, gridDim.x, blockIdx.x, [] {});
+    alive = grid_sync(c, size, rank, [] {});
     if (!alive) break;
     // 3. first level: reached vertices without children
     {
@@ -94,7 +105,7 @@ __global__ __launch_bounds__(kWG) void adjoint_kernel(AdjParams a, const int32_t
         push_wave(a.front[0], &c->fcount[0], leaf, y);
       }
     }
-    alive = grid_sync(c, gridDim.x, blockIdx.x, [&] { adjoint_leader_level<W>(c, 1u); });  // in_count = fcount[0], out = 0
+    alive = grid_sync(c, size, rank, [&] { adjoint_leader_level<W>(c, 1u); });  // in_count = fcount[0], out = 0
     // 4. levels, leaves towards the source
     while (alive) {
       if (threadIdx.x == 0) {
@@ -117,23 +128,25 @@ __global__ __launch_bounds__(kWG) void adjoint_kernel(AdjParams a, const int32_t
           if (pe != kNoParent) {  // (a reached vertex without a parent was reported above)
             x = static_cast<uint32_t>(pe);
             const double gy = ld_agent(&a.g[y]);
-            atomicAdd(&a.grad64[pe >> 32], gy);
-            atomicAdd(&a.g[x], gy);  // read by x's own level, after the next barrier
-            up = atomicSub(&a.cnt[x], 1u) == 1u;
+            g_add(&a.grad64[pe >> 32], gy);
+            g_add(&a.g[x], gy);  // read by x's own level, after the next barrier
+            up = g_add(&a.cnt[x], 0xFFFFFFFFu) == 1u;  // the last child to report releases the parent
           }
         }
         push_wave(a.front[nxt], &c->fcount[nxt], up, x);
       }
       // every reached vertex is released exactly once unless the parents form a cycle
-      if (released) atomicAdd(&c->adj_released, static_cast<unsigned long long>(released));
-      alive = grid_sync(c, gridDim.x, blockIdx.x, [&] { adjoint_leader_level<W>(c, cur); });
+      if (released) g_add(&c->adj_released, static_cast<unsigned long long>(released));
+      alive = grid_sync(c, size, rank, [&] { adjoint_leader_level<W>(c, cur); });
     }
   }
-  if (alive) {
-    alive = grid_sync(c, gridDim.x, blockIdx.x, [] {});
-    if (alive)
-      for (uint64_t e = tid; e < a.m; e += nthreads) grad_w[e] = static_cast<float>(ld_agent(&a.grad64[e]));
-  }
+}
+
+// dL/dw in the caller's edge order, from the fp64 accumulator
+__global__ __launch_bounds__(kAuxWG) void grad_to_f32_kernel(const double* g64, uint64_t m, float* out) {
+  for (uint64_t e = static_cast<uint64_t>(blockIdx.x) * kAuxWG + threadIdx.x; e < m;
+       e += static_cast<uint64_t>(gridDim.x) * kAuxWG)
+    out[e] = static_cast<float>(g64[e]);
 }
 
 // Number of reached vertices of a distance row (for the release-count check).
@@ -204,17 +217,26 @@ hipError_t adjoint_occupancy(int* blocks_per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, adjoint_kernel<WeightF32>, kWG, 0);
 }
 
-hipError_t launch_adjoint(const AdjParams& a, const int32_t* sources, int k, const uint32_t* dist,
-                          const float* grad_dist, float* grad_w, int grid, hipStream_t s) {
-  AdjParams aa = a;
+hipError_t launch_adjoint(const AdjParams* params, uint32_t groups, const int32_t* sources, int k, const uint32_t* dist,
+                          const float* grad_dist, float* grad_w, uint64_t m, double* grad64, int grid, hipStream_t s) {
+  if (groups < 1 || groups > kMaxGroups || grid < 1 || grid % static_cast<int>(groups) != 0) return hipErrorInvalidValue;
+  hipError_t e = launch_fill(reinterpret_cast<uint32_t*>(grad64), 2 * static_cast<size_t>(m), 0u, s);
+  if (e != hipSuccess) return e;
+  const AdjParams* pp = params;
+  uint32_t gg = groups;
   const int32_t* src = sources;
   int kk = k;
   const uint32_t* d = dist;
   const float* gd = grad_dist;
-  float* gw = grad_w;
-  void* args[] = {&aa, &src, &kk, &d, &gd, &gw};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(adjoint_kernel<WeightF32>), dim3(grid), dim3(kWG),
-                                    args, 0, s);
+  void* args[] = {&pp, &gg, &src, &kk, &d, &gd};
+  e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(adjoint_kernel<WeightF32>), dim3(grid), dim3(kWG), args,
+                                 0, s);
+  if (e != hipSuccess) return e;
+  size_t blocks = (static_cast<size_t>(m) + kAuxWG - 1) / kAuxWG;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(grad_to_f32_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kAuxWG), 0, s, grad64, m, grad_w);
+  return hipGetLastError();
 }
 
 hipError_t launch_count_reached(const uint32_t* dist, uint32_t n, int k, int wtype, unsigned long long* out,

@@ -59,6 +59,14 @@ struct sssp_handle {
   uint32_t* adj_cnt = nullptr;
   double* adj_g = nullptr;
   double* adj_grad64 = nullptr;
+  struct AdjMem {  // adjoint working set of an extra concurrent group
+    uint32_t* d = nullptr;
+    unsigned long long* parent = nullptr;
+    uint32_t* cnt = nullptr;
+    double* g = nullptr;
+  };
+  std::vector<AdjMem> adj_extra;
+  sssp::AdjParams* adj_params_dev = nullptr;  // [kMaxGroups]
   unsigned long long* aux = nullptr;  // [2] small device scratch for status reads
   int adj_grid = 0;
 };
@@ -88,9 +96,15 @@ hipError_t dalloc(T** p, size_t count) {
 void free_handle(sssp_handle* h) {
   if (!h) return;
   sssp::Params& p = h->p;
-  void* extra[] = {h->inv, h->adj_d, h->adj_parent, h->adj_cnt, h->adj_g, h->adj_grad64, h->aux, h->params_dev, h->w64};
+  void* extra[] = {h->inv, h->adj_d, h->adj_parent, h->adj_cnt, h->adj_g, h->adj_grad64, h->aux, h->params_dev, h->w64,
+                   h->adj_params_dev};
   for (void* q : extra)
     if (q) (void)hipFree(q);
+  for (sssp_handle::AdjMem& am : h->adj_extra) {
+    void* mem[] = {am.d, am.parent, am.cnt, am.g};
+    for (void* q : mem)
+      if (q) (void)hipFree(q);
+  }
   for (GroupMem& gm : h->extra) {
     void* mem[] = {gm.tbuf[0], gm.tbuf[1], gm.qstamp, gm.sstamp, gm.bstamp, gm.fstamp, gm.ovf_at, gm.front[0],
                    gm.front[1], gm.slist, gm.bins, gm.far[0], gm.far[1], gm.hub};
@@ -558,42 +572,76 @@ sssp_status sssp_backward(sssp_handle* h, const int32_t* sources, int32_t k, con
     SSSP_TRY(dalloc(&h->adj_cnt, un));
     SSSP_TRY(dalloc(&h->adj_g, un));
     SSSP_TRY(dalloc(&h->adj_grad64, um));
+    SSSP_TRY(dalloc(&h->adj_params_dev, sssp::kMaxGroups));
     int occ = 0;
     SSSP_TRY(sssp::adjoint_occupancy(&occ));
     if (occ < 1) return SSSP_ERR_UNSUPPORTED;
     h->adj_grid = h->cus;
   }
+  // sources share the launch as in the forward solve: one group per concurrent source
+  const uint32_t groups = h->adj_grid % static_cast<int>(h->groups) == 0 ? h->groups : 1u;
+  while (h->adj_extra.size() + 1 < groups) {
+    h->adj_extra.emplace_back();
+    sssp_handle::AdjMem& am = h->adj_extra.back();
+    SSSP_TRY(dalloc(&am.d, un));
+    SSSP_TRY(dalloc(&am.parent, un));
+    SSSP_TRY(dalloc(&am.cnt, un));
+    SSSP_TRY(dalloc(&am.g, un));
+  }
   const sssp_status st = stage_sources(h, sources, k, s);
   if (st != SSSP_OK) return st;
-  sssp::AdjParams a{};
-  a.n = static_cast<uint32_t>(h->n);
-  a.m = static_cast<uint64_t>(h->m);
-  a.vid = h->p.vid;
-  a.inv = h->inv;
-  a.rows = h->p.rows;
-  a.edges = h->p.edges;
-  a.perm = h->perm;
-  a.d = h->adj_d;
-  a.parent = h->adj_parent;
-  a.cnt = h->adj_cnt;
-  a.g = h->adj_g;
-  a.front[0] = h->p.front[0];
-  a.front[1] = h->p.front[1];
-  a.grad64 = h->adj_grad64;
-  a.ctl = h->p.ctl;
+  std::vector<sssp::AdjParams> all(groups);
+  for (uint32_t gi = 0; gi < groups; ++gi) {
+    sssp::AdjParams& a = all[gi];
+    a.n = static_cast<uint32_t>(h->n);
+    a.m = static_cast<uint64_t>(h->m);
+    a.vid = h->p.vid;
+    a.inv = h->inv;
+    a.rows = h->p.rows;
+    a.edges = h->p.edges;
+    a.perm = h->perm;
+    a.grad64 = h->adj_grad64;
+    a.ctl = h->ctls + gi;
+    a.next_source = &h->ctls[0].next_source;
+    if (gi == 0) {
+      a.d = h->adj_d;
+      a.parent = h->adj_parent;
+      a.cnt = h->adj_cnt;
+      a.g = h->adj_g;
+      a.front[0] = h->p.front[0];
+      a.front[1] = h->p.front[1];
+    } else {  // the level lists reuse the frontier buffers of the group's solver working set
+      const sssp_handle::AdjMem& am = h->adj_extra[gi - 1];
+      a.d = am.d;
+      a.parent = am.parent;
+      a.cnt = am.cnt;
+      a.g = am.g;
+      a.front[0] = h->extra[gi - 1].front[0];
+      a.front[1] = h->extra[gi - 1].front[1];
+    }
+  }
+  SSSP_TRY(hipMemcpyAsync(h->adj_params_dev, all.data(), sizeof(sssp::AdjParams) * groups, hipMemcpyHostToDevice, s));
   SSSP_TRY(hipMemsetAsync(h->aux, 0, 2 * sizeof(unsigned long long), s));
-  SSSP_TRY(sssp::launch_count_reached(static_cast<const uint32_t*>(dist), a.n, k, h->wtype, h->aux, s));
-  SSSP_TRY(sssp::launch_ctl_reset(h->ctls, 1, 0, nullptr, 0, s));
-  SSSP_TRY(sssp::launch_adjoint(a, h->src_dev, k, static_cast<const uint32_t*>(dist), grad_dist, grad_w, h->adj_grid,
-                                s));
+  SSSP_TRY(sssp::launch_count_reached(static_cast<const uint32_t*>(dist), static_cast<uint32_t>(h->n), k, h->wtype,
+                                      h->aux, s));
+  SSSP_TRY(sssp::launch_ctl_reset(h->ctls, groups, 0, nullptr, 0, s));
+  SSSP_TRY(sssp::launch_adjoint(h->adj_params_dev, groups, h->src_dev, k, static_cast<const uint32_t*>(dist), grad_dist,
+                                grad_w, static_cast<uint64_t>(h->m), h->adj_grad64, h->adj_grid, s));
   unsigned long long reached = 0;
-  SSSP_TRY(hipMemcpyAsync(h->ctl_host, h->p.ctl, sizeof(sssp::Ctl), hipMemcpyDeviceToHost, s));
+  SSSP_TRY(hipMemcpyAsync(h->ctl_host, h->ctls, sizeof(sssp::Ctl) * groups, hipMemcpyDeviceToHost, s));
   SSSP_TRY(hipMemcpyAsync(&reached, h->aux, sizeof(reached), hipMemcpyDeviceToHost, s));
   SSSP_TRY(hipStreamSynchronize(s));
-  const sssp::Ctl& c = *h->ctl_host;
-  if (c.abort) return SSSP_ERR_DEVICE;
+  bool abort = false, bad = false;
+  unsigned long long released = 0;
+  for (uint32_t gi = 0; gi < groups; ++gi) {
+    const sssp::Ctl& c = h->ctl_host[gi];
+    abort |= c.abort != 0;
+    bad |= c.ovf_real != 0;
+    released += c.adj_released;
+  }
+  if (abort) return SSSP_ERR_DEVICE;
   // a reached vertex without a tight in-edge, or parents that never lead to the source
-  if (c.ovf_real || c.adj_released != reached) return SSSP_ERR_INVALID_ARGUMENT;
+  if (bad || released != reached) return SSSP_ERR_INVALID_ARGUMENT;
   return SSSP_OK;
 }
 

@@ -170,14 +170,17 @@ struct AdjParams {
   uint32_t* cnt;              // [n] children still to report
   double* g;                  // [n] accumulated coefficients
   uint32_t* front[2];         // [n] level lists
-  double* grad64;             // [m] dL/dw in caller edge order
-  Ctl* ctl;
+  double* grad64;             // [m] dL/dw in caller edge order (shared by every group)
+  Ctl* ctl;                   // this group's control block
+  uint32_t* next_source;      // shared by every group: next source row to claim
 };
 
 // launchers (sssp_kernels.hip, sssp_adjoint.hip, sssp_build.hip)
 hipError_t adjoint_occupancy(int* blocks_per_cu);
-hipError_t launch_adjoint(const AdjParams& a, const int32_t* sources, int k, const uint32_t* dist,
-                          const float* grad_dist, float* grad_w, int grid, hipStream_t s);
+// `params`: device array of one AdjParams per group; grad64 is zeroed first and
+// converted into grad_w (fp32) after the launch.
+hipError_t launch_adjoint(const AdjParams* params, uint32_t groups, const int32_t* sources, int k, const uint32_t* dist,
+                          const float* grad_dist, float* grad_w, uint64_t m, double* grad64, int grid, hipStream_t s);
 hipError_t launch_count_reached(const uint32_t* dist, uint32_t n, int k, int wtype, unsigned long long* out,
                                 hipStream_t s);
 hipError_t launch_resplit(uint32_t n, const uint4* rows_in, const uint64_t* edges_in, const uint32_t* perm_in,

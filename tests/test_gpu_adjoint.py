@@ -30,9 +30,10 @@ def check_close(got, want, what):
     assert err.max() <= 1e-6, f"{what}: max relative difference {err.max()} at edge {int(err.argmax())}"
 
 
-def run(g, delta, srcs, grad_rows):
+def run(g, delta, srcs, grad_rows, groups=1):
     solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, delta)
     try:
+        solver.set_tuning(concurrent_sources=groups)
         dist = solver.solve(srcs)
         gd = torch.from_numpy(np.ascontiguousarray(grad_rows, dtype=np.float32)).cuda()
         gw = solver.backward(srcs, dist, gd).cpu().numpy()
@@ -79,15 +80,34 @@ def test_backward_ties_follow_smallest_edge():
     assert gw.tolist() == [5.0, 0.0, 5.0, 0.0]
 
 
-def test_backward_c5_configuration():
-    """R-MAT scale 18, fp32 weights in [1, 2), 16 sources, 1024 targets with N(0,1) coefficients."""
+@pytest.mark.parametrize("groups", [1, 16])
+def test_backward_c5_configuration(groups):
+    """R-MAT scale 18, fp32 weights in [1, 2), 16 sources, 1024 targets with N(0,1) coefficients
+    (one source at a time, and all 16 in concurrent groups)."""
+    print(f"[adjoint] C5 groups={groups}", flush=True)
     g = G.workload("rmat_s18_f32onetwo")
     srcs = G.sources_with_outedges(g, 16, cfg=5)
     targets, coef = G.targets_and_coefs(g.n, 1024, cfg=5)
     grad_rows = np.zeros((len(srcs), g.n))
     grad_rows[:, targets] = coef
-    d, gw = run(g, 1.0, srcs, grad_rows)
+    d, gw = run(g, 1.0, srcs, grad_rows, groups)
     check_close(gw, oracle_gradient(g, srcs, d, grad_rows), "C5")
+
+
+def test_backward_groups_subtree_sizes_exact():
+    """Concurrent groups with more sources than groups: integer subtree sizes, bit for bit."""
+    g = G.rmat_graph(12, 16, cfg=6, weights="f32_one_two")
+    srcs = G.sources_with_outedges(g, 11, cfg=6)
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, 0.5)
+    try:
+        solver.set_tuning(concurrent_sources=4)
+        dist = solver.solve(srcs)
+        gw = solver.backward(srcs, dist, torch.isfinite(dist).float()).cpu().numpy()
+        d = dist.cpu().numpy()
+    finally:
+        solver.close()
+    want = oracle_gradient(g, srcs, d, np.isfinite(d).astype(np.float64))
+    assert np.array_equal(gw.astype(np.float64), want)
 
 
 def test_autograd_wrapper():
