@@ -83,16 +83,17 @@ enum InKind : uint32_t { kInF0 = 0, kInF1 = 1, kInBin = 2 };
 struct Ctl {
   // grid barrier: arrival sub-counters on separate 128-byte lines, then the top counter
   uint32_t bar_sub[kBarGroups][32];
-  uint32_t bar_arrive;
-  uint32_t bar_gen;
+  // Fields that different workgroups update or poll at the same time sit on
+  // separate 128-byte lines, so atomics on one do not queue behind traffic to another.
+  alignas(128) uint32_t bar_arrive;
+  alignas(128) uint32_t bar_gen;  // polled by the waiting workgroups
   uint32_t abort;
   uint32_t source_index;  // source (row) the group is solving, kNone when the batch is done
-  uint32_t chunk_next;   // dynamic chunk counter of the current step
-  uint32_t hub_count;    // hub pieces queued by the current phase
+  alignas(128) uint32_t chunk_next;  // dynamic chunk counter of the current step
+  alignas(128) uint32_t hub_count;   // hub pieces queued by the current phase
   uint32_t hub_parent;   // action of the phase that queued them
-  uint32_t pad0;
   // schedule
-  uint32_t action;
+  alignas(128) uint32_t action;
   uint32_t bucket;       // current bucket i
   uint32_t in_kind;      // InKind of the current input list
   uint32_t in_count;     // entries in the current input list
@@ -102,15 +103,15 @@ struct Ctl {
   uint32_t round;        // S de-duplication tag (monotone across solves)
   uint32_t far_epoch;    // far-list de-duplication tag (monotone across solves)
   uint32_t far_cur;      // which far list is current (0/1)
-  uint32_t far_min;      // lower bound on the bucket of any far vertex
-  uint32_t far_min_next;
   // bounds [lo, hi) of the current bucket (integer weights)
   uint64_t lo_u, hi_u;
   // counters
-  uint32_t fcount[2];
-  uint32_t scount;
-  uint32_t farcount[2];
-  uint32_t ovf_seen;     // some candidate did not fit the distance type
+  alignas(128) uint32_t far_min;  // lower bound on the bucket of any far vertex
+  uint32_t far_min_next;
+  alignas(128) uint32_t fcount[2];
+  alignas(128) uint32_t scount;
+  alignas(128) uint32_t farcount[2];
+  alignas(128) uint32_t ovf_seen;  // some candidate did not fit the distance type
   uint32_t ovf_real;     // a reachable vertex has an unrepresentable distance
   uint32_t trace_len;    // step records written (may exceed trace_cap)
   unsigned long long* trace;  // optional step trace: 4 words per record
@@ -118,9 +119,9 @@ struct Ctl {
   uint32_t trace_cap;
   uint32_t next_source;  // batch-wide source counter (used in the first group's block only)
   uint32_t bad_source;   // a source index outside [0, n) was given
-  uint32_t bincount[kRingMax];
+  alignas(128) uint32_t bincount[kRingMax][32];  // ring-slot sizes, one per 128-byte line ([slot][0])
   // statistics (summed over sources)
-  unsigned long long sources, buckets, light_phases, heavy_phases, far_phases;
+  alignas(128) unsigned long long sources, buckets, light_phases, heavy_phases, far_phases;
   unsigned long long light_edges, heavy_edges, improvements, barriers;
   unsigned long long adj_released;  // adjoint: vertices released (equals the reached count)
 };

@@ -102,7 +102,7 @@ struct Counters {
 __device__ inline void load_counters(Ctl* c, Counters* k) {
   const uint32_t t = threadIdx.x;
   if (t < kRingMax) {
-    k->bins[t] = ld_agent(&c->bincount[t]);
+    k->bins[t] = ld_agent(&c->bincount[t][0]);
   } else if (t >= 64 && t < 64 + kCounters) {
     const uint32_t j = t - 64;
     const uint32_t* src = j == kCHubs        ? &c->hub_count
@@ -183,7 +183,7 @@ __device__ inline void push_ring(const Params& p, bool pred, uint32_t j, uint32_
   }
   uint32_t base = 0;
   if (pred && lane() == my_leader)
-    base = g_add(&p.ctl->bincount[j & p.ring_mask], static_cast<uint32_t>(__popcll(my_group)));
+    base = g_add(&p.ctl->bincount[j & p.ring_mask][0], static_cast<uint32_t>(__popcll(my_group)));
   base = __shfl(base, static_cast<int>(my_leader));
   if (pred) st_agent(&p.bins[static_cast<size_t>(j & p.ring_mask) * p.n + base + lanes_below(my_group)], v);
 }
@@ -255,7 +255,7 @@ __device__ void stage_flush(const Params& p, const Sched& s, Stage& sg, bool for
   if (threadIdx.x < kSlots) {
     const uint32_t k = threadIdx.x;
     const uint32_t c = sg.cnt[k];
-    uint32_t* ctr = k < kRingMax      ? &p.ctl->bincount[k]
+    uint32_t* ctr = k < kRingMax      ? &p.ctl->bincount[k][0]
                     : k == kSlotFront ? &p.ctl->fcount[s.out_buf]
                     : k == kSlotFar   ? &p.ctl->farcount[s.far_cur]
                                       : &p.ctl->scount;
@@ -620,7 +620,7 @@ template <class W>
 __device__ void leader_start(const Params& p, typename W::T* t, const int32_t* seeds, int nseeds, bool reset_tags,
                              Sched* s) {
   Ctl* c = p.ctl;
-  if (threadIdx.x < kRingMax) st_agent(&c->bincount[threadIdx.x], 0u);
+  if (threadIdx.x < kRingMax) st_agent(&c->bincount[threadIdx.x][0], 0u);
   if (threadIdx.x == 0) {
     uint32_t step = 0, round = 0, far_epoch = 1;
     if (!reset_tags) {
@@ -655,7 +655,7 @@ __device__ void leader_start(const Params& p, typename W::T* t, const int32_t* s
     }
     const uint32_t u = ldg(&p.vid[src]);
     st_agent(&t[u], typename W::T(0));
-    if (g_min(&p.bstamp[u], 0u) != 0u) st_agent(&p.bins[g_add(&c->bincount[0], 1u)], u);
+    if (g_min(&p.bstamp[u], 0u) != 0u) st_agent(&p.bins[g_add(&c->bincount[0][0], 1u)], u);
   }
   drain_stores();
   __syncthreads();
@@ -663,7 +663,7 @@ __device__ void leader_start(const Params& p, typename W::T* t, const int32_t* s
     set_bucket<W>(p, s, 0u);
     s->action = kActLight;
     s->in_kind = kInBin;
-    s->in_count = ld_agent(&c->bincount[0]);
+    s->in_count = ld_agent(&c->bincount[0][0]);
     s->out_buf = 0u;
     g_add(&c->buckets, 1ull);
     publish_sched(c, *s);
@@ -701,7 +701,7 @@ __device__ void after_step(const Params& p, Sched* s) {
         g_add(&c->light_phases, 1ull);
         n.step = o.step + 1u;
         const uint32_t n_next = k.w[o.out_buf ? kCF1 : kCF0];
-        if (o.in_kind == kInBin) st_agent(&c->bincount[o.bucket & p.ring_mask], 0u);
+        if (o.in_kind == kInBin) st_agent(&c->bincount[o.bucket & p.ring_mask][0], 0u);
         else st_agent(&c->fcount[o.in_kind], 0u);
         if (n_next > 0) {  // while t_Bi != 0: another light phase on the re-inserted vertices
           n.action = kActLight;
