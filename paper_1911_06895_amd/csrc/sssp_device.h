@@ -201,10 +201,18 @@ __device__ inline void record_trace(Ctl* c, uint32_t flags) {
 // `c` (this one has index `rank` among them). Arrivals are counted first per
 // sub-group (rank % 8), then once per sub-group, which keeps same-address
 // atomics short. The last workgroup to arrive runs `leader` (all its threads)
-// before releasing the others. Returns false when the schedule was aborted (a
-// wait ran past kWaitLimitTicks).
+// before releasing the others by advancing the generation word. `gen` (LDS)
+// is this workgroup's copy of the generation (every workgroup passes every
+// barrier, so no load of the word is needed before arriving; init_gen sets it
+// at kernel start). Returns false when the schedule was aborted (a wait ran
+// past kWaitLimitTicks).
+__device__ inline void init_gen(Ctl* c, uint32_t* gen) {
+  if (threadIdx.x == 0) *gen = ld_agent(&c->bar_gen);
+  __syncthreads();
+}
+
 template <class F>
-__device__ bool grid_sync(Ctl* c, uint32_t size, uint32_t rank, F&& leader) {
+__device__ bool grid_sync(Ctl* c, uint32_t size, uint32_t rank, uint32_t* gen_lds, F&& leader) {
   __shared__ uint32_t s_is_leader;
   __shared__ uint32_t s_ok;
   drain_stores();
@@ -214,7 +222,7 @@ __device__ bool grid_sync(Ctl* c, uint32_t size, uint32_t rank, F&& leader) {
     const uint32_t groups = size < kBarGroups ? size : kBarGroups;
     const uint32_t g = rank % groups;
     const uint32_t gsize = (size - g + groups - 1) / groups;
-    gen = ld_agent(&c->bar_gen);
+    gen = *gen_lds;
     bool last = false;
     const uint32_t prev = g_add(&c->bar_sub[g][0], 1u);
     if (prev == gsize - 1) {
@@ -251,6 +259,7 @@ __device__ bool grid_sync(Ctl* c, uint32_t size, uint32_t rank, F&& leader) {
   }
   const bool ok = s_ok != 0u;
   __syncthreads();
+  if (threadIdx.x == 0) *gen_lds = gen + 1u;
   return ok;
 }
 

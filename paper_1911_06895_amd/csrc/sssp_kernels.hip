@@ -825,10 +825,11 @@ __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ 
   using T = typename W::T;
   __shared__ Sched s;
   __shared__ Stage sg;
-  __shared__ uint32_t s_row;
+  __shared__ uint32_t s_row, s_gen;
   const Params& p = params[blockIdx.x % groups];
   const uint32_t rank = grp_rank(p), size = grp_size(p);
   Ctl* c = p.ctl;
+  init_gen(c, &s_gen);
   if (threadIdx.x == 0) sg.n = 0;
   __syncthreads();
   WgStats st{0, 0, 0, 0, 0};
@@ -852,7 +853,7 @@ __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ 
         st_agent(&p.fstamp[v], 0u);
       }
     }
-    alive = grid_sync(c, size, rank, [&] { leader_claim<W>(p, t, sources, k, multi, reset_tags, &s, st, sg); });
+    alive = grid_sync(c, size, rank, &s_gen, [&] { leader_claim<W>(p, t, sources, k, multi, reset_tags, &s, st, sg); });
     if (threadIdx.x == 0) s_row = ld_agent(&c->source_index);
     __syncthreads();
     const uint32_t row = s_row;
@@ -868,7 +869,7 @@ __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ 
       else if (a == kActOverflowCheck) overflow_step<W>(p, t);
       else if (threadIdx.x == 0) st_agent(&c->abort, 1u);
       trace_step_counts(c, st);
-      alive = grid_sync(c, size, rank, [&] { lead<W>(p, t, &s, st, sg, true); });
+      alive = grid_sync(c, size, rank, &s_gen, [&] { lead<W>(p, t, &s, st, sg, true); });
     }
     if (alive) {  // the source's row of the output, in the caller's vertex numbering
       T* out = static_cast<T*>(dist) + static_cast<size_t>(row) * p.n;
