@@ -184,16 +184,17 @@ __device__ inline void drain_stores() {
 }
 
 __device__ inline void record_trace(Ctl* c, uint32_t flags) {
-  if (!c->trace) return;
+  unsigned long long* trace = ldg(&c->trace);
+  if (!trace) return;
   const uint32_t idx = g_add(&c->trace_len, 1u);
-  if (idx < c->trace_cap) {
+  if (idx < ldg(&c->trace_cap)) {
     const unsigned long long what = static_cast<unsigned long long>(ld_agent(&c->in_count)) << 32 |
                                     static_cast<unsigned long long>(ld_agent(&c->bucket) & 0xFFFFFFu) << 8 |
                                     (ld_agent(&c->action) | flags);
-    st_agent(&c->trace[4 * idx], static_cast<unsigned long long>(wall_clock64()));
-    st_agent(&c->trace[4 * idx + 1], what);
-    st_agent(&c->trace[4 * idx + 2], g_exch(&c->tr_edges, 0ull));
-    st_agent(&c->trace[4 * idx + 3], g_exch(&c->tr_impr, 0ull));
+    st_agent(&trace[4 * idx], static_cast<unsigned long long>(wall_clock64()));
+    st_agent(&trace[4 * idx + 1], what);
+    st_agent(&trace[4 * idx + 2], g_exch(&c->tr_edges, 0ull));
+    st_agent(&trace[4 * idx + 3], g_exch(&c->tr_impr, 0ull));
   }
 }
 

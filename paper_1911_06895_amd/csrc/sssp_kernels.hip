@@ -39,6 +39,44 @@ struct Sched {
   uint64_t lo_u, hi_u;
 };
 
+struct WgStats {
+  unsigned long long light_edges, heavy_edges, improvements;
+  unsigned long long step_edges, step_impr;  // since the last traced step boundary
+};
+
+// List appends of a workgroup are staged in LDS and flushed together: one
+// global atomic per destination list per flush instead of one per wave.
+constexpr uint32_t kSlotFront = kRingMax;     // the current bucket's next frontier
+constexpr uint32_t kSlotFar = kRingMax + 1;   // the far list
+constexpr uint32_t kSlotS = kRingMax + 2;     // S, the vertices expanded in this bucket
+constexpr uint32_t kSlots = kRingMax + 3;     // ring slots 0..kRingMax-1, then the three above
+constexpr uint32_t kNoSlot = 0xFFu;
+
+struct Stage {
+  uint32_t v[kStage];
+  uint32_t rank[kStage];
+  uint8_t slot[kStage];
+  uint32_t n;
+  uint32_t cnt[kSlots];
+  uint32_t base[kSlots];
+};
+
+// The workgroup's state, in LDS: its group's parameters (copied from the
+// launch argument at kernel start), the current schedule, the append staging
+// and the work counters. Device functions name these objects directly rather
+// than receiving references: their accesses then compile to LDS instructions
+// (through a reference, a function that is not inlined would use flat ones,
+// which wait on the global-memory counter as well), and the parameters are
+// not reloaded after every global store.
+__shared__ Params lp;
+__shared__ Sched ls;
+__shared__ Stage lsg;
+__shared__ WgStats lst;
+
+__device__ inline void count_add(unsigned long long* field, unsigned long long v) {
+  if (v) atomicAdd(field, v);
+}
+
 // i*delta <= x < (i+1)*delta for the current bucket i
 template <class W>
 __device__ inline bool in_bucket(typename W::T x, const Sched& s, const Params& p) {
@@ -48,7 +86,8 @@ __device__ inline bool in_bucket(typename W::T x, const Sched& s, const Params& 
 
 // Every workgroup's copy of the schedule the leader published. The loads are
 // independent and issued together (one round trip to the coherent level).
-__device__ inline void load_sched(Ctl* c, Sched* s) {
+__device__ inline void load_sched(Ctl* c) {
+  Sched* s = &ls;
   if (threadIdx.x == 0) {
     const uint32_t action = ld_agent(&c->action), bucket = ld_agent(&c->bucket), in_kind = ld_agent(&c->in_kind),
                    in_count = ld_agent(&c->in_count), out_buf = ld_agent(&c->out_buf), step = ld_agent(&c->step),
@@ -128,33 +167,14 @@ __device__ inline const uint32_t* phase_list(const Params& p, const Sched& s, bo
 
 // ------------------------------------------------------------------ relaxation
 
-struct WgStats {
-  unsigned long long light_edges, heavy_edges, improvements;
-  unsigned long long step_edges, step_impr;  // since the last traced step boundary
-};
-
 // Traced runs only: add this workgroup's counts of the finished step to the
 // control block (one atomic per workgroup), for the next trace record.
-__device__ inline void trace_step_counts(Ctl* c, WgStats& st) {
-  if (!c->trace) return;
-  __shared__ unsigned long long s_e[kWG / 64], s_i[kWG / 64];
-  unsigned long long e = st.step_edges, im = st.step_impr;
-  st.step_edges = st.step_impr = 0;
-  for (int d = 32; d > 0; d >>= 1) {
-    e += __shfl_down(e, d);
-    im += __shfl_down(im, d);
-  }
-  if (lane() == 0) {
-    s_e[threadIdx.x >> 6] = e;
-    s_i[threadIdx.x >> 6] = im;
-  }
+__device__ inline void trace_step_counts(Ctl* c) {
+  if (!ldg(&c->trace)) return;
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long te = 0, ti = 0;
-    for (int w = 0; w < kWG / 64; ++w) {
-      te += s_e[w];
-      ti += s_i[w];
-    }
+    const unsigned long long te = lst.step_edges, ti = lst.step_impr;
+    lst.step_edges = lst.step_impr = 0;
     if (te) g_add(&c->tr_edges, te);
     if (ti) g_add(&c->tr_impr, ti);
   }
@@ -165,7 +185,8 @@ __device__ inline void trace_step_counts(Ctl* c, WgStats& st) {
 // bucket with ballots only; then every group leader issues its atomic at the
 // same time, so a wave waits for one atomic round trip whatever the number of
 // distinct buckets.
-__device__ inline void push_ring(const Params& p, bool pred, uint32_t j, uint32_t v) {
+__device__ inline void push_ring(bool pred, uint32_t j, uint32_t v) {
+  const Params& p = lp;
   uint64_t rest = __ballot(pred);
   if (rest == 0) return;
   uint32_t my_leader = 0;
@@ -188,24 +209,8 @@ __device__ inline void push_ring(const Params& p, bool pred, uint32_t j, uint32_
   if (pred) st_agent(&p.bins[static_cast<size_t>(j & p.ring_mask) * p.n + base + lanes_below(my_group)], v);
 }
 
-// List appends of a workgroup are staged in LDS and flushed together: one
-// global atomic per destination list per flush instead of one per wave.
-constexpr uint32_t kSlotFront = kRingMax;     // the current bucket's next frontier
-constexpr uint32_t kSlotFar = kRingMax + 1;   // the far list
-constexpr uint32_t kSlotS = kRingMax + 2;     // S, the vertices expanded in this bucket
-constexpr uint32_t kSlots = kRingMax + 3;     // ring slots 0..kRingMax-1, then the three above
-constexpr uint32_t kNoSlot = 0xFFu;
-
-struct Stage {
-  uint32_t v[kStage];
-  uint32_t rank[kStage];
-  uint8_t slot[kStage];
-  uint32_t n;
-  uint32_t cnt[kSlots];
-  uint32_t base[kSlots];
-};
-
-__device__ inline void stage_push(Stage& sg, bool push, uint32_t slot, uint32_t v) {
+__device__ inline void stage_push(bool push, uint32_t slot, uint32_t v) {
+  Stage& sg = lsg;
   const uint64_t mask = __ballot(push);
   if (mask == 0) return;
   const int leader = first_lane(mask);
@@ -221,7 +226,10 @@ __device__ inline void stage_push(Stage& sg, bool push, uint32_t slot, uint32_t 
 
 // Move the staged appends to their lists. Unless `force`, only when another
 // round of kWG * kILP appends might not fit. All threads of the workgroup call it.
-__device__ void stage_flush(const Params& p, const Sched& s, Stage& sg, bool force) {
+__device__ void stage_flush(bool force) {
+  const Params& p = lp;
+  const Sched& s = ls;
+  Stage& sg = lsg;
   __syncthreads();
   const uint32_t n = sg.n;
   if (n == 0 || (!force && n <= kStage - kWG * kILP)) return;
@@ -282,9 +290,10 @@ __device__ void stage_flush(const Params& p, const Sched& s, Stage& sg, bool for
 // Sec. IV-C), into the ring of near buckets, or into the far list. The loads and
 // atomics of the kILP requests are independent and overlap in flight.
 template <class W>
-__device__ inline void relax_batch(const Params& p, typename W::T* t, const Sched& s, const bool (&active)[kILP],
-                                   const typename W::T (&tu)[kILP], const uint32_t (&v)[kILP],
-                                   const typename W::Wt (&w)[kILP], uint64_t near_end, WgStats& st, Stage& sg) {
+__device__ inline void relax_batch(typename W::T* t, const bool (&active)[kILP], const typename W::T (&tu)[kILP],
+                                   const uint32_t (&v)[kILP], const typename W::Wt (&w)[kILP], uint64_t near_end) {
+  const Params& p = lp;
+  const Sched& s = ls;
   typename W::T cand[kILP], tv[kILP];
   bool ok[kILP], win[kILP];
 #pragma unroll
@@ -314,14 +323,15 @@ __device__ inline void relax_batch(const Params& p, typename W::T* t, const Sche
       }
     }
   }
+  uint32_t nwin = 0;
 #pragma unroll
   for (uint32_t q = 0; q < kILP; ++q) {
-    const uint64_t wins = __ballot(win[q]);
-    if (lane() == 0) {
-      st.improvements += __popcll(wins);
-      st.step_impr += __popcll(wins);
-    }
-    stage_push(sg, slot[q] != kNoSlot, slot[q], v[q]);
+    nwin += static_cast<uint32_t>(__popcll(__ballot(win[q])));
+    stage_push(slot[q] != kNoSlot, slot[q], v[q]);
+  }
+  if (lane() == 0) {
+    count_add(&lst.improvements, nwin);
+    count_add(&lst.step_impr, nwin);
   }
 }
 
@@ -340,7 +350,8 @@ __device__ inline uint32_t claim_next(Ctl* c, uint32_t prev, uint32_t nitems, bo
 }
 
 // Queue the pieces of one high-degree vertex (kHub or more edges in this phase).
-__device__ inline void queue_hub(const Params& p, uint32_t u, uint32_t deg) {
+__device__ inline void queue_hub(uint32_t u, uint32_t deg) {
+  const Params& p = lp;
   const uint32_t pieces = (deg + kPiece - 1) / kPiece;
   const uint32_t base = g_add(&p.ctl->hub_count, pieces);
   for (uint32_t k = 0; k < pieces && base + k < p.hub_cap; ++k)
@@ -373,9 +384,11 @@ struct Entry {
 };
 
 template <class W, bool kLight>
-__device__ void phase(const Params& p, typename W::T* t, const Sched& s, WgStats& st, Stage& sg, bool solo,
-                      bool preloaded = false, Entry<typename W::T> pre = Entry<typename W::T>{}) {
+__device__ void phase(typename W::T* t, bool solo, bool preloaded = false,
+                      Entry<typename W::T> pre = Entry<typename W::T>{}) {
   using T = typename W::T;
+  const Params& p = lp;
+  const Sched& s = ls;
   __shared__ uint32_t s_pref[kChunk];
   __shared__ uint32_t s_beg[kChunk];
   __shared__ T s_tu[kChunk];
@@ -416,14 +429,13 @@ __device__ void phase(const Params& p, typename W::T* t, const Sched& s, WgStats
           to_s = g_exch(&p.sstamp[u], s.round) != s.round;
         }
       }
-      stage_push(sg, to_s, kSlotS, u);
-      stage_flush(p, s, sg, false);
+      stage_push(to_s, kSlotS, u);
+      stage_flush(false);
     }
     if (!solo && deg >= kHub) {
-      queue_hub(p, u, deg);
-      if (kLight) st.light_edges += deg;
-      else st.heavy_edges += deg;
-      st.step_edges += deg;
+      queue_hub(u, deg);
+      count_add(kLight ? &lst.light_edges : &lst.heavy_edges, deg);
+      count_add(&lst.step_edges, deg);
       deg = 0;
     }
     uint32_t total;
@@ -435,9 +447,8 @@ __device__ void phase(const Params& p, typename W::T* t, const Sched& s, WgStats
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      if (kLight) st.light_edges += total;
-      else st.heavy_edges += total;
-      st.step_edges += total;
+      count_add(kLight ? &lst.light_edges : &lst.heavy_edges, total);
+      count_add(&lst.step_edges, total);
     }
     const uint32_t rounds = (total + kWG * kILP - 1) / (kWG * kILP);
     for (uint32_t r = 0; r < rounds; ++r) {
@@ -466,19 +477,21 @@ __device__ void phase(const Params& p, typename W::T* t, const Sched& s, WgStats
           tw[q] = s_tu[lo];
         }
       }
-      relax_batch<W>(p, t, s, active, tw, v, w, near_end, st, sg);
-      stage_flush(p, s, sg, false);
+      relax_batch<W>(t, active, tw, v, w, near_end);
+      stage_flush(false);
     }
     __syncthreads();
   }
-  stage_flush(p, s, sg, true);
+  stage_flush(true);
 }
 
 // Hub step: pieces of kPiece consecutive edges of the high-degree vertices
 // queued by the previous phase, spread over all workgroups.
 template <class W>
-__device__ void hub_step(const Params& p, typename W::T* t, const Sched& s, WgStats& st, Stage& sg) {
+__device__ void hub_step(typename W::T* t) {
   using T = typename W::T;
+  const Params& p = lp;
+  const Sched& s = ls;
   __shared__ uint32_t s_beg, s_end, s_claim;
   __shared__ T s_tu;
   const bool light = s.hub_parent == kActLight;
@@ -516,16 +529,18 @@ __device__ void hub_step(const Params& p, typename W::T* t, const Sched& s, WgSt
         w[q] = W::weight(p, ed, e);
       }
     }
-    relax_batch<W>(p, t, s, active, tw, v, w, near_end, st, sg);
-    stage_flush(p, s, sg, false);
+    relax_batch<W>(t, active, tw, v, w, near_end);
+    stage_flush(false);
   }
-  stage_flush(p, s, sg, true);
+  stage_flush(true);
 }
 
 // Far-list redistribution: far vertices whose bucket is now within the ring
 // move into it; the rest move to the other far list.
 template <class W>
-__device__ void far_step(const Params& p, typename W::T* t, const Sched& s) {
+__device__ void far_step(typename W::T* t) {
+  const Params& p = lp;
+  const Sched& s = ls;
   const uint32_t count = s.in_count;
   const uint32_t* list = p.far[s.far_cur];
   const uint32_t nxt = 1u - s.far_cur;
@@ -549,7 +564,7 @@ __device__ void far_step(const Params& p, typename W::T* t, const Sched& s) {
         }
       }
     }
-    push_ring(p, to_ring, j, v);
+    push_ring(to_ring, j, v);
     push_wave(p.far[nxt], &p.ctl->farcount[nxt], to_far, v);
   }
 }
@@ -557,7 +572,8 @@ __device__ void far_step(const Params& p, typename W::T* t, const Sched& s) {
 // A candidate that did not fit marked its target; the distance of that target
 // is unrepresentable exactly when no other path reached it.
 template <class W>
-__device__ void overflow_step(const Params& p, typename W::T* t) {
+__device__ void overflow_step(typename W::T* t) {
+  const Params& p = lp;
   for (uint32_t v = grp_rank(p) * kWG + threadIdx.x; v < p.n; v += grp_size(p) * kWG) {
     if (ld_agent(&p.ovf_at[v])) {
       if (ld_agent(&t[v]) == W::kInf) st_agent(&p.ctl->ovf_real, 1u);
@@ -570,7 +586,9 @@ __device__ void overflow_step(const Params& p, typename W::T* t) {
 
 // Bucket i: [i*delta, (i+1)*delta) as integer bounds (integer weights).
 template <class W>
-__device__ inline void set_bucket(const Params& p, Sched* s, uint32_t i) {
+__device__ inline void set_bucket(uint32_t i) {
+  const Params& p = lp;
+  Sched* s = &ls;
   s->bucket = i;
   s->lo_u = static_cast<uint64_t>(i) * p.delta_u;
   s->hi_u = static_cast<uint64_t>(i + 1ull) * p.delta_u;
@@ -580,8 +598,9 @@ __device__ inline void set_bucket(const Params& p, Sched* s, uint32_t i) {
 // buckets starting at `from`, unless far-future vertices (fc of them, none
 // below bucket fmin) may come first. Wave 0 scans the slots; thread 0 decides.
 template <class W>
-__device__ void choose_next(const Params& p, Sched* s, const Counters& k, uint32_t from, uint32_t len, uint32_t fc,
-                            uint32_t fmin) {
+__device__ void choose_next(const Counters& k, uint32_t from, uint32_t len, uint32_t fc, uint32_t fmin) {
+  const Params& p = lp;
+  Sched* s = &ls;
   __shared__ uint32_t s_jn;
   if (threadIdx.x < 64) {
     const uint32_t l = threadIdx.x;
@@ -599,7 +618,7 @@ __device__ void choose_next(const Params& p, Sched* s, const Counters& k, uint32
     } else if (jn == kNone) {
       s->action = k.w[kCOvf] ? kActOverflowCheck : kActDone;
     } else {  // B_i = {v : i*delta <= t(v) < (i+1)*delta} for the smallest non-empty i
-      set_bucket<W>(p, s, jn);
+      set_bucket<W>(jn);
       s->action = kActLight;
       s->in_kind = kInBin;
       s->in_count = k.bins[jn & p.ring_mask];
@@ -617,8 +636,9 @@ __device__ void choose_next(const Params& p, Sched* s, const Counters& k, uint32
 // is left in *s and published. `reset_tags`: the group's stamps were just
 // cleared, so the de-duplication tags restart.
 template <class W>
-__device__ void leader_start(const Params& p, typename W::T* t, const int32_t* seeds, int nseeds, bool reset_tags,
-                             Sched* s) {
+__device__ void leader_start(typename W::T* t, const int32_t* seeds, int nseeds, bool reset_tags) {
+  const Params& p = lp;
+  Sched* s = &ls;
   Ctl* c = p.ctl;
   if (threadIdx.x < kRingMax) st_agent(&c->bincount[threadIdx.x][0], 0u);
   if (threadIdx.x == 0) {
@@ -660,7 +680,7 @@ __device__ void leader_start(const Params& p, typename W::T* t, const int32_t* s
   drain_stores();
   __syncthreads();
   if (threadIdx.x == 0) {
-    set_bucket<W>(p, s, 0u);
+    set_bucket<W>(0u);
     s->action = kActLight;
     s->in_kind = kInBin;
     s->in_count = ld_agent(&c->bincount[0][0]);
@@ -677,7 +697,9 @@ __device__ void leader_start(const Params& p, typename W::T* t, const int32_t* s
 // are read in one round trip; the rest is stores, which the caller drains
 // before anything reads them back (the barrier release does).
 template <class W>
-__device__ void after_step(const Params& p, Sched* s) {
+__device__ void after_step() {
+  const Params& p = lp;
+  Sched* s = &ls;
   Ctl* c = p.ctl;
   __shared__ Counters k;
   __shared__ uint32_t s_next, s_fc, s_fmin;  // s_next 0: decided; 1: next bucket after s.bucket; 2: after a far step
@@ -751,8 +773,8 @@ __device__ void after_step(const Params& p, Sched* s) {
   }
   __syncthreads();
   const uint32_t next = s_next;
-  if (next == 1) choose_next<W>(p, s, k, s->bucket + 1u, p.ring - 1u, s_fc, s_fmin);
-  else if (next == 2) choose_next<W>(p, s, k, s->far_base, p.ring, s_fc, s_fmin);
+  if (next == 1) choose_next<W>(k, s->bucket + 1u, p.ring - 1u, s_fc, s_fmin);
+  else if (next == 2) choose_next<W>(k, s->far_base, p.ring, s_fc, s_fmin);
   if (threadIdx.x == 0) publish_sched(c, *s);
   __syncthreads();
 }
@@ -760,7 +782,9 @@ __device__ void after_step(const Params& p, Sched* s) {
 // Edges a light or heavy step would scan (its list has at most kWG entries);
 // each thread keeps its entry for the phase that may follow on this workgroup.
 template <bool kLight, class T>
-__device__ uint32_t step_edges(const Params& p, const T* t, const Sched& s, uint32_t* s_wsum, Entry<T>* e) {
+__device__ uint32_t step_edges(const T* t, uint32_t* s_wsum, Entry<T>* e) {
+  const Params& p = lp;
+  const Sched& s = ls;
   const uint32_t* list = phase_list(p, s, kLight);
   uint32_t deg = 0;
   if (threadIdx.x < s.in_count) {
@@ -777,24 +801,26 @@ __device__ uint32_t step_edges(const Params& p, const T* t, const Sched& s, uint
 // The leader's part of a barrier: schedule the step after `s`; while that step
 // is a small light or heavy phase, run it on this workgroup alone and schedule again.
 template <class W>
-__device__ void lead(const Params& p, typename W::T* t, Sched* s, WgStats& st, Stage& sg, bool schedule_first) {
+__device__ void lead(typename W::T* t, bool schedule_first) {
+  const Params& p = lp;
+  Sched* s = &ls;
   __shared__ uint32_t s_wsum[kWG / 64];
-  if (schedule_first) after_step<W>(p, s);
+  if (schedule_first) after_step<W>();
   for (;;) {  // *s is the current schedule (set by leader_start or after_step)
     const bool light = s->action == kActLight;
     if (!(light || s->action == kActHeavy) || s->in_count > static_cast<uint32_t>(kChunk)) break;
     Entry<typename W::T> e{};
-    const uint32_t edges = light ? step_edges<true>(p, t, *s, s_wsum, &e) : step_edges<false>(p, t, *s, s_wsum, &e);
+    const uint32_t edges = light ? step_edges<true>(t, s_wsum, &e) : step_edges<false>(t, s_wsum, &e);
     if (edges > p.inline_edges) break;
     drain_stores();  // the counter resets of after_step land before this step's appends
     __syncthreads();
     if (threadIdx.x == 0) record_trace(p.ctl, 0x80u);
-    if (light) phase<W, true>(p, t, *s, st, sg, true, true, e);
-    else phase<W, false>(p, t, *s, st, sg, true, true, e);
-    trace_step_counts(p.ctl, st);
+    if (light) phase<W, true>(t, true, true, e);
+    else phase<W, false>(t, true, true, e);
+    trace_step_counts(p.ctl);
     drain_stores();
     __syncthreads();
-    after_step<W>(p, s);
+    after_step<W>();
   }
 }
 
@@ -802,8 +828,8 @@ __device__ void lead(const Params& p, typename W::T* t, Sched* s, WgStats& st, S
 // the batch and initialise its solve, or mark the group finished. A row is one
 // source, or (multi) all k sources at once in a single row.
 template <class W>
-__device__ void leader_claim(const Params& p, typename W::T* t, const int32_t* sources, int k, int multi, bool reset_tags,
-                             Sched* s, WgStats& st, Stage& sg) {
+__device__ void leader_claim(typename W::T* t, const int32_t* sources, int k, int multi, bool reset_tags) {
+  const Params& p = lp;
   __shared__ uint32_t s_row;
   Ctl* c = p.ctl;
   if (threadIdx.x == 0) {
@@ -815,24 +841,25 @@ __device__ void leader_claim(const Params& p, typename W::T* t, const int32_t* s
   __syncthreads();
   const uint32_t r = s_row;
   if (r == kNone) return;
-  leader_start<W>(p, t, multi ? sources : sources + r, multi ? k : 1, reset_tags, s);
-  lead<W>(p, t, s, st, sg, false);  // the first phases (around the seeds) are usually small
+  leader_start<W>(t, multi ? sources : sources + r, multi ? k : 1, reset_tags);
+  lead<W>(t, false);  // the first phases (around the seeds) are usually small
 }
 
 template <class W>
 __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ params, uint32_t groups,
                                                      const int32_t* sources, int k, int multi, void* dist) {
   using T = typename W::T;
-  __shared__ Sched s;
-  __shared__ Stage sg;
   __shared__ uint32_t s_row, s_gen;
-  const Params& p = params[blockIdx.x % groups];
+  if (threadIdx.x == 0) {
+    lp = params[blockIdx.x % groups];
+    lsg.n = 0;
+    lst = WgStats{0, 0, 0, 0, 0};
+  }
+  __syncthreads();
+  const Params& p = lp;
   const uint32_t rank = grp_rank(p), size = grp_size(p);
   Ctl* c = p.ctl;
   init_gen(c, &s_gen);
-  if (threadIdx.x == 0) sg.n = 0;
-  __syncthreads();
-  WgStats st{0, 0, 0, 0, 0};
   bool alive = true;
   for (uint32_t it = 0; alive; ++it) {
     // the de-duplication tags grow by one per step and per bucket: long before
@@ -853,40 +880,35 @@ __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ 
         st_agent(&p.fstamp[v], 0u);
       }
     }
-    alive = grid_sync(c, size, rank, &s_gen, [&] { leader_claim<W>(p, t, sources, k, multi, reset_tags, &s, st, sg); });
+    alive = grid_sync(c, size, rank, &s_gen, [&] { leader_claim<W>(t, sources, k, multi, reset_tags); });
     if (threadIdx.x == 0) s_row = ld_agent(&c->source_index);
     __syncthreads();
     const uint32_t row = s_row;
     if (!alive || row == kNone) break;
     while (alive) {
-      load_sched(c, &s);
-      const uint32_t a = s.action;
+      load_sched(c);
+      const uint32_t a = ls.action;
       if (a == kActDone) break;
-      if (a == kActLight) phase<W, true>(p, t, s, st, sg, false);
-      else if (a == kActHeavy) phase<W, false>(p, t, s, st, sg, false);
-      else if (a == kActHub) hub_step<W>(p, t, s, st, sg);
-      else if (a == kActFar) far_step<W>(p, t, s);
-      else if (a == kActOverflowCheck) overflow_step<W>(p, t);
+      if (a == kActLight) phase<W, true>(t, false);
+      else if (a == kActHeavy) phase<W, false>(t, false);
+      else if (a == kActHub) hub_step<W>(t);
+      else if (a == kActFar) far_step<W>(t);
+      else if (a == kActOverflowCheck) overflow_step<W>(t);
       else if (threadIdx.x == 0) st_agent(&c->abort, 1u);
-      trace_step_counts(c, st);
-      alive = grid_sync(c, size, rank, &s_gen, [&] { lead<W>(p, t, &s, st, sg, true); });
+      trace_step_counts(c);
+      alive = grid_sync(c, size, rank, &s_gen, [&] { lead<W>(t, true); });
     }
     if (alive) {  // the source's row of the output, in the caller's vertex numbering
       T* out = static_cast<T*>(dist) + static_cast<size_t>(row) * p.n;
       for (uint32_t v = rank * kWG + threadIdx.x; v < p.n; v += size * kWG) *gp(&out[v]) = ld_agent(&t[ldg(&p.vid[v])]);
     }
   }
-  // fold per-lane counters into the group's control block
-  unsigned long long le = st.light_edges, he = st.heavy_edges, im = st.improvements;
-  for (int d = 32; d > 0; d >>= 1) {
-    le += __shfl_down(le, d);
-    he += __shfl_down(he, d);
-    im += __shfl_down(im, d);
-  }
-  if (lane() == 0) {
-    if (le) g_add(&c->light_edges, le);
-    if (he) g_add(&c->heavy_edges, he);
-    if (im) g_add(&c->improvements, im);
+  // add this workgroup's counters to the group's control block
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (lst.light_edges) g_add(&c->light_edges, lst.light_edges);
+    if (lst.heavy_edges) g_add(&c->heavy_edges, lst.heavy_edges);
+    if (lst.improvements) g_add(&c->improvements, lst.improvements);
   }
 }
 
