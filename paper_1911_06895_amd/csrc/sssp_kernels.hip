@@ -367,10 +367,20 @@ __device__ inline void queue_hub(uint32_t u, uint32_t deg) {
 // consecutive lanes read consecutive edges of a row. Vertices with kHub or
 // more edges are queued as pieces for a grid-wide hub step instead.
 // List entries per claimed chunk: enough chunks for about four per workgroup.
+// Chunk sizes are powers of two (the edge-to-entry search relies on it).
+static_assert((kChunk & (kChunk - 1)) == 0 && (kMinChunk & (kMinChunk - 1)) == 0, "chunk sizes are powers of two");
 __device__ inline uint32_t chunk_for(uint32_t count, uint32_t size) {
   const uint32_t target = (count + 4 * size - 1) / (4 * size);
   uint32_t c = kMinChunk;
   while (c < target && c < kChunk) c <<= 1;
+  return c;
+}
+
+// A step run by the leader workgroup alone takes its whole list (at most
+// kChunk entries) as one chunk, of the next power of two.
+__device__ inline uint32_t solo_chunk(uint32_t count) {
+  uint32_t c = kMinChunk;
+  while (c < count && c < kChunk) c <<= 1;
   return c;
 }
 
@@ -400,7 +410,7 @@ __device__ void phase(typename W::T* t, bool solo, bool preloaded = false,
   const uint32_t count = s.in_count;
   const uint64_t near_end = static_cast<uint64_t>(s.bucket) + p.ring;  // no wrap near 2^32
   const uint32_t size = grp_size(p);
-  const uint32_t chunk = solo ? kChunk : chunk_for(count, size);
+  const uint32_t chunk = solo ? solo_chunk(count) : chunk_for(count, size);
   const uint32_t nchunks = (count + chunk - 1) / chunk;
 
   for (uint32_t c = solo ? 0u : grp_rank(p); c < nchunks; c = claim_next(p.ctl, c, nchunks, solo, size, &s_claim)) {
@@ -453,28 +463,37 @@ __device__ void phase(typename W::T* t, bool solo, bool preloaded = false,
     const uint32_t rounds = (total + kWG * kILP - 1) / (kWG * kILP);
     for (uint32_t r = 0; r < rounds; ++r) {
       bool active[kILP];
-      uint32_t v[kILP];
+      uint32_t v[kILP], e[kILP], at[kILP];
       typename W::Wt w[kILP];
       T tw[kILP];
 #pragma unroll
       for (uint32_t q = 0; q < kILP; ++q) {
-        const uint32_t e = (r * kILP + q) * kWG + threadIdx.x;
-        active[q] = e < total;
+        e[q] = (r * kILP + q) * kWG + threadIdx.x;
+        active[q] = e[q] < total;
+        at[q] = 0;
+      }
+      // the entry owning edge e: the last one whose range starts at or before e
+      // (the prefix sums do not decrease; chunk is a power of two, so every
+      // search takes log2(chunk) steps and the kILP searches advance together,
+      // their LDS reads in flight at once)
+      if (active[0]) {  // e[0] is this lane's lowest edge
+        for (uint32_t half = chunk >> 1; half > 0; half >>= 1) {
+#pragma unroll
+          for (uint32_t q = 0; q < kILP; ++q)
+            if (s_pref[at[q] + half] <= e[q]) at[q] += half;
+        }
+      }
+#pragma unroll
+      for (uint32_t q = 0; q < kILP; ++q) {
         v[q] = 0;
         w[q] = 0;
         tw[q] = W::kInf;
         if (active[q]) {
-          uint32_t lo = 0, hi = chunk - 1;  // last entry whose range starts at or before e
-          while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (s_pref[mid] <= e) lo = mid;
-            else hi = mid - 1;
-          }
-          const uint32_t pos = s_beg[lo] + (e - s_pref[lo]);
+          const uint32_t pos = s_beg[at[q]] + (e[q] - s_pref[at[q]]);
           const uint64_t ed = ldg(&p.edges[pos]);
           v[q] = static_cast<uint32_t>(ed);
           w[q] = W::weight(p, ed, pos);
-          tw[q] = s_tu[lo];
+          tw[q] = s_tu[at[q]];
         }
       }
       relax_batch<W>(t, active, tw, v, w, near_end);
