@@ -224,15 +224,12 @@ __device__ inline void stage_push(bool push, uint32_t slot, uint32_t v) {
   }
 }
 
-// Move the staged appends to their lists. Unless `force`, only when another
-// round of kWG * kILP appends might not fit. All threads of the workgroup call it.
-__device__ void stage_flush(bool force) {
+// Move the n staged appends to their lists. All threads of the workgroup call
+// it with the same n (read between two barriers, so no append raced the read).
+__device__ void stage_flush_now(uint32_t n) {
   const Params& p = lp;
   const Sched& s = ls;
   Stage& sg = lsg;
-  __syncthreads();
-  const uint32_t n = sg.n;
-  if (n == 0 || (!force && n <= kStage - kWG * kILP)) return;
   if (threadIdx.x < kSlots) sg.cnt[threadIdx.x] = 0;
   __syncthreads();
   // rank of each entry within its destination: lanes grouped by destination, one LDS atomic per group
@@ -283,30 +280,36 @@ __device__ void stage_flush(bool force) {
   __syncthreads();
 }
 
-// kILP requests (v, t(u) (+) w) per lane: t(v) = min(t(v), request) (Sec. III-C
-// relax; Sec. IV-C/IV-D t = min(t, t_Req)), then file each improved v by the
-// bucket of its new tentative distance: back into the current bucket's frontier
-// (the re-insertion mask (i*delta <= t_Req < (i+1)*delta) o (t_Req < t) of
-// Sec. IV-C), into the ring of near buckets, or into the far list. The loads and
-// atomics of the kILP requests are independent and overlap in flight.
+// A relaxation of (v, t(u) (+) w): t(v) = min(t(v), request) (Sec. III-C relax;
+// Sec. IV-C/IV-D t = min(t, t_Req)), then v is filed by the bucket of its new
+// tentative distance: back into the current bucket's frontier (the
+// re-insertion mask (i*delta <= t_Req < (i+1)*delta) o (t_Req < t) of
+// Sec. IV-C), into the ring of near buckets, or into the far list.
+//
+// It runs in two parts. The prefilter compares each request with a cached
+// (possibly stale, never lower) copy of t(v); most requests end there. Those
+// that pass are queued in LDS, and the queue is drained in bulk by the whole
+// workgroup: the atomic min on t(v) and the filing, whose round trips are
+// then shared by many requests instead of stalling every round.
+constexpr uint32_t kQueue = 2048;  // LDS candidates; drained once half full at a round boundary
+
+struct Queue {
+  uint32_t v[kQueue];
+  uint64_t c[kQueue];  // candidate distance bits
+  uint32_t n;          // may pass kQueue: the excess was relaxed directly
+};
+__shared__ Queue lq;
+
+// The atomic part for kILP candidates per lane (their atomics overlap in flight).
 template <class W>
-__device__ inline void relax_batch(typename W::T* t, const bool (&active)[kILP], const typename W::T (&tu)[kILP],
-                                   const uint32_t (&v)[kILP], const typename W::Wt (&w)[kILP], uint64_t near_end) {
+__device__ inline void relax_candidates(typename W::T* t, const bool (&active)[kILP],
+                                        const typename W::T (&cand)[kILP], const uint32_t (&v)[kILP],
+                                        uint64_t near_end) {
   const Params& p = lp;
   const Sched& s = ls;
-  typename W::T cand[kILP], tv[kILP];
-  bool ok[kILP], win[kILP];
+  bool win[kILP];
 #pragma unroll
-  for (uint32_t q = 0; q < kILP; ++q) {
-    ok[q] = active[q] && W::add(tu[q], w[q], &cand[q]);
-    if (active[q] && !ok[q]) {
-      st_agent(&p.ovf_at[v[q]], 1u);
-      st_agent(&p.ctl->ovf_seen, 1u);
-    }
-    tv[q] = ok[q] ? ldg(&t[v[q]]) : typename W::T(0);  // may be stale, but never below the current value
-  }
-#pragma unroll
-  for (uint32_t q = 0; q < kILP; ++q) win[q] = ok[q] && cand[q] < tv[q] && cand[q] < g_min(&t[v[q]], cand[q]);
+  for (uint32_t q = 0; q < kILP; ++q) win[q] = active[q] && cand[q] < g_min(&t[v[q]], cand[q]);
   uint32_t slot[kILP];
 #pragma unroll
   for (uint32_t q = 0; q < kILP; ++q) {
@@ -333,6 +336,109 @@ __device__ inline void relax_batch(typename W::T* t, const bool (&active)[kILP],
     count_add(&lst.improvements, nwin);
     count_add(&lst.step_impr, nwin);
   }
+}
+
+// Queue the lanes' candidates; returns true for a candidate that found the
+// queue full (the caller relaxes it at once).
+__device__ inline bool queue_push(bool pass, uint32_t v, uint64_t c) {
+  const uint64_t mask = __ballot(pass);
+  if (mask == 0) return false;
+  const int leader = first_lane(mask);
+  uint32_t b = 0;
+  if (static_cast<int>(lane()) == leader) b = atomicAdd(&lq.n, static_cast<uint32_t>(__popcll(mask)));
+  b = __shfl(b, leader);
+  if (!pass) return false;
+  const uint32_t i = b + lanes_below(mask);
+  if (i >= kQueue) return true;
+  lq.v[i] = v;
+  lq.c[i] = c;
+  return false;
+}
+
+// The prefilter for kILP requests (v, t(u) (+) w) per lane.
+template <class W>
+__device__ inline void relax_batch(typename W::T* t, const bool (&active)[kILP], const typename W::T (&tu)[kILP],
+                                   const uint32_t (&v)[kILP], const typename W::Wt (&w)[kILP], uint64_t near_end) {
+  using T = typename W::T;
+  const Params& p = lp;
+  T cand[kILP], tv[kILP];
+  bool ok[kILP];
+#pragma unroll
+  for (uint32_t q = 0; q < kILP; ++q) {
+    ok[q] = active[q] && W::add(tu[q], w[q], &cand[q]);
+    if (active[q] && !ok[q]) {
+      st_agent(&p.ovf_at[v[q]], 1u);
+      st_agent(&p.ctl->ovf_seen, 1u);
+    }
+    tv[q] = ok[q] ? ldg(&t[v[q]]) : T(0);  // may be stale, but never below the current value
+  }
+  bool direct[kILP];
+  bool any = false;
+#pragma unroll
+  for (uint32_t q = 0; q < kILP; ++q) {
+    direct[q] = queue_push(ok[q] && cand[q] < tv[q], v[q], static_cast<uint64_t>(cand[q]));
+    any |= direct[q];
+  }
+  if (__ballot(any)) relax_candidates<W>(t, direct, cand, v, near_end);
+}
+
+// The staged-append and queue counts as every thread sees them: read between
+// two barriers, so that no append or push of a faster wave races the reads.
+__device__ inline void read_counts(uint32_t* staged, uint32_t* queued) {
+  __syncthreads();
+  *staged = lsg.n;
+  *queued = lq.n;
+  __syncthreads();
+}
+
+// Flush the staged appends when another round of kWG * kILP might not fit.
+__device__ inline void stage_room() {
+  uint32_t staged, queued;
+  read_counts(&staged, &queued);
+  if (staged > kStage - kWG * kILP) stage_flush_now(staged);
+}
+
+// Relax the `queued` candidates (read with read_counts) and empty the queue.
+// All threads call it; the staging has room for kQueue appends.
+template <class W>
+__device__ void drain_queue(typename W::T* t, uint64_t near_end, uint32_t queued) {
+  using T = typename W::T;
+  static_assert(kQueue <= kWG * kILP, "one pass drains the queue");
+  const uint32_t n = min(queued, kQueue);
+  for (uint32_t base = 0; base < n; base += kWG * kILP) {
+    bool active[kILP];
+    T cand[kILP];
+    uint32_t v[kILP];
+#pragma unroll
+    for (uint32_t q = 0; q < kILP; ++q) {
+      const uint32_t i = base + q * kWG + threadIdx.x;
+      active[q] = i < n;
+      v[q] = active[q] ? lq.v[i] : 0u;
+      cand[q] = active[q] ? static_cast<T>(lq.c[i]) : T(0);
+    }
+    relax_candidates<W>(t, active, cand, v, near_end);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) lq.n = 0;
+  __syncthreads();
+}
+
+// After a round of relax_batch: make room in the staging for another round,
+// drain the queue once it is half full, and with `force` (the end of a step)
+// drain and flush everything.
+template <class W>
+__device__ inline void round_end(typename W::T* t, uint64_t near_end, bool force) {
+  uint32_t staged, queued;
+  read_counts(&staged, &queued);
+  if (staged > kStage - kWG * kILP - kQueue) {
+    stage_flush_now(staged);
+    staged = 0;
+  }
+  if (queued >= (force ? 1u : kQueue / 2)) {
+    drain_queue<W>(t, near_end, queued);
+    if (force) read_counts(&staged, &queued);
+  }
+  if (force && staged > 0) stage_flush_now(staged);
 }
 
 // Work distribution over `nitems` items: in a step run by a whole group, the
@@ -440,7 +546,7 @@ __device__ void phase(typename W::T* t, bool solo, bool preloaded = false,
         }
       }
       stage_push(to_s, kSlotS, u);
-      stage_flush(false);
+      stage_room();
     }
     if (!solo && deg >= kHub) {
       queue_hub(u, deg);
@@ -497,11 +603,11 @@ __device__ void phase(typename W::T* t, bool solo, bool preloaded = false,
         }
       }
       relax_batch<W>(t, active, tw, v, w, near_end);
-      stage_flush(false);
+      round_end<W>(t, near_end, false);
     }
     __syncthreads();
   }
-  stage_flush(true);
+  round_end<W>(t, near_end, true);
 }
 
 // Hub step: pieces of kPiece consecutive edges of the high-degree vertices
@@ -549,9 +655,9 @@ __device__ void hub_step(typename W::T* t) {
       }
     }
     relax_batch<W>(t, active, tw, v, w, near_end);
-    stage_flush(false);
+    round_end<W>(t, near_end, false);
   }
-  stage_flush(true);
+  round_end<W>(t, near_end, true);
 }
 
 // Far-list redistribution: far vertices whose bucket is now within the ring
@@ -872,6 +978,7 @@ __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ 
   if (threadIdx.x == 0) {
     lp = params[blockIdx.x % groups];
     lsg.n = 0;
+    lq.n = 0;
     lst = WgStats{0, 0, 0, 0, 0};
   }
   __syncthreads();
