@@ -39,12 +39,13 @@ __global__ __launch_bounds__(kWG) void adjoint_kernel(const AdjParams* __restric
   const uint32_t n = a.n;
   const uint32_t tid = rank * kWG + threadIdx.x;
   const uint32_t nthreads = size * kWG;
-  __shared__ uint32_t s_count, s_cur, s_row, s_gen;
-  init_gen(c, &s_gen);
+  __shared__ uint32_t s_count, s_cur, s_row;
+  __shared__ BarrierState s_bar;
+  init_barrier(c, s_bar);
   bool alive = true;
   while (alive) {
     // claim the next source row for this group
-    alive = grid_sync(c, size, rank, &s_gen, [&] {
+    alive = grid_sync(c, size, rank, s_bar, [&] {
       if (threadIdx.x == 0) {
         const uint32_t r = g_add(a.next_source, 1u);
         st_agent(&c->source_index, r < static_cast<uint32_t>(k) ? r : kNone);
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(kWG) void adjoint_kernel(const AdjParams* __restric
       st_agent(&a.cnt[x], 0u);
       st_agent(&a.g[x], (dx < W::kInf && x != s) ? static_cast<double>(ldg(&grow[v])) : 0.0);
     }
-    alive = grid_sync(c, size, rank, &s_gen, [] {});
+    alive = grid_sync(c, size, rank, s_bar, [] {});
     if (!alive) break;
     // 1. parents: one wave per row, lanes over the row's edges
     {
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(kWG) void adjoint_kernel(const AdjParams* __restric
         }
       }
     }
-    alive = grid_sync(c, size, rank, &s_gen, [] {});
+    alive = grid_sync(c, size, rank, s_bar, [] {});
     if (!alive) break;
     // 2. children per vertex; a reached vertex other than s must have a parent
     for (uint32_t y = tid; y < n; y += nthreads) {
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(kWG) void adjoint_kernel(const AdjParams* __restric
       if (pe == kNoParent) st_agent(&c->ovf_real, 1u);  // not a shortest-path vector
       else g_add(&a.cnt[static_cast<uint32_t>(pe)], 1u);
     }
-    alive = grid_sync(c, size, rank, &s_gen, [] {});
+    alive = grid_sync(c, size, rank, s_bar, [] {});
     if (!alive) break;
     // 3. first level: reached vertices without children
     {
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(kWG) void adjoint_kernel(const AdjParams* __restric
         push_wave(a.front[0], &c->fcount[0], leaf, y);
       }
     }
-    alive = grid_sync(c, size, rank, &s_gen, [&] { adjoint_leader_level<W>(c, 1u); });  // in_count = fcount[0], out = 0
+    alive = grid_sync(c, size, rank, s_bar, [&] { adjoint_leader_level<W>(c, 1u); });  // in_count = fcount[0], out = 0
     // 4. levels, leaves towards the source
     while (alive) {
       if (threadIdx.x == 0) {
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(kWG) void adjoint_kernel(const AdjParams* __restric
       }
       // every reached vertex is released exactly once unless the parents form a cycle
       if (released) g_add(&c->adj_released, static_cast<unsigned long long>(released));
-      alive = grid_sync(c, size, rank, &s_gen, [&] { adjoint_leader_level<W>(c, cur); });
+      alive = grid_sync(c, size, rank, s_bar, [&] { adjoint_leader_level<W>(c, cur); });
     }
   }
 }

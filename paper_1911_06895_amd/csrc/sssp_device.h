@@ -183,8 +183,9 @@ __device__ inline void drain_stores() {
   __builtin_amdgcn_s_waitcnt(0);
 }
 
-__device__ inline void record_trace(Ctl* c, uint32_t flags) {
-  unsigned long long* trace = ldg(&c->trace);
+// One record of a traced run (`trace`: the control block's trace buffer, null
+// when the run is not traced).
+__device__ inline void record_trace(Ctl* c, unsigned long long* trace, uint32_t flags) {
   if (!trace) return;
   const uint32_t idx = g_add(&c->trace_len, 1u);
   if (idx < ldg(&c->trace_cap)) {
@@ -202,18 +203,26 @@ __device__ inline void record_trace(Ctl* c, uint32_t flags) {
 // `c` (this one has index `rank` among them). Arrivals are counted first per
 // sub-group (rank % 8), then once per sub-group, which keeps same-address
 // atomics short. The last workgroup to arrive runs `leader` (all its threads)
-// before releasing the others by advancing the generation word. `gen` (LDS)
-// is this workgroup's copy of the generation (every workgroup passes every
-// barrier, so no load of the word is needed before arriving; init_gen sets it
-// at kernel start). Returns false when the schedule was aborted (a wait ran
-// past kWaitLimitTicks).
-__device__ inline void init_gen(Ctl* c, uint32_t* gen) {
-  if (threadIdx.x == 0) *gen = ld_agent(&c->bar_gen);
+// before releasing the others by advancing the generation word. `b` (LDS) is
+// this workgroup's copy of the generation (every workgroup passes every
+// barrier, so no load of the word is needed before arriving) and of the trace
+// buffer pointer, both loaded by init_barrier at kernel start. Returns false
+// when the schedule was aborted (a wait ran past kWaitLimitTicks).
+struct BarrierState {
+  uint32_t gen;
+  unsigned long long* trace;
+};
+
+__device__ inline void init_barrier(Ctl* c, BarrierState& b) {
+  if (threadIdx.x == 0) {
+    b.gen = ld_agent(&c->bar_gen);
+    b.trace = ldg(&c->trace);
+  }
   __syncthreads();
 }
 
 template <class F>
-__device__ bool grid_sync(Ctl* c, uint32_t size, uint32_t rank, uint32_t* gen_lds, F&& leader) {
+__device__ bool grid_sync(Ctl* c, uint32_t size, uint32_t rank, BarrierState& b, F&& leader) {
   __shared__ uint32_t s_is_leader;
   __shared__ uint32_t s_ok;
   drain_stores();
@@ -223,7 +232,7 @@ __device__ bool grid_sync(Ctl* c, uint32_t size, uint32_t rank, uint32_t* gen_ld
     const uint32_t groups = size < kBarGroups ? size : kBarGroups;
     const uint32_t g = rank % groups;
     const uint32_t gsize = (size - g + groups - 1) / groups;
-    gen = *gen_lds;
+    gen = b.gen;
     bool last = false;
     const uint32_t prev = g_add(&c->bar_sub[g][0], 1u);
     if (prev == gsize - 1) {
@@ -234,9 +243,13 @@ __device__ bool grid_sync(Ctl* c, uint32_t size, uint32_t rank, uint32_t* gen_ld
     s_is_leader = last ? 1u : 0u;
     uint32_t ok = 1;
     if (!last) {
+      // the generation and the abort flag are loaded together: one round trip per poll
       const unsigned long long t0 = wall_clock64();
-      while (ld_agent(&c->bar_gen) == gen) {
-        if (ld_agent(&c->abort) != 0u || wall_clock64() - t0 > kWaitLimitTicks) {
+      for (;;) {
+        const uint32_t g_now = ld_agent(&c->bar_gen);
+        const uint32_t abort_now = ld_agent(&c->abort);
+        if (g_now != gen) break;
+        if (abort_now != 0u || wall_clock64() - t0 > kWaitLimitTicks) {
           st_agent(&c->abort, 1u);
           ok = 0;
           break;
@@ -253,14 +266,14 @@ __device__ bool grid_sync(Ctl* c, uint32_t size, uint32_t rank, uint32_t* gen_ld
     __syncthreads();
     if (threadIdx.x == 0) {
       g_add(&c->barriers, 1ull);
-      record_trace(c, 0u);
+      record_trace(c, b.trace, 0u);
       drain_stores();
       st_agent(&c->bar_gen, gen + 1u);
     }
   }
   const bool ok = s_ok != 0u;
   __syncthreads();
-  if (threadIdx.x == 0) *gen_lds = gen + 1u;
+  if (threadIdx.x == 0) b.gen = gen + 1u;
   return ok;
 }
 

@@ -72,6 +72,7 @@ __shared__ Params lp;
 __shared__ Sched ls;
 __shared__ Stage lsg;
 __shared__ WgStats lst;
+__shared__ BarrierState lbar;
 
 __device__ inline void count_add(unsigned long long* field, unsigned long long v) {
   if (v) atomicAdd(field, v);
@@ -170,7 +171,7 @@ __device__ inline const uint32_t* phase_list(const Params& p, const Sched& s, bo
 // Traced runs only: add this workgroup's counts of the finished step to the
 // control block (one atomic per workgroup), for the next trace record.
 __device__ inline void trace_step_counts(Ctl* c) {
-  if (!ldg(&c->trace)) return;
+  if (!lbar.trace) return;
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned long long te = lst.step_edges, ti = lst.step_impr;
@@ -939,7 +940,7 @@ __device__ void lead(typename W::T* t, bool schedule_first) {
     if (edges > p.inline_edges) break;
     drain_stores();  // the counter resets of after_step land before this step's appends
     __syncthreads();
-    if (threadIdx.x == 0) record_trace(p.ctl, 0x80u);
+    if (threadIdx.x == 0) record_trace(p.ctl, lbar.trace, 0x80u);
     if (light) phase<W, true>(t, true, true, e);
     else phase<W, false>(t, true, true, e);
     trace_step_counts(p.ctl);
@@ -974,7 +975,7 @@ template <class W>
 __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ params, uint32_t groups,
                                                      const int32_t* sources, int k, int multi, void* dist) {
   using T = typename W::T;
-  __shared__ uint32_t s_row, s_gen;
+  __shared__ uint32_t s_row;
   if (threadIdx.x == 0) {
     lp = params[blockIdx.x % groups];
     lsg.n = 0;
@@ -985,7 +986,7 @@ __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ 
   const Params& p = lp;
   const uint32_t rank = grp_rank(p), size = grp_size(p);
   Ctl* c = p.ctl;
-  init_gen(c, &s_gen);
+  init_barrier(c, lbar);
   bool alive = true;
   for (uint32_t it = 0; alive; ++it) {
     // the de-duplication tags grow by one per step and per bucket: long before
@@ -1006,7 +1007,7 @@ __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ 
         st_agent(&p.fstamp[v], 0u);
       }
     }
-    alive = grid_sync(c, size, rank, &s_gen, [&] { leader_claim<W>(t, sources, k, multi, reset_tags); });
+    alive = grid_sync(c, size, rank, lbar, [&] { leader_claim<W>(t, sources, k, multi, reset_tags); });
     if (threadIdx.x == 0) s_row = ld_agent(&c->source_index);
     __syncthreads();
     const uint32_t row = s_row;
@@ -1022,7 +1023,7 @@ __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ 
       else if (a == kActOverflowCheck) overflow_step<W>(t);
       else if (threadIdx.x == 0) st_agent(&c->abort, 1u);
       trace_step_counts(c);
-      alive = grid_sync(c, size, rank, &s_gen, [&] { lead<W>(t, true); });
+      alive = grid_sync(c, size, rank, lbar, [&] { lead<W>(t, true); });
     }
     if (alive) {  // the source's row of the output, in the caller's vertex numbering
       T* out = static_cast<T*>(dist) + static_cast<size_t>(row) * p.n;
