@@ -501,8 +501,8 @@ struct Entry {
 };
 
 template <class W, bool kLight>
-__device__ void phase(typename W::T* t, bool solo, bool preloaded = false,
-                      Entry<typename W::T> pre = Entry<typename W::T>{}) {
+__device__ __attribute__((always_inline)) void phase(typename W::T* t, bool solo, bool preloaded = false,
+                                                     Entry<typename W::T> pre = Entry<typename W::T>{}) {
   using T = typename W::T;
   const Params& p = lp;
   const Sched& s = ls;
@@ -609,6 +609,15 @@ __device__ void phase(typename W::T* t, bool solo, bool preloaded = false,
     __syncthreads();
   }
   round_end<W>(t, near_end, true);
+}
+
+// The leader's steps run alone (inside the barrier) call this out-of-line
+// copy; the group-wide steps of the kernel's loop have the phase inlined, so
+// that their workgroups do not save and restore registers around a call at
+// every step.
+template <class W, bool kLight>
+__device__ __attribute__((noinline)) void phase_solo(typename W::T* t, Entry<typename W::T> pre) {
+  phase<W, kLight>(t, true, true, pre);
 }
 
 // Hub step: pieces of kPiece consecutive edges of the high-degree vertices
@@ -941,8 +950,8 @@ __device__ void lead(typename W::T* t, bool schedule_first) {
     drain_stores();  // the counter resets of after_step land before this step's appends
     __syncthreads();
     if (threadIdx.x == 0) record_trace(p.ctl, lbar.trace, 0x80u);
-    if (light) phase<W, true>(t, true, true, e);
-    else phase<W, false>(t, true, true, e);
+    if (light) phase_solo<W, true>(t, e);
+    else phase_solo<W, false>(t, e);
     trace_step_counts(p.ctl);
     drain_stores();
     __syncthreads();
