@@ -222,7 +222,7 @@ sssp_status alloc_group(sssp_handle* h, GroupMem* gm) {
   for (uint32_t** q : words) SSSP_TRY(dalloc(q, un));
   for (void** q : {&gm->tbuf[0], &gm->tbuf[1]}) SSSP_TRY(hipMalloc(q, un * dist_bytes(h->wtype)));
   SSSP_TRY(dalloc(&gm->bins, un * h->p.ring));
-  SSSP_TRY(dalloc(&gm->hub, h->p.hub_cap));
+  SSSP_TRY(dalloc(&gm->hub, 2 * static_cast<size_t>(h->p.hub_cap)));
   uint32_t* zero[] = {gm->qstamp, gm->sstamp, gm->fstamp, gm->ovf_at};
   for (uint32_t* q : zero) SSSP_TRY(hipMemset(q, 0, un * sizeof(uint32_t)));
   return SSSP_OK;
@@ -346,7 +346,7 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   // each vertex appears at most once in a phase's list, so the pieces of its
   // high-degree vertices number at most m / kPiece + m / kHub
   p.hub_cap = static_cast<uint32_t>(um / sssp::kPiece + um / sssp::kHub + 16);
-  SSSP_TRY(dalloc(&p.hub, p.hub_cap));
+  SSSP_TRY(dalloc(&p.hub, 2 * static_cast<size_t>(p.hub_cap)));
   p.inline_edges = h->tuning.inline_edges > 0 ? static_cast<uint32_t>(h->tuning.inline_edges) : kDefaultInlineEdges;
   SSSP_TRY(dalloc(&p.front[0], un));
   SSSP_TRY(dalloc(&p.front[1], un));

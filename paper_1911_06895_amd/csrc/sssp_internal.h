@@ -91,7 +91,11 @@ struct Ctl {
   uint32_t source_index;  // source (row) the group is solving, kNone when the batch is done
   alignas(128) uint32_t chunk_next;  // dynamic chunk counter of the current step
   alignas(128) uint32_t hub_count;   // hub pieces queued by the current phase
-  uint32_t hub_parent;   // action of the phase that queued them
+  alignas(128) uint32_t hub_next;    // dynamic claim counter of the pieces processed by the current step
+  // schedule of the pieces processed by the current step
+  alignas(128) uint32_t hub_parent;  // action of the phase that queued them
+  uint32_t hub_backlog;  // pieces to process (a hub step, or a light phase finishing the previous one's)
+  uint32_t hub_in;       // queue buffer holding them; a phase appends to the other one
   // schedule
   alignas(128) uint32_t action;
   uint32_t bucket;       // current bucket i
@@ -148,7 +152,7 @@ struct Params {
   uint32_t* slist;        // [n] S
   uint32_t* bins;         // [ring][n]
   uint32_t* far[2];       // [n] far lists
-  uint64_t* hub;          // [hub_cap] pieces (vertex | piece index << 32)
+  uint64_t* hub;          // [2][hub_cap] pieces (vertex | piece index << 32), two alternating queues
   uint32_t hub_cap;
   uint32_t inline_edges;  // steps with at most this many edges run on the leader workgroup alone
   uint32_t groups;        // workgroup groups of the launch, each solving its own sources

@@ -35,7 +35,7 @@ __device__ inline uint32_t grp_size(const Params& p) { return gridDim.x / p.grou
 
 struct Sched {
   uint32_t action, bucket, in_kind, in_count, out_buf, step, round, far_epoch, far_cur, far_base;
-  uint32_t hub_count, hub_parent;
+  uint32_t hub_parent, hub_backlog, hub_in;
   uint64_t lo_u, hi_u;
 };
 
@@ -94,7 +94,8 @@ __device__ inline void load_sched(Ctl* c) {
                    in_count = ld_agent(&c->in_count), out_buf = ld_agent(&c->out_buf), step = ld_agent(&c->step),
                    round = ld_agent(&c->round), far_epoch = ld_agent(&c->far_epoch),
                    far_cur = ld_agent(&c->far_cur), far_base = ld_agent(&c->far_base),
-                   hub_count = ld_agent(&c->hub_count), hub_parent = ld_agent(&c->hub_parent);
+                   hub_parent = ld_agent(&c->hub_parent), hub_backlog = ld_agent(&c->hub_backlog),
+                   hub_in = ld_agent(&c->hub_in);
     const uint64_t lo_u = ld_agent(&c->lo_u), hi_u = ld_agent(&c->hi_u);
     s->action = action;
     s->bucket = bucket;
@@ -106,8 +107,9 @@ __device__ inline void load_sched(Ctl* c) {
     s->far_epoch = far_epoch;
     s->far_cur = far_cur;
     s->far_base = far_base;
-    s->hub_count = hub_count;
     s->hub_parent = hub_parent;
+    s->hub_backlog = hub_backlog;
+    s->hub_in = hub_in;
     s->lo_u = lo_u;
     s->hi_u = hi_u;
   }
@@ -127,6 +129,8 @@ __device__ inline void publish_sched(Ctl* c, const Sched& s) {
   st_agent(&c->far_epoch, s.far_epoch);
   st_agent(&c->far_cur, s.far_cur);
   st_agent(&c->hub_parent, s.hub_parent);
+  st_agent(&c->hub_backlog, s.hub_backlog);
+  st_agent(&c->hub_in, s.hub_in);
   st_agent(&c->lo_u, s.lo_u);
   st_agent(&c->hi_u, s.hi_u);
 }
@@ -447,12 +451,12 @@ __device__ inline void round_end(typename W::T* t, uint64_t near_end, bool force
 // workgroup of rank b first takes item b with no atomic, then claims further
 // items from a shared counter; the leader workgroup running a step alone walks
 // every item in order.
-__device__ inline uint32_t claim_next(Ctl* c, uint32_t prev, uint32_t nitems, bool solo, uint32_t size,
+__device__ inline uint32_t claim_next(uint32_t* counter, uint32_t prev, uint32_t nitems, bool solo, uint32_t size,
                                       uint32_t* s_claim) {
   if (solo) return prev + 1;
   if (nitems <= size) return nitems;  // every item was taken statically
   __syncthreads();
-  if (threadIdx.x == 0) *s_claim = size + g_add(&c->chunk_next, 1u);
+  if (threadIdx.x == 0) *s_claim = size + g_add(counter, 1u);
   __syncthreads();
   return *s_claim;
 }
@@ -461,9 +465,10 @@ __device__ inline uint32_t claim_next(Ctl* c, uint32_t prev, uint32_t nitems, bo
 __device__ inline void queue_hub(uint32_t u, uint32_t deg) {
   const Params& p = lp;
   const uint32_t pieces = (deg + kPiece - 1) / kPiece;
+  uint64_t* queue = p.hub + static_cast<size_t>(1u - ls.hub_in) * p.hub_cap;
   const uint32_t base = g_add(&p.ctl->hub_count, pieces);
   for (uint32_t k = 0; k < pieces && base + k < p.hub_cap; ++k)
-    st_agent(&p.hub[base + k], static_cast<uint64_t>(u) | (static_cast<uint64_t>(k) << 32));
+    st_agent(&queue[base + k], static_cast<uint64_t>(u) | (static_cast<uint64_t>(k) << 32));
 }
 
 // One relaxation phase: every vertex u of the input list sends t(u) (+) w along
@@ -501,6 +506,9 @@ struct Entry {
   uint4 row;
 };
 
+template <class W>
+__device__ void hub_pieces(typename W::T* t, bool light);
+
 template <class W, bool kLight>
 __device__ __attribute__((always_inline)) void phase(typename W::T* t, bool solo, bool preloaded = false,
                                                      Entry<typename W::T> pre = Entry<typename W::T>{}) {
@@ -520,8 +528,11 @@ __device__ __attribute__((always_inline)) void phase(typename W::T* t, bool solo
   const uint32_t size = grp_size(p);
   const uint32_t chunk = solo ? solo_chunk(count) : chunk_for(count, size);
   const uint32_t nchunks = (count + chunk - 1) / chunk;
+  if constexpr (kLight) {
+    if (!solo && s.hub_backlog > 0) hub_pieces<W>(t, true);  // the previous light phase's pieces
+  }
 
-  for (uint32_t c = solo ? 0u : grp_rank(p); c < nchunks; c = claim_next(p.ctl, c, nchunks, solo, size, &s_claim)) {
+  for (uint32_t c = solo ? 0u : grp_rank(p); c < nchunks; c = claim_next(&p.ctl->chunk_next, c, nchunks, solo, size, &s_claim)) {
     const uint32_t k = c * chunk + threadIdx.x;
     uint32_t beg = 0, deg = 0, u = 0;
     T tu = W::kInf;
@@ -621,22 +632,28 @@ __device__ __attribute__((noinline)) void phase_solo(typename W::T* t, Entry<typ
   phase<W, kLight>(t, true, true, pre);
 }
 
-// Hub step: pieces of kPiece consecutive edges of the high-degree vertices
-// queued by the previous phase, spread over all workgroups.
+constexpr uint32_t kHandOverMinGroup = 128;  // workgroups
+
+// Hub pieces: kPiece consecutive edges of the high-degree vertices queued by
+// the previous phase (light or heavy edges, per `light`), spread over all
+// workgroups. They are a step of their own (a hub step), or, when the
+// previous phase was a light phase whose frontier is not empty, the first
+// work of the next light phase (relaxations commute, and the phase's
+// re-insertions are simply found one phase later).
 template <class W>
-__device__ void hub_step(typename W::T* t) {
+__device__ void hub_pieces(typename W::T* t, bool light) {
   using T = typename W::T;
   const Params& p = lp;
   const Sched& s = ls;
   __shared__ uint32_t s_beg, s_end, s_claim;
   __shared__ T s_tu;
-  const bool light = s.hub_parent == kActLight;
-  const uint32_t count = s.hub_count < p.hub_cap ? s.hub_count : p.hub_cap;
+  const uint64_t* queue = p.hub + static_cast<size_t>(s.hub_in) * p.hub_cap;
+  const uint32_t count = s.hub_backlog < p.hub_cap ? s.hub_backlog : p.hub_cap;
   const uint64_t near_end = static_cast<uint64_t>(s.bucket) + p.ring;  // no wrap near 2^32
   const uint32_t size = grp_size(p);
-  for (uint32_t c = grp_rank(p); c < count; c = claim_next(p.ctl, c, count, false, size, &s_claim)) {
+  for (uint32_t c = grp_rank(p); c < count; c = claim_next(&p.ctl->hub_next, c, count, false, size, &s_claim)) {
     if (threadIdx.x == 0) {
-      const uint64_t rec = ld_agent(&p.hub[c]);
+      const uint64_t rec = ld_agent(&queue[c]);
       const uint32_t u = static_cast<uint32_t>(rec);
       const uint32_t piece = static_cast<uint32_t>(rec >> 32);
       const uint4 row = ldg(&p.rows[u]);
@@ -795,6 +812,7 @@ __device__ void leader_start(typename W::T* t, const int32_t* seeds, int nseeds,
     st_agent(&c->ovf_seen, 0u);
     st_agent(&c->hub_count, 0u);
     st_agent(&c->chunk_next, 0u);
+    st_agent(&c->hub_next, 0u);
     Sched n{};
     n.step = step + 1u;
     n.round = round + 1u;
@@ -845,16 +863,28 @@ __device__ void after_step() {
     Sched n = o;
     uint32_t next = 0;
     st_agent(&c->chunk_next, 0u);
-    const uint32_t hubs = k.w[kCHubs];
+    st_agent(&c->hub_next, 0u);
+    const uint32_t hubs = k.w[kCHubs];  // pieces queued by the finished step (a hub step queues none)
     const bool phase_done = o.action == kActLight || o.action == kActHeavy;
-    if (phase_done && hubs > 0) {  // finish the phase: its high-degree vertices
+    // A light phase that re-inserted vertices hands its pieces to the next light
+    // phase (saving a barrier), in a group that spans most of the device (where
+    // a barrier is dearest) and unless that phase is small enough for the
+    // leader to run alone.
+    const bool hand_over = o.action == kActLight && hubs > 0 && k.w[o.out_buf ? kCF1 : kCF0] > kChunk &&
+                           grp_size(p) >= kHandOverMinGroup;
+    n.hub_backlog = 0;
+    if (phase_done && hubs > 0 && !hand_over) {  // finish the phase: its high-degree vertices
       n.hub_parent = o.action;
-      n.hub_count = hubs;
+      n.hub_backlog = hubs;
+      n.hub_in = 1u - o.hub_in;
       n.action = kActHub;
     } else {
       const uint32_t parent = o.action == kActHub ? o.hub_parent : o.action;
       st_agent(&c->hub_count, 0u);
-      n.hub_count = 0;
+      if (hand_over) {
+        n.hub_backlog = hubs;
+        n.hub_in = 1u - o.hub_in;
+      }
       if (parent == kActLight) {
         g_add(&c->light_phases, 1ull);
         n.step = o.step + 1u;
@@ -944,7 +974,7 @@ __device__ void lead(typename W::T* t, bool schedule_first) {
   if (schedule_first) after_step<W>();
   for (;;) {  // *s is the current schedule (set by leader_start or after_step)
     const bool light = s->action == kActLight;
-    if (!(light || s->action == kActHeavy) || s->in_count > static_cast<uint32_t>(kChunk)) break;
+    if (!(light || s->action == kActHeavy) || s->in_count > static_cast<uint32_t>(kChunk) || s->hub_backlog > 0) break;
     Entry<typename W::T> e{};
     const uint32_t edges = light ? step_edges<true>(t, s_wsum, &e) : step_edges<false>(t, s_wsum, &e);
     if (edges > p.inline_edges) break;
@@ -1028,7 +1058,7 @@ __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ 
       if (a == kActDone) break;
       if (a == kActLight) phase<W, true>(t, false);
       else if (a == kActHeavy) phase<W, false>(t, false);
-      else if (a == kActHub) hub_step<W>(t);
+      else if (a == kActHub) hub_pieces<W>(t, ls.hub_parent == kActLight);
       else if (a == kActFar) far_step<W>(t);
       else if (a == kActOverflowCheck) overflow_step<W>(t);
       else if (threadIdx.x == 0) st_agent(&c->abort, 1u);
