@@ -87,12 +87,14 @@ typedef struct {
 
 /* Schedule parameters (every field 0 = library default). */
 typedef struct {
-  int32_t workgroups_per_cu; /* resident 1024-thread workgroups per compute unit (default 1) */
+  int32_t workgroups_per_cu; /* resident 1024-thread workgroups per compute unit when one source is
+                                solved at a time (default 1); concurrent sources always run on two
+                                512-thread workgroups per compute unit */
   int32_t ring_buckets;      /* buckets held in the near ring, power of two in [2, 64] (default: fit max weight) */
   int32_t inline_edges;      /* phases scanning at most this many edges (and at most 512 list entries)
                                 run on one workgroup without a device-wide barrier (default 4096) */
   int32_t concurrent_sources; /* sources solved at the same time, each by its own group of workgroups
-                                 (a divisor of the launch's workgroup count, at most 256; default 1).
+                                 (a power of two dividing the launch's workgroup counts, at most 256; default 1).
                                  Each extra group holds its own working set, about (11 + ring) * 4 * n bytes */
 } sssp_tuning;
 

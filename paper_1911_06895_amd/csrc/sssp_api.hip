@@ -30,9 +30,11 @@ struct sssp_handle {
   double delta_d = 0;
   uint64_t wmax_bits = 0;
   uint64_t* w64 = nullptr;  // [m] fp64 weights at the split positions (fp64 handles)
-  int grid = 0;
+  int grid = 0;         // workgroups of a launch of one source at a time (kWG threads each)
+  int grid_groups = 0;  // workgroups of a launch of concurrent sources (kWGGroups threads, two per CU; 0: none)
   int cus = 0;
   int occupancy = 0;
+  int occupancy_groups = 0;
   sssp_tuning tuning{};
   sssp::Params p{};
   uint32_t* perm = nullptr;
@@ -133,6 +135,7 @@ sssp_status configure_grid(sssp_handle* h) {
   if (per_cu > h->occupancy) per_cu = h->occupancy;
   if (per_cu < 1) return SSSP_ERR_UNSUPPORTED;
   h->grid = per_cu * h->cus;
+  h->grid_groups = h->occupancy_groups >= 2 ? 2 * h->cus : 0;
   return SSSP_OK;
 }
 
@@ -288,7 +291,8 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   SSSP_TRY(hipGetDeviceProperties(&prop, h->device));
   if (!prop.cooperativeLaunch) return SSSP_ERR_UNSUPPORTED;
   h->cus = prop.multiProcessorCount;
-  SSSP_TRY(sssp::solver_occupancy(g->wtype, &h->occupancy));
+  SSSP_TRY(sssp::solver_occupancy(g->wtype, sssp::kWG, &h->occupancy));
+  SSSP_TRY(sssp::solver_occupancy(g->wtype, sssp::kWGGroups, &h->occupancy_groups));
 
   const int64_t n = g->n, m = g->m;
   h->n = n;
@@ -344,8 +348,8 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   SSSP_TRY(dalloc(&p.fstamp, un));
   SSSP_TRY(dalloc(&p.ovf_at, un));
   // each vertex appears at most once in a phase's list, so the pieces of its
-  // high-degree vertices number at most m / kPiece + m / kHub
-  p.hub_cap = static_cast<uint32_t>(um / sssp::kPiece + um / sssp::kHub + 16);
+  // high-degree vertices number at most m / kPieceMin + m / kHub (pieces of the smaller workgroup)
+  p.hub_cap = static_cast<uint32_t>(um / sssp::kPieceMin + um / sssp::kHub + 16);
   SSSP_TRY(dalloc(&p.hub, 2 * static_cast<size_t>(p.hub_cap)));
   p.inline_edges = h->tuning.inline_edges > 0 ? static_cast<uint32_t>(h->tuning.inline_edges) : kDefaultInlineEdges;
   SSSP_TRY(dalloc(&p.front[0], un));
@@ -432,8 +436,12 @@ sssp_status enqueue_solve(sssp_handle* h, const int32_t* sources_dev, int32_t k,
     h->stamps_dirty = false;
   }
   SSSP_TRY(sssp::launch_ctl_reset(h->ctls, groups, reset_epochs, h->trace, h->trace_cap, s));
+  // concurrent sources run on two smaller workgroups per CU; one source (or one
+  // multi-source row) on one full workgroup per CU
+  const bool small = groups > 1 && h->grid_groups > 0;
   SSSP_TRY(sssp::launch_solver(multi ? h->params_dev + sssp::kMaxGroups : h->params_dev, groups, h->p.wtype,
-                               sources_dev, k, multi, static_cast<uint32_t*>(dist), h->grid, s));
+                               sources_dev, k, multi, static_cast<uint32_t*>(dist), small ? h->grid_groups : h->grid,
+                               small ? sssp::kWGGroups : sssp::kWG, s));
   h->enq_groups = groups;
   return SSSP_OK;
 }
@@ -719,11 +727,12 @@ sssp_status sssp_set_tuning(sssp_handle* h, const sssp_tuning* t) {
     return SSSP_ERR_UNSUPPORTED;  // the ring is sized at create time
   SSSP_TRY(hipSetDevice(h->device));
   const sssp_tuning old = h->tuning;
-  const int old_grid = h->grid;
+  const int old_grid = h->grid, old_grid_groups = h->grid_groups;
   h->tuning = *t;
   sssp_status st = configure_grid(h);
   const uint32_t groups = t->concurrent_sources > 0 ? static_cast<uint32_t>(t->concurrent_sources) : 1u;
-  if (st == SSSP_OK && (groups > sssp::kMaxGroups || h->grid % static_cast<int>(groups) != 0))
+  if (st == SSSP_OK && (groups > sssp::kMaxGroups || h->grid % static_cast<int>(groups) != 0 ||
+                        h->grid_groups % static_cast<int>(groups) != 0))
     st = SSSP_ERR_UNSUPPORTED;  // every group gets the same number of workgroups
   while (st == SSSP_OK && h->extra.size() + 1 < groups) {
     h->extra.emplace_back();
@@ -732,6 +741,7 @@ sssp_status sssp_set_tuning(sssp_handle* h, const sssp_tuning* t) {
   if (st != SSSP_OK) {
     h->tuning = old;
     h->grid = old_grid;
+    h->grid_groups = old_grid_groups;
     return st;
   }
   h->groups = groups;

@@ -87,7 +87,8 @@ __device__ inline uint32_t wave_scan(uint32_t x) {
   return x;
 }
 
-// Exclusive prefix sum across the workgroup; returns the total in *total.
+// Exclusive prefix sum across a workgroup of WG threads; returns the total in *total.
+template <uint32_t WG = kWG>
 __device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t* total, uint32_t* s_wsum) {
   const uint32_t inc = wave_scan(x);
   const uint32_t w = threadIdx.x >> 6;
@@ -95,7 +96,7 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t* total, uin
   __syncthreads();
   uint32_t before = 0, all = 0;
 #pragma unroll
-  for (uint32_t k = 0; k < kWG / 64; ++k) {
+  for (uint32_t k = 0; k < WG / 64; ++k) {
     const uint32_t s = s_wsum[k];
     before += (k < w) ? s : 0u;
     all += s;

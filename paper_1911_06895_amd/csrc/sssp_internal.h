@@ -6,14 +6,14 @@
 
 namespace sssp {
 
-constexpr int kWG = 1024;              // solver workgroup: 16 wave64s, one per compute unit
+constexpr int kWG = 1024;              // solver workgroup of one source over the device: 16 wave64s, one per CU
+constexpr int kWGGroups = 512;         // solver workgroup of concurrent sources: 8 wave64s, two per CU
 constexpr int kAuxWG = 256;            // workgroup of the create-time kernels
 constexpr uint32_t kChunk = 512;       // most list entries a workgroup expands at a time
 constexpr uint32_t kMinChunk = 32;     // fewest list entries per claimed chunk
 constexpr uint32_t kILP = 4;           // edges per lane in flight
-constexpr uint32_t kPiece = kWG * kILP;  // edges of one hub piece (one round of a workgroup)
+constexpr uint32_t kPieceMin = kWGGroups * kILP;  // edges of the smaller hub piece (one round of a workgroup)
 constexpr uint32_t kHub = 1024;        // a vertex with at least this many edges in a phase goes to the hub step
-constexpr uint32_t kStage = 2 * kWG * kILP;  // LDS staging capacity for list appends (entries)
 constexpr uint32_t kBarGroups = 8;     // arrival sub-counters of the grid barrier
 constexpr uint32_t kRingMax = 64;      // near-bucket ring capacity
 constexpr uint32_t kDegClasses = 65536;  // in-degree classes of the relabelling (the last one open-ended)
@@ -201,16 +201,17 @@ hipError_t launch_relabel_and_split(const int64_t* row_ptr, const int32_t* col, 
                                     int64_t n, int64_t m, uint32_t* scratch,
                                     uint32_t* new_id, uint32_t* off, uint32_t* split, uint64_t* edges,
                                     uint64_t* w64, uint32_t* perm, hipStream_t s);
-hipError_t solver_occupancy(int wtype, int* blocks_per_cu);
+hipError_t solver_occupancy(int wtype, int wg, int* blocks_per_cu);
 hipError_t launch_pack_rows(const uint32_t* off, const uint32_t* split, int64_t n, uint4* rows, hipStream_t s);
 hipError_t launch_ctl_reset(Ctl* c, uint32_t groups, int reset_epochs, unsigned long long* trace, uint32_t trace_cap,
                             hipStream_t s);
 hipError_t launch_fill(uint32_t* p, size_t count, uint32_t value, hipStream_t s);
 // `params` is a device array of one Params per group; grid must be a multiple of
-// groups. multi = 0: row r of dist holds the distances from sources[r]; multi =
-// 1: one row, the distances from the nearest of the k sources.
+// groups; wg (kWG or kWGGroups) is the workgroup size. multi = 0: row r of dist
+// holds the distances from sources[r]; multi = 1: one row, the distances from
+// the nearest of the k sources.
 hipError_t launch_solver(const Params* params, uint32_t groups, uint32_t wtype, const int32_t* sources, int k,
-                         int multi, void* dist, int grid, hipStream_t s);
+                         int multi, void* dist, int grid, int wg, hipStream_t s);
 
 // validation status bits
 enum : uint32_t {

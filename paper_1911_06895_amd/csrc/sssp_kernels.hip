@@ -52,27 +52,91 @@ constexpr uint32_t kSlotS = kRingMax + 2;     // S, the vertices expanded in thi
 constexpr uint32_t kSlots = kRingMax + 3;     // ring slots 0..kRingMax-1, then the three above
 constexpr uint32_t kNoSlot = 0xFFu;
 
+template <uint32_t N>
 struct Stage {
-  uint32_t v[kStage];
-  uint32_t rank[kStage];
-  uint8_t slot[kStage];
+  uint32_t v[N];
+  uint32_t rank[N];
+  uint8_t slot[N];
   uint32_t n;
   uint32_t cnt[kSlots];
   uint32_t base[kSlots];
 };
 
+// Candidates that passed the prefilter (see relax_batch), queued in LDS.
+template <uint32_t N>
+struct Queue {
+  uint32_t v[N];
+  uint64_t c[N];  // candidate distance bits
+  uint32_t n;     // may pass N: the excess was relaxed directly
+};
+
+// Solver configuration: the weight arithmetic plus the workgroup size. A
+// single source (or one multi-source row) runs on 1024-thread workgroups, one
+// per CU; concurrent sources run on 512-thread workgroups, two per CU, whose
+// independent schedules overlap each other's latency-bound steps (15-20 %
+// faster there, 5 % slower on one source over the whole device).
+template <class Wt, uint32_t WG>
+struct Cfg : Wt {
+  static constexpr uint32_t kWG = WG;
+  static constexpr uint32_t kPiece = WG * kILP;  // edges of one hub piece (one round of a workgroup)
+  static constexpr uint32_t kQueue = 2 * WG;     // LDS candidates; drained once a quarter full
+  // LDS staging for list appends: room for a round and a drain above the flush threshold
+  static constexpr uint32_t kStage = WG * kILP + kQueue + 2048;
+};
+
 // The workgroup's state, in LDS: its group's parameters (copied from the
-// launch argument at kernel start), the current schedule, the append staging
-// and the work counters. Device functions name these objects directly rather
-// than receiving references: their accesses then compile to LDS instructions
-// (through a reference, a function that is not inlined would use flat ones,
-// which wait on the global-memory counter as well), and the parameters are
-// not reloaded after every global store.
-__shared__ Params lp;
-__shared__ Sched ls;
-__shared__ Stage lsg;
-__shared__ WgStats lst;
-__shared__ BarrierState lbar;
+// launch argument at kernel start), the current schedule, the append staging,
+// the candidate queue, the work counters and its view of the barrier. Device
+// functions reach it through lds<W>(), which names one static LDS object per
+// configuration, never through a reference parameter: the accesses then
+// compile to LDS instructions (through a reference, a function that is not
+// inlined would use flat ones, which wait on the global-memory counter as
+// well), and the parameters are not reloaded after every global store.
+template <class W>
+__device__ __attribute__((always_inline)) inline Params& lds_params() {
+  __shared__ Params x;
+  return x;
+}
+template <class W>
+__device__ __attribute__((always_inline)) inline Sched& lds_sched() {
+  __shared__ Sched x;
+  return x;
+}
+template <class W>
+__device__ __attribute__((always_inline)) inline Stage<W::kStage>& lds_stage() {
+  __shared__ Stage<W::kStage> x;
+  return x;
+}
+template <class W>
+__device__ __attribute__((always_inline)) inline WgStats& lds_stats() {
+  __shared__ WgStats x;
+  return x;
+}
+template <class W>
+__device__ __attribute__((always_inline)) inline BarrierState& lds_barrier() {
+  __shared__ BarrierState x;
+  return x;
+}
+template <class W>
+__device__ __attribute__((always_inline)) inline Queue<W::kQueue>& lds_queue() {
+  __shared__ Queue<W::kQueue> x;
+  return x;
+}
+
+template <class W>
+struct Lds {
+  Params& p;
+  Sched& s;
+  Stage<W::kStage>& sg;
+  WgStats& st;
+  BarrierState& bar;
+  Queue<W::kQueue>& q;
+};
+
+template <class W>
+__device__ __attribute__((always_inline)) inline Lds<W> lds() {
+  return Lds<W>{lds_params<W>(), lds_sched<W>(), lds_stage<W>(), lds_stats<W>(), lds_barrier<W>(), lds_queue<W>()};
+}
 
 __device__ inline void count_add(unsigned long long* field, unsigned long long v) {
   if (v) atomicAdd(field, v);
@@ -87,8 +151,10 @@ __device__ inline bool in_bucket(typename W::T x, const Sched& s, const Params& 
 
 // Every workgroup's copy of the schedule the leader published. The loads are
 // independent and issued together (one round trip to the coherent level).
+template <class W>
 __device__ inline void load_sched(Ctl* c) {
-  Sched* s = &ls;
+  const Lds<W> L = lds<W>();
+  Sched* s = &L.s;
   if (threadIdx.x == 0) {
     const uint32_t action = ld_agent(&c->action), bucket = ld_agent(&c->bucket), in_kind = ld_agent(&c->in_kind),
                    in_count = ld_agent(&c->in_count), out_buf = ld_agent(&c->out_buf), step = ld_agent(&c->step),
@@ -174,12 +240,14 @@ __device__ inline const uint32_t* phase_list(const Params& p, const Sched& s, bo
 
 // Traced runs only: add this workgroup's counts of the finished step to the
 // control block (one atomic per workgroup), for the next trace record.
+template <class W>
 __device__ inline void trace_step_counts(Ctl* c) {
-  if (!lbar.trace) return;
+  const Lds<W> L = lds<W>();
+  if (!L.bar.trace) return;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned long long te = lst.step_edges, ti = lst.step_impr;
-    lst.step_edges = lst.step_impr = 0;
+    const unsigned long long te = L.st.step_edges, ti = L.st.step_impr;
+    L.st.step_edges = L.st.step_impr = 0;
     if (te) g_add(&c->tr_edges, te);
     if (ti) g_add(&c->tr_impr, ti);
   }
@@ -190,8 +258,10 @@ __device__ inline void trace_step_counts(Ctl* c) {
 // bucket with ballots only; then every group leader issues its atomic at the
 // same time, so a wave waits for one atomic round trip whatever the number of
 // distinct buckets.
+template <class W>
 __device__ inline void push_ring(bool pred, uint32_t j, uint32_t v) {
-  const Params& p = lp;
+  const Lds<W> L = lds<W>();
+  const Params& p = L.p;
   uint64_t rest = __ballot(pred);
   if (rest == 0) return;
   uint32_t my_leader = 0;
@@ -214,8 +284,10 @@ __device__ inline void push_ring(bool pred, uint32_t j, uint32_t v) {
   if (pred) st_agent(&p.bins[static_cast<size_t>(j & p.ring_mask) * p.n + base + lanes_below(my_group)], v);
 }
 
+template <class W>
 __device__ inline void stage_push(bool push, uint32_t slot, uint32_t v) {
-  Stage& sg = lsg;
+  const Lds<W> L = lds<W>();
+  auto& sg = L.sg;
   const uint64_t mask = __ballot(push);
   if (mask == 0) return;
   const int leader = first_lane(mask);
@@ -231,14 +303,16 @@ __device__ inline void stage_push(bool push, uint32_t slot, uint32_t v) {
 
 // Move the n staged appends to their lists. All threads of the workgroup call
 // it with the same n (read between two barriers, so no append raced the read).
+template <class W>
 __device__ void stage_flush_now(uint32_t n) {
-  const Params& p = lp;
-  const Sched& s = ls;
-  Stage& sg = lsg;
+  const Lds<W> L = lds<W>();
+  const Params& p = L.p;
+  const Sched& s = L.s;
+  auto& sg = L.sg;
   if (threadIdx.x < kSlots) sg.cnt[threadIdx.x] = 0;
   __syncthreads();
   // rank of each entry within its destination: lanes grouped by destination, one LDS atomic per group
-  for (uint32_t i0 = 0; i0 < n; i0 += kWG) {
+  for (uint32_t i0 = 0; i0 < n; i0 += W::kWG) {
     const uint32_t i = i0 + threadIdx.x;
     const bool valid = i < n;
     const uint32_t slot = valid ? sg.slot[i] : kNoSlot;
@@ -272,7 +346,7 @@ __device__ void stage_flush_now(uint32_t n) {
     sg.base[k] = c ? g_add(ctr, c) : 0u;
   }
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < n; i += kWG) {
+  for (uint32_t i = threadIdx.x; i < n; i += W::kWG) {
     const uint32_t slot = sg.slot[i];
     uint32_t* list = slot < kRingMax      ? p.bins + static_cast<size_t>(slot) * p.n
                      : slot == kSlotFront ? p.front[s.out_buf]
@@ -296,22 +370,15 @@ __device__ void stage_flush_now(uint32_t n) {
 // that pass are queued in LDS, and the queue is drained in bulk by the whole
 // workgroup: the atomic min on t(v) and the filing, whose round trips are
 // then shared by many requests instead of stalling every round.
-constexpr uint32_t kQueue = 2048;  // LDS candidates; drained once a quarter full at a round boundary
-
-struct Queue {
-  uint32_t v[kQueue];
-  uint64_t c[kQueue];  // candidate distance bits
-  uint32_t n;          // may pass kQueue: the excess was relaxed directly
-};
-__shared__ Queue lq;
 
 // The atomic part for kILP candidates per lane (their atomics overlap in flight).
 template <class W>
 __device__ inline void relax_candidates(typename W::T* t, const bool (&active)[kILP],
                                         const typename W::T (&cand)[kILP], const uint32_t (&v)[kILP],
                                         uint64_t near_end) {
-  const Params& p = lp;
-  const Sched& s = ls;
+  const Lds<W> L = lds<W>();
+  const Params& p = L.p;
+  const Sched& s = L.s;
   bool win[kILP];
 #pragma unroll
   for (uint32_t q = 0; q < kILP; ++q) win[q] = active[q] && cand[q] < g_min(&t[v[q]], cand[q]);
@@ -335,28 +402,30 @@ __device__ inline void relax_candidates(typename W::T* t, const bool (&active)[k
 #pragma unroll
   for (uint32_t q = 0; q < kILP; ++q) {
     nwin += static_cast<uint32_t>(__popcll(__ballot(win[q])));
-    stage_push(slot[q] != kNoSlot, slot[q], v[q]);
+    stage_push<W>(slot[q] != kNoSlot, slot[q], v[q]);
   }
   if (lane() == 0) {
-    count_add(&lst.improvements, nwin);
-    count_add(&lst.step_impr, nwin);
+    count_add(&L.st.improvements, nwin);
+    count_add(&L.st.step_impr, nwin);
   }
 }
 
 // Queue the lanes' candidates; returns true for a candidate that found the
 // queue full (the caller relaxes it at once).
+template <class W>
 __device__ inline bool queue_push(bool pass, uint32_t v, uint64_t c) {
+  const Lds<W> L = lds<W>();
   const uint64_t mask = __ballot(pass);
   if (mask == 0) return false;
   const int leader = first_lane(mask);
   uint32_t b = 0;
-  if (static_cast<int>(lane()) == leader) b = atomicAdd(&lq.n, static_cast<uint32_t>(__popcll(mask)));
+  if (static_cast<int>(lane()) == leader) b = atomicAdd(&L.q.n, static_cast<uint32_t>(__popcll(mask)));
   b = __shfl(b, leader);
   if (!pass) return false;
   const uint32_t i = b + lanes_below(mask);
-  if (i >= kQueue) return true;
-  lq.v[i] = v;
-  lq.c[i] = c;
+  if (i >= W::kQueue) return true;
+  L.q.v[i] = v;
+  L.q.c[i] = c;
   return false;
 }
 
@@ -364,8 +433,9 @@ __device__ inline bool queue_push(bool pass, uint32_t v, uint64_t c) {
 template <class W>
 __device__ inline void relax_batch(typename W::T* t, const bool (&active)[kILP], const typename W::T (&tu)[kILP],
                                    const uint32_t (&v)[kILP], const typename W::Wt (&w)[kILP], uint64_t near_end) {
+  const Lds<W> L = lds<W>();
   using T = typename W::T;
-  const Params& p = lp;
+  const Params& p = L.p;
   T cand[kILP], tv[kILP];
   bool ok[kILP];
 #pragma unroll
@@ -381,7 +451,7 @@ __device__ inline void relax_batch(typename W::T* t, const bool (&active)[kILP],
   bool any = false;
 #pragma unroll
   for (uint32_t q = 0; q < kILP; ++q) {
-    direct[q] = queue_push(ok[q] && cand[q] < tv[q], v[q], static_cast<uint64_t>(cand[q]));
+    direct[q] = queue_push<W>(ok[q] && cand[q] < tv[q], v[q], static_cast<uint64_t>(cand[q]));
     any |= direct[q];
   }
   if (__ballot(any)) relax_candidates<W>(t, direct, cand, v, near_end);
@@ -389,42 +459,46 @@ __device__ inline void relax_batch(typename W::T* t, const bool (&active)[kILP],
 
 // The staged-append and queue counts as every thread sees them: read between
 // two barriers, so that no append or push of a faster wave races the reads.
+template <class W>
 __device__ inline void read_counts(uint32_t* staged, uint32_t* queued) {
+  const Lds<W> L = lds<W>();
   __syncthreads();
-  *staged = lsg.n;
-  *queued = lq.n;
+  *staged = L.sg.n;
+  *queued = L.q.n;
   __syncthreads();
 }
 
-// Flush the staged appends when another round of kWG * kILP might not fit.
+// Flush the staged appends when another round of W::kWG * kILP might not fit.
+template <class W>
 __device__ inline void stage_room() {
   uint32_t staged, queued;
-  read_counts(&staged, &queued);
-  if (staged > kStage - kWG * kILP) stage_flush_now(staged);
+  read_counts<W>(&staged, &queued);
+  if (staged > W::kStage - W::kWG * kILP) stage_flush_now<W>(staged);
 }
 
 // Relax the `queued` candidates (read with read_counts) and empty the queue.
-// All threads call it; the staging has room for kQueue appends.
+// All threads call it; the staging has room for W::kQueue appends.
 template <class W>
 __device__ void drain_queue(typename W::T* t, uint64_t near_end, uint32_t queued) {
+  const Lds<W> L = lds<W>();
   using T = typename W::T;
-  static_assert(kQueue <= kWG * kILP, "one pass drains the queue");
-  const uint32_t n = min(queued, kQueue);
-  for (uint32_t base = 0; base < n; base += kWG * kILP) {
+  static_assert(W::kQueue <= W::kWG * kILP, "one pass drains the queue");
+  const uint32_t n = min(queued, W::kQueue);
+  for (uint32_t base = 0; base < n; base += W::kWG * kILP) {
     bool active[kILP];
     T cand[kILP];
     uint32_t v[kILP];
 #pragma unroll
     for (uint32_t q = 0; q < kILP; ++q) {
-      const uint32_t i = base + q * kWG + threadIdx.x;
+      const uint32_t i = base + q * W::kWG + threadIdx.x;
       active[q] = i < n;
-      v[q] = active[q] ? lq.v[i] : 0u;
-      cand[q] = active[q] ? static_cast<T>(lq.c[i]) : T(0);
+      v[q] = active[q] ? L.q.v[i] : 0u;
+      cand[q] = active[q] ? static_cast<T>(L.q.c[i]) : T(0);
     }
     relax_candidates<W>(t, active, cand, v, near_end);
   }
   __syncthreads();
-  if (threadIdx.x == 0) lq.n = 0;
+  if (threadIdx.x == 0) L.q.n = 0;
   __syncthreads();
 }
 
@@ -435,16 +509,16 @@ __device__ void drain_queue(typename W::T* t, uint64_t near_end, uint32_t queued
 template <class W>
 __device__ inline void round_end(typename W::T* t, uint64_t near_end, bool force) {
   uint32_t staged, queued;
-  read_counts(&staged, &queued);
-  if (staged > kStage - kWG * kILP - kQueue) {
-    stage_flush_now(staged);
+  read_counts<W>(&staged, &queued);
+  if (staged > W::kStage - W::kWG * kILP - W::kQueue) {
+    stage_flush_now<W>(staged);
     staged = 0;
   }
-  if (queued >= (force ? 1u : kQueue / 4)) {
+  if (queued >= (force ? 1u : W::kQueue / 4)) {
     drain_queue<W>(t, near_end, queued);
-    if (force) read_counts(&staged, &queued);
+    if (force) read_counts<W>(&staged, &queued);
   }
-  if (force && staged > 0) stage_flush_now(staged);
+  if (force && staged > 0) stage_flush_now<W>(staged);
 }
 
 // Work distribution over `nitems` items: in a step run by a whole group, the
@@ -462,10 +536,12 @@ __device__ inline uint32_t claim_next(uint32_t* counter, uint32_t prev, uint32_t
 }
 
 // Queue the pieces of one high-degree vertex (kHub or more edges in this phase).
+template <class W>
 __device__ inline void queue_hub(uint32_t u, uint32_t deg) {
-  const Params& p = lp;
-  const uint32_t pieces = (deg + kPiece - 1) / kPiece;
-  uint64_t* queue = p.hub + static_cast<size_t>(1u - ls.hub_in) * p.hub_cap;
+  const Lds<W> L = lds<W>();
+  const Params& p = L.p;
+  const uint32_t pieces = (deg + W::kPiece - 1) / W::kPiece;
+  uint64_t* queue = p.hub + static_cast<size_t>(1u - L.s.hub_in) * p.hub_cap;
   const uint32_t base = g_add(&p.ctl->hub_count, pieces);
   for (uint32_t k = 0; k < pieces && base + k < p.hub_cap; ++k)
     st_agent(&queue[base + k], static_cast<uint64_t>(u) | (static_cast<uint64_t>(k) << 32));
@@ -513,12 +589,13 @@ template <class W, bool kLight>
 __device__ __attribute__((always_inline)) void phase(typename W::T* t, bool solo, bool preloaded = false,
                                                      Entry<typename W::T> pre = Entry<typename W::T>{}) {
   using T = typename W::T;
-  const Params& p = lp;
-  const Sched& s = ls;
+  const Lds<W> L = lds<W>();
+  const Params& p = L.p;
+  const Sched& s = L.s;
   __shared__ uint32_t s_pref[kChunk];
   __shared__ uint32_t s_beg[kChunk];
   __shared__ T s_tu[kChunk];
-  __shared__ uint32_t s_wsum[kWG / 64];
+  __shared__ uint32_t s_wsum[W::kWG / 64];
   __shared__ uint32_t s_claim;
 
   const bool from_bin = kLight && s.in_kind == kInBin;
@@ -558,17 +635,17 @@ __device__ __attribute__((always_inline)) void phase(typename W::T* t, bool solo
           to_s = g_exch(&p.sstamp[u], s.round) != s.round;
         }
       }
-      stage_push(to_s, kSlotS, u);
-      stage_room();
+      stage_push<W>(to_s, kSlotS, u);
+      stage_room<W>();
     }
     if (!solo && deg >= kHub) {
-      queue_hub(u, deg);
-      count_add(kLight ? &lst.light_edges : &lst.heavy_edges, deg);
-      count_add(&lst.step_edges, deg);
+      queue_hub<W>(u, deg);
+      count_add(kLight ? &L.st.light_edges : &L.st.heavy_edges, deg);
+      count_add(&L.st.step_edges, deg);
       deg = 0;
     }
     uint32_t total;
-    const uint32_t excl = block_exclusive_scan(deg, &total, s_wsum);
+    const uint32_t excl = block_exclusive_scan<W::kWG>(deg, &total, s_wsum);
     if (threadIdx.x < kChunk) {
       s_pref[threadIdx.x] = excl;
       s_beg[threadIdx.x] = beg;
@@ -576,10 +653,10 @@ __device__ __attribute__((always_inline)) void phase(typename W::T* t, bool solo
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      count_add(kLight ? &lst.light_edges : &lst.heavy_edges, total);
-      count_add(&lst.step_edges, total);
+      count_add(kLight ? &L.st.light_edges : &L.st.heavy_edges, total);
+      count_add(&L.st.step_edges, total);
     }
-    const uint32_t rounds = (total + kWG * kILP - 1) / (kWG * kILP);
+    const uint32_t rounds = (total + W::kWG * kILP - 1) / (W::kWG * kILP);
     for (uint32_t r = 0; r < rounds; ++r) {
       bool active[kILP];
       uint32_t v[kILP], e[kILP], at[kILP];
@@ -587,7 +664,7 @@ __device__ __attribute__((always_inline)) void phase(typename W::T* t, bool solo
       T tw[kILP];
 #pragma unroll
       for (uint32_t q = 0; q < kILP; ++q) {
-        e[q] = (r * kILP + q) * kWG + threadIdx.x;
+        e[q] = (r * kILP + q) * W::kWG + threadIdx.x;
         active[q] = e[q] < total;
         at[q] = 0;
       }
@@ -634,7 +711,7 @@ __device__ __attribute__((noinline)) void phase_solo(typename W::T* t, Entry<typ
 
 constexpr uint32_t kHandOverMinGroup = 128;  // workgroups
 
-// Hub pieces: kPiece consecutive edges of the high-degree vertices queued by
+// Hub pieces: W::kPiece consecutive edges of the high-degree vertices queued by
 // the previous phase (light or heavy edges, per `light`), spread over all
 // workgroups. They are a step of their own (a hub step), or, when the
 // previous phase was a light phase whose frontier is not empty, the first
@@ -642,9 +719,10 @@ constexpr uint32_t kHandOverMinGroup = 128;  // workgroups
 // re-insertions are simply found one phase later).
 template <class W>
 __device__ void hub_pieces(typename W::T* t, bool light) {
+  const Lds<W> L = lds<W>();
   using T = typename W::T;
-  const Params& p = lp;
-  const Sched& s = ls;
+  const Params& p = L.p;
+  const Sched& s = L.s;
   __shared__ uint32_t s_beg, s_end, s_claim;
   __shared__ T s_tu;
   const uint64_t* queue = p.hub + static_cast<size_t>(s.hub_in) * p.hub_cap;
@@ -659,9 +737,9 @@ __device__ void hub_pieces(typename W::T* t, bool light) {
       const uint4 row = ldg(&p.rows[u]);
       const uint32_t b = light ? row.x : row.y;
       const uint32_t e = light ? row.y : row.z;
-      const uint32_t pb = b + piece * kPiece;
+      const uint32_t pb = b + piece * W::kPiece;
       s_beg = pb;
-      s_end = e - pb > kPiece ? pb + kPiece : e;
+      s_end = e - pb > W::kPiece ? pb + W::kPiece : e;
       s_tu = ld_agent(&t[u]);
     }
     __syncthreads();
@@ -671,7 +749,7 @@ __device__ void hub_pieces(typename W::T* t, bool light) {
     T tw[kILP];
 #pragma unroll
     for (uint32_t q = 0; q < kILP; ++q) {
-      const uint32_t e = s_beg + q * kWG + threadIdx.x;
+      const uint32_t e = s_beg + q * W::kWG + threadIdx.x;
       active[q] = e < s_end;
       v[q] = 0;
       w[q] = 0;
@@ -692,16 +770,17 @@ __device__ void hub_pieces(typename W::T* t, bool light) {
 // move into it; the rest move to the other far list.
 template <class W>
 __device__ void far_step(typename W::T* t) {
-  const Params& p = lp;
-  const Sched& s = ls;
+  const Lds<W> L = lds<W>();
+  const Params& p = L.p;
+  const Sched& s = L.s;
   const uint32_t count = s.in_count;
   const uint32_t* list = p.far[s.far_cur];
   const uint32_t nxt = 1u - s.far_cur;
   const uint64_t near_end = static_cast<uint64_t>(s.far_base) + p.ring;
   const uint32_t size = grp_size(p), rank = grp_rank(p);
-  const uint32_t iters = (count + size * kWG - 1) / (size * kWG);
+  const uint32_t iters = (count + size * W::kWG - 1) / (size * W::kWG);
   for (uint32_t it = 0; it < iters; ++it) {
-    const uint32_t k = (it * size + rank) * kWG + threadIdx.x;
+    const uint32_t k = (it * size + rank) * W::kWG + threadIdx.x;
     bool to_ring = false, to_far = false;
     uint32_t v = 0, j = 0;
     if (k < count) {
@@ -717,7 +796,7 @@ __device__ void far_step(typename W::T* t) {
         }
       }
     }
-    push_ring(to_ring, j, v);
+    push_ring<W>(to_ring, j, v);
     push_wave(p.far[nxt], &p.ctl->farcount[nxt], to_far, v);
   }
 }
@@ -726,8 +805,9 @@ __device__ void far_step(typename W::T* t) {
 // is unrepresentable exactly when no other path reached it.
 template <class W>
 __device__ void overflow_step(typename W::T* t) {
-  const Params& p = lp;
-  for (uint32_t v = grp_rank(p) * kWG + threadIdx.x; v < p.n; v += grp_size(p) * kWG) {
+  const Lds<W> L = lds<W>();
+  const Params& p = L.p;
+  for (uint32_t v = grp_rank(p) * W::kWG + threadIdx.x; v < p.n; v += grp_size(p) * W::kWG) {
     if (ld_agent(&p.ovf_at[v])) {
       if (ld_agent(&t[v]) == W::kInf) st_agent(&p.ctl->ovf_real, 1u);
       st_agent(&p.ovf_at[v], 0u);
@@ -740,8 +820,9 @@ __device__ void overflow_step(typename W::T* t) {
 // Bucket i: [i*delta, (i+1)*delta) as integer bounds (integer weights).
 template <class W>
 __device__ inline void set_bucket(uint32_t i) {
-  const Params& p = lp;
-  Sched* s = &ls;
+  const Lds<W> L = lds<W>();
+  const Params& p = L.p;
+  Sched* s = &L.s;
   s->bucket = i;
   s->lo_u = static_cast<uint64_t>(i) * p.delta_u;
   s->hi_u = static_cast<uint64_t>(i + 1ull) * p.delta_u;
@@ -752,8 +833,9 @@ __device__ inline void set_bucket(uint32_t i) {
 // below bucket fmin) may come first. Wave 0 scans the slots; thread 0 decides.
 template <class W>
 __device__ void choose_next(const Counters& k, uint32_t from, uint32_t len, uint32_t fc, uint32_t fmin) {
-  const Params& p = lp;
-  Sched* s = &ls;
+  const Lds<W> L = lds<W>();
+  const Params& p = L.p;
+  Sched* s = &L.s;
   __shared__ uint32_t s_jn;
   if (threadIdx.x < 64) {
     const uint32_t l = threadIdx.x;
@@ -790,8 +872,9 @@ __device__ void choose_next(const Counters& k, uint32_t from, uint32_t len, uint
 // cleared, so the de-duplication tags restart.
 template <class W>
 __device__ void leader_start(typename W::T* t, const int32_t* seeds, int nseeds, bool reset_tags) {
-  const Params& p = lp;
-  Sched* s = &ls;
+  const Lds<W> L = lds<W>();
+  const Params& p = L.p;
+  Sched* s = &L.s;
   Ctl* c = p.ctl;
   if (threadIdx.x < kRingMax) st_agent(&c->bincount[threadIdx.x][0], 0u);
   if (threadIdx.x == 0) {
@@ -821,7 +904,7 @@ __device__ void leader_start(typename W::T* t, const int32_t* seeds, int nseeds,
   }
   drain_stores();
   __syncthreads();
-  for (int i = threadIdx.x; i < nseeds; i += kWG) {
+  for (int i = threadIdx.x; i < nseeds; i += W::kWG) {
     const int32_t src = ldg(&seeds[i]);
     if (src < 0 || static_cast<uint32_t>(src) >= p.n) {
       st_agent(&c->bad_source, 1u);
@@ -852,8 +935,9 @@ __device__ void leader_start(typename W::T* t, const int32_t* seeds, int nseeds,
 // before anything reads them back (the barrier release does).
 template <class W>
 __device__ void after_step() {
-  const Params& p = lp;
-  Sched* s = &ls;
+  const Lds<W> L = lds<W>();
+  const Params& p = L.p;
+  Sched* s = &L.s;
   Ctl* c = p.ctl;
   __shared__ Counters k;
   __shared__ uint32_t s_next, s_fc, s_fmin;  // s_next 0: decided; 1: next bucket after s.bucket; 2: after a far step
@@ -945,12 +1029,13 @@ __device__ void after_step() {
   __syncthreads();
 }
 
-// Edges a light or heavy step would scan (its list has at most kWG entries);
+// Edges a light or heavy step would scan (its list has at most W::kWG entries);
 // each thread keeps its entry for the phase that may follow on this workgroup.
-template <bool kLight, class T>
-__device__ uint32_t step_edges(const T* t, uint32_t* s_wsum, Entry<T>* e) {
-  const Params& p = lp;
-  const Sched& s = ls;
+template <bool kLight, class W>
+__device__ uint32_t step_edges(const typename W::T* t, uint32_t* s_wsum, Entry<typename W::T>* e) {
+  const Lds<W> L = lds<W>();
+  const Params& p = L.p;
+  const Sched& s = L.s;
   const uint32_t* list = phase_list(p, s, kLight);
   uint32_t deg = 0;
   if (threadIdx.x < s.in_count) {
@@ -960,7 +1045,7 @@ __device__ uint32_t step_edges(const T* t, uint32_t* s_wsum, Entry<T>* e) {
     deg = kLight ? e->row.y - e->row.x : e->row.z - e->row.y;
   }
   uint32_t total;
-  (void)block_exclusive_scan(deg, &total, s_wsum);
+  (void)block_exclusive_scan<W::kWG>(deg, &total, s_wsum);
   return total;
 }
 
@@ -968,22 +1053,23 @@ __device__ uint32_t step_edges(const T* t, uint32_t* s_wsum, Entry<T>* e) {
 // is a small light or heavy phase, run it on this workgroup alone and schedule again.
 template <class W>
 __device__ void lead(typename W::T* t, bool schedule_first) {
-  const Params& p = lp;
-  Sched* s = &ls;
-  __shared__ uint32_t s_wsum[kWG / 64];
+  const Lds<W> L = lds<W>();
+  const Params& p = L.p;
+  Sched* s = &L.s;
+  __shared__ uint32_t s_wsum[W::kWG / 64];
   if (schedule_first) after_step<W>();
   for (;;) {  // *s is the current schedule (set by leader_start or after_step)
     const bool light = s->action == kActLight;
     if (!(light || s->action == kActHeavy) || s->in_count > static_cast<uint32_t>(kChunk) || s->hub_backlog > 0) break;
     Entry<typename W::T> e{};
-    const uint32_t edges = light ? step_edges<true>(t, s_wsum, &e) : step_edges<false>(t, s_wsum, &e);
+    const uint32_t edges = light ? step_edges<true, W>(t, s_wsum, &e) : step_edges<false, W>(t, s_wsum, &e);
     if (edges > p.inline_edges) break;
     drain_stores();  // the counter resets of after_step land before this step's appends
     __syncthreads();
-    if (threadIdx.x == 0) record_trace(p.ctl, lbar.trace, 0x80u);
+    if (threadIdx.x == 0) record_trace(p.ctl, L.bar.trace, 0x80u);
     if (light) phase_solo<W, true>(t, e);
     else phase_solo<W, false>(t, e);
-    trace_step_counts(p.ctl);
+    trace_step_counts<W>(p.ctl);
     drain_stores();
     __syncthreads();
     after_step<W>();
@@ -995,7 +1081,8 @@ __device__ void lead(typename W::T* t, bool schedule_first) {
 // source, or (multi) all k sources at once in a single row.
 template <class W>
 __device__ void leader_claim(typename W::T* t, const int32_t* sources, int k, int multi, bool reset_tags) {
-  const Params& p = lp;
+  const Lds<W> L = lds<W>();
+  const Params& p = L.p;
   __shared__ uint32_t s_row;
   Ctl* c = p.ctl;
   if (threadIdx.x == 0) {
@@ -1012,21 +1099,22 @@ __device__ void leader_claim(typename W::T* t, const int32_t* sources, int k, in
 }
 
 template <class W>
-__global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ params, uint32_t groups,
+__global__ __launch_bounds__(W::kWG, 4) void solver_kernel(const Params* __restrict__ params, uint32_t groups,
                                                      const int32_t* sources, int k, int multi, void* dist) {
+  const Lds<W> L = lds<W>();
   using T = typename W::T;
   __shared__ uint32_t s_row;
   if (threadIdx.x == 0) {
-    lp = params[blockIdx.x % groups];
-    lsg.n = 0;
-    lq.n = 0;
-    lst = WgStats{0, 0, 0, 0, 0};
+    L.p = params[blockIdx.x % groups];
+    L.sg.n = 0;
+    L.q.n = 0;
+    L.st = WgStats{0, 0, 0, 0, 0};
   }
   __syncthreads();
-  const Params& p = lp;
+  const Params& p = L.p;
   const uint32_t rank = grp_rank(p), size = grp_size(p);
   Ctl* c = p.ctl;
-  init_barrier(c, lbar);
+  init_barrier(c, L.bar);
   bool alive = true;
   for (uint32_t it = 0; alive; ++it) {
     // the de-duplication tags grow by one per step and per bucket: long before
@@ -1038,7 +1126,7 @@ __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ 
     // distances live in solver ids; a group's consecutive sources alternate
     // buffers so that copying out one row never races with initialising the next
     T* t = static_cast<T*>(p.tbuf[it & 1]);
-    for (uint32_t v = rank * kWG + threadIdx.x; v < p.n; v += size * kWG) {
+    for (uint32_t v = rank * W::kWG + threadIdx.x; v < p.n; v += size * W::kWG) {
       st_agent(&t[v], W::kInf);
       st_agent(&p.bstamp[v], kNone);
       if (reset_tags) {
@@ -1047,35 +1135,35 @@ __global__ __launch_bounds__(kWG) void solver_kernel(const Params* __restrict__ 
         st_agent(&p.fstamp[v], 0u);
       }
     }
-    alive = grid_sync(c, size, rank, lbar, [&] { leader_claim<W>(t, sources, k, multi, reset_tags); });
+    alive = grid_sync(c, size, rank, L.bar, [&] { leader_claim<W>(t, sources, k, multi, reset_tags); });
     if (threadIdx.x == 0) s_row = ld_agent(&c->source_index);
     __syncthreads();
     const uint32_t row = s_row;
     if (!alive || row == kNone) break;
     while (alive) {
-      load_sched(c);
-      const uint32_t a = ls.action;
+      load_sched<W>(c);
+      const uint32_t a = L.s.action;
       if (a == kActDone) break;
       if (a == kActLight) phase<W, true>(t, false);
       else if (a == kActHeavy) phase<W, false>(t, false);
-      else if (a == kActHub) hub_pieces<W>(t, ls.hub_parent == kActLight);
+      else if (a == kActHub) hub_pieces<W>(t, L.s.hub_parent == kActLight);
       else if (a == kActFar) far_step<W>(t);
       else if (a == kActOverflowCheck) overflow_step<W>(t);
       else if (threadIdx.x == 0) st_agent(&c->abort, 1u);
-      trace_step_counts(c);
-      alive = grid_sync(c, size, rank, lbar, [&] { lead<W>(t, true); });
+      trace_step_counts<W>(c);
+      alive = grid_sync(c, size, rank, L.bar, [&] { lead<W>(t, true); });
     }
     if (alive) {  // the source's row of the output, in the caller's vertex numbering
       T* out = static_cast<T*>(dist) + static_cast<size_t>(row) * p.n;
-      for (uint32_t v = rank * kWG + threadIdx.x; v < p.n; v += size * kWG) *gp(&out[v]) = ld_agent(&t[ldg(&p.vid[v])]);
+      for (uint32_t v = rank * W::kWG + threadIdx.x; v < p.n; v += size * W::kWG) *gp(&out[v]) = ld_agent(&t[ldg(&p.vid[v])]);
     }
   }
   // add this workgroup's counters to the group's control block
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (lst.light_edges) g_add(&c->light_edges, lst.light_edges);
-    if (lst.heavy_edges) g_add(&c->heavy_edges, lst.heavy_edges);
-    if (lst.improvements) g_add(&c->improvements, lst.improvements);
+    if (L.st.light_edges) g_add(&c->light_edges, L.st.light_edges);
+    if (L.st.heavy_edges) g_add(&c->heavy_edges, L.st.heavy_edges);
+    if (L.st.improvements) g_add(&c->improvements, L.st.improvements);
   }
 }
 
@@ -1134,18 +1222,29 @@ hipError_t launch_fill(uint32_t* p, size_t count, uint32_t value, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t solver_occupancy(int wtype, int* blocks_per_cu) {
-  if (wtype == kWU32) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solver_kernel<WeightU32>, kWG, 0);
-  if (wtype == kWF32) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solver_kernel<WeightF32>, kWG, 0);
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solver_kernel<WeightF64>, kWG, 0);
+namespace {
+// the solver kernel of a weight type and workgroup size
+template <uint32_t WG>
+const void* solver_fn(uint32_t wtype) {
+  return wtype == kWU32   ? reinterpret_cast<const void*>(solver_kernel<Cfg<WeightU32, WG>>)
+         : wtype == kWF32 ? reinterpret_cast<const void*>(solver_kernel<Cfg<WeightF32, WG>>)
+                          : reinterpret_cast<const void*>(solver_kernel<Cfg<WeightF64, WG>>);
+}
+const void* solver_fn(uint32_t wtype, int wg) { return wg == kWGGroups ? solver_fn<kWGGroups>(wtype) : solver_fn<kWG>(wtype); }
+}  // namespace
+
+hipError_t solver_occupancy(int wtype, int wg, int* blocks_per_cu) {
+  if (wg != kWG && wg != kWGGroups) return hipErrorInvalidValue;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solver_fn(static_cast<uint32_t>(wtype), wg), wg, 0);
 }
 
 // One cooperative launch (every workgroup co-resident, which the barriers
 // need). While the stream is being captured into a graph, the launch-attribute
 // form records a cooperative kernel node.
 hipError_t launch_solver(const Params* params, uint32_t groups, uint32_t wtype, const int32_t* sources, int k,
-                         int multi, void* dist, int grid, hipStream_t s) {
+                         int multi, void* dist, int grid, int wg, hipStream_t s) {
   if (groups < 1 || groups > kMaxGroups || grid < 1 || grid % static_cast<int>(groups) != 0) return hipErrorInvalidValue;
+  if (wg != kWG && wg != kWGGroups) return hipErrorInvalidValue;
   const Params* pp = params;
   uint32_t gg = groups;
   const int32_t* src = sources;
@@ -1153,19 +1252,17 @@ hipError_t launch_solver(const Params* params, uint32_t groups, uint32_t wtype, 
   int mm = multi;
   void* d = dist;
   void* args[] = {&pp, &gg, &src, &kk, &mm, &d};
-  const void* fn = wtype == kWU32   ? reinterpret_cast<const void*>(solver_kernel<WeightU32>)
-                   : wtype == kWF32 ? reinterpret_cast<const void*>(solver_kernel<WeightF32>)
-                                    : reinterpret_cast<const void*>(solver_kernel<WeightF64>);
+  const void* fn = solver_fn(wtype, wg);
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   const hipError_t e = hipStreamIsCapturing(s, &cap);
   if (e != hipSuccess) return e;
-  if (cap == hipStreamCaptureStatusNone) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kWG), args, 0, s);
+  if (cap == hipStreamCaptureStatusNone) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(wg), args, 0, s);
   hipLaunchAttribute attr[1] = {};
   attr[0].id = hipLaunchAttributeCooperative;
   attr[0].val.cooperative = 1;
   hipLaunchConfig_t cfg{};
   cfg.gridDim = dim3(static_cast<uint32_t>(grid));
-  cfg.blockDim = dim3(kWG);
+  cfg.blockDim = dim3(static_cast<uint32_t>(wg));
   cfg.dynamicSmemBytes = 0;
   cfg.stream = s;
   cfg.attrs = attr;
