@@ -729,20 +729,31 @@ __device__ void hub_pieces(typename W::T* t, bool light) {
   const uint32_t count = s.hub_backlog < p.hub_cap ? s.hub_backlog : p.hub_cap;
   const uint64_t near_end = static_cast<uint64_t>(s.bucket) + p.ring;  // no wrap near 2^32
   const uint32_t size = grp_size(p);
-  for (uint32_t c = grp_rank(p); c < count; c = claim_next(&p.ctl->hub_next, c, count, false, size, &s_claim)) {
+  // Workgroup b takes piece b, then claims further pieces from a counter.
+  // Thread 0 works one piece ahead: while a piece is relaxed, the next one is
+  // already claimed and its queue record is in flight, so a piece boundary
+  // waits only for the row and t(u) of the next vertex.
+  uint32_t c = grp_rank(p);
+  uint64_t rec = 0;  // thread 0: queue record of piece c
+  if (threadIdx.x == 0 && c < count) rec = ld_agent(&queue[c]);
+  while (c < count) {
     if (threadIdx.x == 0) {
-      const uint64_t rec = ld_agent(&queue[c]);
+      const uint32_t nc = count <= size ? count : size + g_add(&p.ctl->hub_next, 1u);
       const uint32_t u = static_cast<uint32_t>(rec);
       const uint32_t piece = static_cast<uint32_t>(rec >> 32);
       const uint4 row = ldg(&p.rows[u]);
+      const T tu = ld_agent(&t[u]);
+      rec = nc < count ? ld_agent(&queue[nc]) : 0ull;
       const uint32_t b = light ? row.x : row.y;
       const uint32_t e = light ? row.y : row.z;
       const uint32_t pb = b + piece * W::kPiece;
       s_beg = pb;
       s_end = e - pb > W::kPiece ? pb + W::kPiece : e;
-      s_tu = ld_agent(&t[u]);
+      s_tu = tu;
+      s_claim = nc;
     }
     __syncthreads();
+    c = s_claim;
     bool active[kILP];
     uint32_t v[kILP];
     typename W::Wt w[kILP];
