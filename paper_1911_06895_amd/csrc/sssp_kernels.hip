@@ -1,8 +1,9 @@
 // HIP kernels for gfx950 (CDNA4, wave64): graph validation, the light/heavy
 // split of the adjacency matrix, and the persistent delta-stepping solver.
 //
-// The solver is one cooperative launch per call, one 1024-thread workgroup per
-// compute unit. Every step of the method (a light phase, a heavy phase, a
+// The solver is one cooperative launch per call: one 1024-thread workgroup per
+// compute unit for one source at a time, two 512-thread workgroups per compute
+// unit when several sources run at once (see Cfg). Every step of the method (a light phase, a heavy phase, a
 // far-bucket redistribution) is processed by all workgroups; steps are
 // separated by a device-wide barrier whose last arriving workgroup (the
 // leader) evaluates the loop tests of Fig. 1 ("while t_Bi != 0",
@@ -468,7 +469,7 @@ __device__ inline void read_counts(uint32_t* staged, uint32_t* queued) {
   __syncthreads();
 }
 
-// Flush the staged appends when another round of W::kWG * kILP might not fit.
+// Flush the staged appends when another round (W::kWG * kILP appends) might not fit.
 template <class W>
 __device__ inline void stage_room() {
   uint32_t staged, queued;
@@ -1040,7 +1041,7 @@ __device__ void after_step() {
   __syncthreads();
 }
 
-// Edges a light or heavy step would scan (its list has at most W::kWG entries);
+// Edges a light or heavy step would scan (its list has at most kChunk entries);
 // each thread keeps its entry for the phase that may follow on this workgroup.
 template <bool kLight, class W>
 __device__ uint32_t step_edges(const typename W::T* t, uint32_t* s_wsum, Entry<typename W::T>* e) {
