@@ -87,9 +87,11 @@ typedef struct {
 
 /* Schedule parameters (every field 0 = library default). */
 typedef struct {
-  int32_t workgroups_per_cu; /* resident 1024-thread workgroups per compute unit when one source is
-                                solved at a time (default 1); concurrent sources always run on two
-                                512-thread workgroups per compute unit */
+  int32_t workgroups_per_cu; /* workgroups per compute unit of a launch with one source (or one
+                                multi-source row): 1 = one of 1024 threads, 2 or more = two of 512
+                                threads; 0 = library choice (1024 threads for a single source on a
+                                graph of 2^25 edges or more, else 512). Concurrent sources always
+                                run two 512-thread workgroups per compute unit */
   int32_t ring_buckets;      /* buckets held in the near ring, power of two in [2, 64] (default: fit max weight) */
   int32_t inline_edges;      /* phases scanning at most this many edges (and at most 512 list entries)
                                 run on one workgroup without a device-wide barrier (default 4096) */
@@ -228,8 +230,8 @@ sssp_status sssp_last_stats(const sssp_handle *h, sssp_stats *out);
  * Replace the schedule parameters of a handle (host struct; copied). Allocates
  * the working sets of new concurrent groups (and synchronises the device).
  * Errors: INVALID_ARGUMENT (negative fields, a ring size other than the
- * handle's), UNSUPPORTED (workgroups_per_cu above the device's occupancy, or
- * concurrent_sources not dividing the workgroup count), OUT_OF_MEMORY.
+ * handle's), UNSUPPORTED (concurrent_sources above 256 or not dividing the
+ * workgroup counts), OUT_OF_MEMORY.
  */
 sssp_status sssp_set_tuning(sssp_handle *h, const sssp_tuning *t);
 
