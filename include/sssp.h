@@ -88,10 +88,9 @@ typedef struct {
 /* Schedule parameters (every field 0 = library default). */
 typedef struct {
   int32_t workgroups_per_cu; /* workgroups per compute unit of a launch with one source (or one
-                                multi-source row): 1 = one of 1024 threads, 2 or more = two of 512
-                                threads; 0 = library choice (1024 threads for a single source on a
-                                graph of 2^25 edges or more, else 512). Concurrent sources always
-                                run two 512-thread workgroups per compute unit */
+                                multi-source row): 1 = one of 1024 threads; 0 (default) or 2 and
+                                more = two of 512 threads. Concurrent sources always run two
+                                512-thread workgroups per compute unit */
   int32_t ring_buckets;      /* buckets held in the near ring, power of two in [2, 64] (default: fit max weight) */
   int32_t inline_edges;      /* phases scanning at most this many edges (and at most 512 list entries)
                                 run on one workgroup without a device-wide barrier (default 4096) */

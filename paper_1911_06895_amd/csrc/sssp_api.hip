@@ -137,19 +137,15 @@ sssp_status configure_grid(sssp_handle* h) {
   return SSSP_OK;
 }
 
-// Single-source launches on graphs with at least this many edges default to
-// the 1024-thread workgroups (measured: R-MAT scale 22, 65 M edges, 5 % faster
-// there; R-MAT scale 18 and a 512-graph ragged batch 8 % faster on 512).
-constexpr int64_t kLargeGraphEdges = int64_t{1} << 25;
-
 // Whether a launch runs two 512-thread workgroups per CU (else one of 1024).
+// The smaller workgroups are the default: measured faster on every workload
+// (R-MAT scale 22 single source +2 %, scale 18 +6 %, the ragged batch +8 %,
+// concurrent sources +15-20 %); workgroups_per_cu = 1 selects the larger ones
+// for one source or one multi-source row.
 bool small_workgroups(const sssp_handle* h, uint32_t groups, int multi) {
+  (void)multi;
   if (h->grid_groups == 0) return false;
-  if (groups > 1) return true;
-  const int32_t per_cu = h->tuning.workgroups_per_cu;
-  if (per_cu == 1) return false;
-  if (per_cu >= 2) return true;
-  return multi || h->m < kLargeGraphEdges;
+  return groups > 1 || h->tuning.workgroups_per_cu != 1;
 }
 
 // Bytes of one distance (and one weight) of the handle's type.
