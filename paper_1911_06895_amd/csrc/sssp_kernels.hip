@@ -556,13 +556,20 @@ __device__ inline void queue_hub(uint32_t u, uint32_t deg) {
 // are prefix-summed in LDS and the lanes walk the concatenated edge ranges, so
 // consecutive lanes read consecutive edges of a row. Vertices with kHub or
 // more edges are queued as pieces for a grid-wide hub step instead.
+// A group of at least this many workgroups (most of the device) hands hub
+// pieces over between light phases, claims chunks of at most kChunk / 2
+// entries (more chunks per workgroup: better balance over many workgroups)
+// and runs steps of at most kChunk / 2 entries on the leader alone; smaller
+// groups use kChunk for both.
+constexpr uint32_t kHandOverMinGroup = 128;  // workgroups
+
 // List entries per claimed chunk: enough chunks for about four per workgroup.
 // Chunk sizes are powers of two (the edge-to-entry search relies on it).
 static_assert((kChunk & (kChunk - 1)) == 0 && (kMinChunk & (kMinChunk - 1)) == 0, "chunk sizes are powers of two");
-__device__ inline uint32_t chunk_for(uint32_t count, uint32_t size) {
+__device__ inline uint32_t chunk_for(uint32_t count, uint32_t size, uint32_t cap) {
   const uint32_t target = (count + 4 * size - 1) / (4 * size);
   uint32_t c = kMinChunk;
-  while (c < target && c < kChunk) c <<= 1;
+  while (c < target && c < cap) c <<= 1;
   return c;
 }
 
@@ -604,7 +611,7 @@ __device__ __attribute__((always_inline)) void phase(typename W::T* t, bool solo
   const uint32_t count = s.in_count;
   const uint64_t near_end = static_cast<uint64_t>(s.bucket) + p.ring;  // no wrap near 2^32
   const uint32_t size = grp_size(p);
-  const uint32_t chunk = solo ? solo_chunk(count) : chunk_for(count, size);
+  const uint32_t chunk = solo ? solo_chunk(count) : chunk_for(count, size, size >= kHandOverMinGroup ? kChunk / 2 : kChunk);
   const uint32_t nchunks = (count + chunk - 1) / chunk;
   if constexpr (kLight) {
     if (!solo && s.hub_backlog > 0) hub_pieces<W>(t, true);  // the previous light phase's pieces
@@ -709,8 +716,6 @@ template <class W, bool kLight>
 __device__ __attribute__((noinline)) void phase_solo(typename W::T* t, Entry<typename W::T> pre) {
   phase<W, kLight>(t, true, true, pre);
 }
-
-constexpr uint32_t kHandOverMinGroup = 128;  // workgroups
 
 // Hub pieces: W::kPiece consecutive edges of the high-degree vertices queued by
 // the previous phase (light or heavy edges, per `light`), spread over all
@@ -966,8 +971,8 @@ __device__ void after_step() {
     // phase (saving a barrier), in a group that spans most of the device (where
     // a barrier is dearest) and unless that phase is small enough for the
     // leader to run alone.
-    const bool hand_over = o.action == kActLight && hubs > 0 && k.w[o.out_buf ? kCF1 : kCF0] > kChunk &&
-                           grp_size(p) >= kHandOverMinGroup;
+    const bool hand_over = o.action == kActLight && hubs > 0 && grp_size(p) >= kHandOverMinGroup &&
+                           k.w[o.out_buf ? kCF1 : kCF0] > kChunk / 2;
     n.hub_backlog = 0;
     if (phase_done && hubs > 0 && !hand_over) {  // finish the phase: its high-degree vertices
       n.hub_parent = o.action;
@@ -1072,7 +1077,7 @@ __device__ void lead(typename W::T* t, bool schedule_first) {
   if (schedule_first) after_step<W>();
   for (;;) {  // *s is the current schedule (set by leader_start or after_step)
     const bool light = s->action == kActLight;
-    if (!(light || s->action == kActHeavy) || s->in_count > static_cast<uint32_t>(kChunk) || s->hub_backlog > 0) break;
+    if (!(light || s->action == kActHeavy) || s->in_count > (grp_size(p) >= kHandOverMinGroup ? kChunk / 2 : kChunk) || s->hub_backlog > 0) break;
     Entry<typename W::T> e{};
     const uint32_t edges = light ? step_edges<true, W>(t, s_wsum, &e) : step_edges<false, W>(t, s_wsum, &e);
     if (edges > p.inline_edges) break;
