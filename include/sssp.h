@@ -92,7 +92,8 @@ typedef struct {
                                 more = two of 512 threads. Concurrent sources always run two
                                 512-thread workgroups per compute unit */
   int32_t ring_buckets;      /* buckets held in the near ring, power of two in [2, 64] (default: fit max weight) */
-  int32_t inline_edges;      /* phases scanning at most this many edges (and at most 512 list entries)
+  int32_t inline_edges;      /* phases scanning at most this many edges (and at most 512 list entries,
+                                256 in groups of 128 or more workgroups)
                                 run on one workgroup without a device-wide barrier (default 4096) */
   int32_t concurrent_sources; /* sources solved at the same time, each by its own group of workgroups
                                  (a power of two dividing the launch's workgroup counts, at most 256; default 1).
