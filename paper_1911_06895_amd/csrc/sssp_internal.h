@@ -6,8 +6,8 @@
 
 namespace sssp {
 
-constexpr int kWG = 1024;              // solver workgroup of one source over the device: 16 wave64s, one per CU
-constexpr int kWGGroups = 512;         // solver workgroup of concurrent sources: 8 wave64s, two per CU
+constexpr int kWG = 1024;              // larger solver workgroup (on request; the adjoint's): 16 wave64s, one per CU
+constexpr int kWGGroups = 512;         // default solver workgroup: 8 wave64s, two per CU
 constexpr int kAuxWG = 256;            // workgroup of the create-time kernels
 constexpr uint32_t kChunk = 512;       // most list entries a workgroup expands at a time
 constexpr uint32_t kMinChunk = 32;     // fewest list entries per claimed chunk

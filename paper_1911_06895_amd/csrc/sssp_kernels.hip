@@ -1,10 +1,10 @@
 // HIP kernels for gfx950 (CDNA4, wave64): graph validation, the light/heavy
 // split of the adjacency matrix, and the persistent delta-stepping solver.
 //
-// The solver is one cooperative launch per call: one 1024-thread workgroup per
-// compute unit for one source at a time, two 512-thread workgroups per compute
-// unit when several sources run at once (see Cfg). Every step of the method (a light phase, a heavy phase, a
-// far-bucket redistribution) is processed by all workgroups; steps are
+// The solver is one cooperative launch per call, with two 512-thread
+// workgroups per compute unit (or, on request, one of 1024 threads; see Cfg).
+// Every step of the method (a light phase, a heavy phase, a far-bucket
+// redistribution) is processed by all workgroups; steps are
 // separated by a device-wide barrier whose last arriving workgroup (the
 // leader) evaluates the loop tests of Fig. 1 ("while t_Bi != 0",
 // "while (t >= i*delta) != 0") and publishes the next step before releasing
@@ -71,11 +71,11 @@ struct Queue {
   uint32_t n;     // may pass N: the excess was relaxed directly
 };
 
-// Solver configuration: the weight arithmetic plus the workgroup size. A
-// single source (or one multi-source row) runs on 1024-thread workgroups, one
-// per CU; concurrent sources run on 512-thread workgroups, two per CU, whose
-// independent schedules overlap each other's latency-bound steps (15-20 %
-// faster there, 5 % slower on one source over the whole device).
+// Solver configuration: the weight arithmetic plus the workgroup size. The
+// default is 512-thread workgroups, two per CU, whose independent schedules
+// overlap each other's latency-bound steps (faster on every workload measured);
+// 1024-thread workgroups, one per CU, can be requested for one source or one
+// multi-source row.
 template <class Wt, uint32_t WG>
 struct Cfg : Wt {
   static constexpr uint32_t kWG = WG;
