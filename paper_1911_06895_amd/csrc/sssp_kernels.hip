@@ -522,6 +522,16 @@ __device__ inline void round_end(typename W::T* t, uint64_t near_end, bool force
   if (force && staged > 0) stage_flush_now<W>(staged);
 }
 
+// The prefilter's cached loads of t rely on every cached copy being from the
+// current solve, hence stale only upward. A group's distance buffers alternate
+// between its rows, so a buffer's earlier row may have left lines in this CU's
+// L1 or this XCD's L2 that lie below the new row's values (the other XCDs'
+// stores that reset the buffer do not reach those caches). Before the first
+// step of each row, after the barrier that completes the reset, every
+// workgroup therefore drops them: an agent-scope acquire invalidates both
+// caches.
+__device__ inline void forget_cached_distances() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
 // Work distribution over `nitems` items: in a step run by a whole group, the
 // workgroup of rank b first takes item b with no atomic, then claims further
 // items from a shared counter; the leader workgroup running a step alone walks
@@ -1111,6 +1121,7 @@ __device__ void leader_claim(typename W::T* t, const int32_t* sources, int k, in
   __syncthreads();
   const uint32_t r = s_row;
   if (r == kNone) return;
+  forget_cached_distances();  // the inline steps below use the prefilter
   leader_start<W>(t, multi ? sources : sources + r, multi ? k : 1, reset_tags);
   lead<W>(t, false);  // the first phases (around the seeds) are usually small
 }
@@ -1157,6 +1168,7 @@ __global__ __launch_bounds__(W::kWG, 4) void solver_kernel(const Params* __restr
     __syncthreads();
     const uint32_t row = s_row;
     if (!alive || row == kNone) break;
+    forget_cached_distances();
     while (alive) {
       load_sched<W>(c);
       const uint32_t a = L.s.action;

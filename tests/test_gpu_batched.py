@@ -58,6 +58,25 @@ def test_concurrent_groups_match_oracle(groups, kind):
         solver.close()
 
 
+@pytest.mark.parametrize("groups", [1, 2])
+def test_reused_distance_buffers(groups):
+    """Hundreds of rows per group in one launch: each of a group's two distance
+    buffers serves every other row, so the cached copies an earlier row leaves
+    must never feed the next row's prefilter. Every row is certified, over
+    three launches."""
+    print(f"[batched] reused buffers groups={groups}", flush=True)
+    g, delta = G.rmat_graph(14, 16, cfg=61, weights="u32", wlo=1, whi=255), 32
+    srcs = G.sources_with_outedges(g, 401, cfg=64)
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, delta)
+    try:
+        solver.set_tuning(concurrent_sources=groups)
+        for launch in range(3):
+            rows = solver.solve_numpy(srcs)
+            check_rows(g, srcs, rows, exact_rows=2 if launch == 0 else 0)
+    finally:
+        solver.close()
+
+
 def test_c4a_configuration():
     """R-MAT scale 18, fp32 log-uniform weights in [1e-2, 1e2], 256 sources, 8 groups."""
     print("[batched] C4a rmat_s18_f32log k=256 groups=8", flush=True)
