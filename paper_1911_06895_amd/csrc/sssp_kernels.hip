@@ -528,9 +528,13 @@ __device__ inline void round_end(typename W::T* t, uint64_t near_end, bool force
 // L1 or this XCD's L2 that lie below the new row's values (the other XCDs'
 // stores that reset the buffer do not reach those caches). Before the first
 // step of each row, after the barrier that completes the reset, every
-// workgroup therefore drops them: an agent-scope acquire invalidates both
-// caches.
-__device__ inline void forget_cached_distances() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+// workgroup therefore drops them: one agent-scope acquire invalidates both
+// caches, and the workgroup barrier after it orders the other waves' loads
+// behind it (one invalidation per workgroup rather than per wave).
+__device__ inline void forget_cached_distances() {
+  if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __syncthreads();
+}
 
 // Work distribution over `nitems` items: in a step run by a whole group, the
 // workgroup of rank b first takes item b with no atomic, then claims further
