@@ -22,6 +22,8 @@ same GPU ("modes"), each from the library's autotuner and timed with HIP events:
                          (nearest-source solve) from a HIP graph, against 512 per-graph solves
   backward_rmat_s18      R-MAT scale 18, fp32 [1, 2) weights, 16 sources, loss over 1024
                          targets: forward GTEPS and backward GTEPS = k * m / t_backward
+  grid_4096              4096 x 4096 grid, u32 U[1, 1000], corner source, delta 50 / 100 / 400:
+                         the high-diameter case (thousands of buckets), one source per launch
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -304,6 +306,43 @@ def mode_backward(dev, steps: int) -> dict:
             "backward_ms": round(ms_b, 3), "backward_gteps": round(len(srcs) * g.m / ms_b / 1e6, 3)}
 
 
+def mode_grid(dev, steps: int) -> dict:
+    """The high-diameter workload: a 4096 x 4096 4-neighbour grid, u32 weights U[1,1000] per
+    directed edge, the corner source, one source per launch, for each delta of {50, 100, 400}.
+    Thousands of buckets with small frontiers: bound by the latency of the steps and their
+    barriers rather than by HBM, which the per-phase time and the algorithmic GB/s show."""
+    import torch
+
+    from paper_1911_06895_amd import graphs as G
+    from paper_1911_06895_amd import sssp
+
+    g = G.workload("grid4096_u32")
+    rp, ci, wt = device_graph(g, dev)
+    src = np.zeros(1, dtype=np.int32)
+    dist = torch.empty((1, g.n), dtype=torch.int32, device=dev)
+    per_delta, ref = {}, None
+    for delta in (50.0, 100.0, 400.0):
+        h = sssp.sssp_create(rp, ci, wt, delta)
+        ms = timed_ms(lambda: sssp.sssp_solve(h, src, dist), reps=steps)
+        st = sssp.sssp_last_stats(h)
+        sssp.sssp_destroy(h)
+        rows = dist.cpu().numpy().view(np.uint32)
+        if ref is None:
+            ref = rows.copy()
+        elif not np.array_equal(rows, ref):
+            raise SystemExit("bench: grid distances differ between deltas")
+        m_r = reached_edges(g, rows)
+        gbs = algorithmic_bytes(g, rows, st["improvements"]) / ms / 1e6
+        phases = st["light_phases"] + st["heavy_phases"]
+        per_delta[f"{delta:g}"] = {"ms": round(ms, 3), "gteps": round(m_r / ms / 1e6, 4),
+                                   "algorithmic_gbs": round(gbs, 2), "hbm_frac": round(gbs / HBM_PEAK_GBS, 5),
+                                   "buckets": st["buckets"], "phases": phases,
+                                   "us_per_phase": round(ms * 1e3 / max(1, phases), 2)}
+    best = min(per_delta, key=lambda k: per_delta[k]["ms"])
+    return {"workload": "grid 4096 x 4096, 4-neighbour, u32 U[1,1000], corner source, one source per launch",
+            "n": g.n, "m": g.m, "best_delta": float(best), "per_delta": per_delta}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -417,7 +456,7 @@ def main():
         log(f"[bench] concurrent_rmat_s22_k64: {modes['concurrent_rmat_s22_k64']} ({time.perf_counter() - t0:.1f}s)")
     if not args.no_modes:
         for name, fn in (("batched_rmat_s18_k256", mode_batched_s18), ("batched_ragged_er512", mode_batched_ragged),
-                         ("backward_rmat_s18", mode_backward)):
+                         ("backward_rmat_s18", mode_backward), ("grid_4096", mode_grid)):
             t0 = time.perf_counter()
             modes[name] = fn(dev, max(1, args.steps))
             log(f"[bench] {name}: {modes[name]} ({time.perf_counter() - t0:.1f}s)")
