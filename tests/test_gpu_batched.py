@@ -58,18 +58,22 @@ def test_concurrent_groups_match_oracle(groups, kind):
         solver.close()
 
 
-@pytest.mark.parametrize("groups", [1, 2])
-def test_reused_distance_buffers(groups):
+@pytest.mark.parametrize("groups,wpc,kind", [(1, 0, "u32"), (2, 0, "u32"), (1, 1, "u32"), (2, 0, "f32_loguniform"),
+                                             (16, 0, "f32_loguniform")])
+def test_reused_distance_buffers(groups, wpc, kind):
     """Hundreds of rows per group in one launch: each of a group's two distance
     buffers serves every other row, so the cached copies an earlier row leaves
     must never feed the next row's prefilter. Every row is certified, over
-    three launches."""
-    print(f"[batched] reused buffers groups={groups}", flush=True)
-    g, delta = G.rmat_graph(14, 16, cfg=61, weights="u32", wlo=1, whi=255), 32
+    three launches (wpc 1: the 1024-thread workgroup configuration)."""
+    print(f"[batched] reused buffers groups={groups} workgroups_per_cu={wpc} kind={kind}", flush=True)
+    if kind == "u32":
+        g, delta = G.rmat_graph(14, 16, cfg=61, weights="u32", wlo=1, whi=255), 32
+    else:
+        g, delta = G.rmat_graph(14, 16, cfg=62, weights="f32_loguniform", wlo=1e-2, whi=1e2), 2.0 ** -5
     srcs = G.sources_with_outedges(g, 401, cfg=64)
     solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, delta)
     try:
-        solver.set_tuning(concurrent_sources=groups)
+        solver.set_tuning(concurrent_sources=groups, workgroups_per_cu=wpc)
         for launch in range(3):
             rows = solver.solve_numpy(srcs)
             check_rows(g, srcs, rows, exact_rows=2 if launch == 0 else 0)
