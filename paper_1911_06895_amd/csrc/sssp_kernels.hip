@@ -562,20 +562,13 @@ __device__ inline void queue_hub(uint32_t u, uint32_t deg) {
     st_agent(&queue[base + k], static_cast<uint64_t>(u) | (static_cast<uint64_t>(k) << 32));
 }
 
-// One relaxation phase: every vertex u of the input list sends t(u) (+) w along
-// its light (kLight) or heavy out-edges -- the masked min-plus product
-// t_Req = A_L^T (t o t_Bi) or A_H^T (t o S) of Sec. IV-C/IV-D, fused with the
-// min-merge into t (the paper's fusion of the Hadamard product into vxm).
-// Edges are balanced over the workgroup: the degrees of kChunk list entries
-// are prefix-summed in LDS and the lanes walk the concatenated edge ranges, so
-// consecutive lanes read consecutive edges of a row. Vertices with kHub or
-// more edges are queued as pieces for a grid-wide hub step instead.
 // A group of at least this many workgroups (most of the device) hands hub
 // pieces over between light phases, claims chunks of at most kChunk / 2
 // entries (more chunks per workgroup: better balance over many workgroups)
 // and runs steps of at most kChunk / 2 entries on the leader alone; smaller
 // groups use kChunk for both.
 constexpr uint32_t kHandOverMinGroup = 128;  // workgroups
+__device__ inline uint32_t chunk_cap(uint32_t size) { return size >= kHandOverMinGroup ? kChunk / 2 : kChunk; }
 
 // List entries per claimed chunk: enough chunks for about four per workgroup.
 // Chunk sizes are powers of two (the edge-to-entry search relies on it).
@@ -607,6 +600,14 @@ struct Entry {
 template <class W>
 __device__ void hub_pieces(typename W::T* t, bool light);
 
+// One relaxation phase: every vertex u of the input list sends t(u) (+) w along
+// its light (kLight) or heavy out-edges -- the masked min-plus product
+// t_Req = A_L^T (t o t_Bi) or A_H^T (t o S) of Sec. IV-C/IV-D, fused with the
+// min-merge into t (the paper's fusion of the Hadamard product into vxm).
+// Edges are balanced over the workgroup: the degrees of kChunk list entries
+// are prefix-summed in LDS and the lanes walk the concatenated edge ranges, so
+// consecutive lanes read consecutive edges of a row. Vertices with kHub or
+// more edges are queued as pieces for a grid-wide hub step instead.
 template <class W, bool kLight>
 __device__ __attribute__((always_inline)) void phase(typename W::T* t, bool solo, bool preloaded = false,
                                                      Entry<typename W::T> pre = Entry<typename W::T>{}) {
@@ -625,7 +626,7 @@ __device__ __attribute__((always_inline)) void phase(typename W::T* t, bool solo
   const uint32_t count = s.in_count;
   const uint64_t near_end = static_cast<uint64_t>(s.bucket) + p.ring;  // no wrap near 2^32
   const uint32_t size = grp_size(p);
-  const uint32_t chunk = solo ? solo_chunk(count) : chunk_for(count, size, size >= kHandOverMinGroup ? kChunk / 2 : kChunk);
+  const uint32_t chunk = solo ? solo_chunk(count) : chunk_for(count, size, chunk_cap(size));
   const uint32_t nchunks = (count + chunk - 1) / chunk;
   if constexpr (kLight) {
     if (!solo && s.hub_backlog > 0) hub_pieces<W>(t, true);  // the previous light phase's pieces
@@ -1091,7 +1092,7 @@ __device__ void lead(typename W::T* t, bool schedule_first) {
   if (schedule_first) after_step<W>();
   for (;;) {  // *s is the current schedule (set by leader_start or after_step)
     const bool light = s->action == kActLight;
-    if (!(light || s->action == kActHeavy) || s->in_count > (grp_size(p) >= kHandOverMinGroup ? kChunk / 2 : kChunk) || s->hub_backlog > 0) break;
+    if (!(light || s->action == kActHeavy) || s->in_count > chunk_cap(grp_size(p)) || s->hub_backlog > 0) break;
     Entry<typename W::T> e{};
     const uint32_t edges = light ? step_edges<true, W>(t, s_wsum, &e) : step_edges<false, W>(t, s_wsum, &e);
     if (edges > p.inline_edges) break;
