@@ -95,24 +95,43 @@ hipError_t dalloc(T** p, size_t count) {
   return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
 }
 
+void free_group(GroupMem& gm) {
+  void* mem[] = {gm.tbuf[0], gm.tbuf[1], gm.qstamp, gm.sstamp, gm.bstamp, gm.fstamp, gm.ovf_at, gm.front[0],
+                 gm.front[1], gm.slist, gm.bins, gm.far[0], gm.far[1], gm.hub};
+  for (void* q : mem)
+    if (q) (void)hipFree(q);
+  gm = GroupMem{};
+}
+
+void free_adj_group(sssp_handle::AdjMem& am) {
+  void* mem[] = {am.d, am.parent, am.cnt, am.g};
+  for (void* q : mem)
+    if (q) (void)hipFree(q);
+  am = sssp_handle::AdjMem{};
+}
+
+// The first group's adjoint working set (all of it or none of it).
+void free_adj(sssp_handle* h) {
+  void* mem[] = {h->adj_d, h->adj_parent, h->adj_cnt, h->adj_g, h->adj_grad64, h->adj_params_dev};
+  for (void* q : mem)
+    if (q) (void)hipFree(q);
+  h->adj_d = nullptr;
+  h->adj_parent = nullptr;
+  h->adj_cnt = nullptr;
+  h->adj_g = nullptr;
+  h->adj_grad64 = nullptr;
+  h->adj_params_dev = nullptr;
+}
+
 void free_handle(sssp_handle* h) {
   if (!h) return;
   sssp::Params& p = h->p;
-  void* extra[] = {h->inv, h->adj_d, h->adj_parent, h->adj_cnt, h->adj_g, h->adj_grad64, h->aux, h->params_dev, h->w64,
-                   h->adj_params_dev};
+  free_adj(h);
+  void* extra[] = {h->inv, h->aux, h->params_dev, h->w64};
   for (void* q : extra)
     if (q) (void)hipFree(q);
-  for (sssp_handle::AdjMem& am : h->adj_extra) {
-    void* mem[] = {am.d, am.parent, am.cnt, am.g};
-    for (void* q : mem)
-      if (q) (void)hipFree(q);
-  }
-  for (GroupMem& gm : h->extra) {
-    void* mem[] = {gm.tbuf[0], gm.tbuf[1], gm.qstamp, gm.sstamp, gm.bstamp, gm.fstamp, gm.ovf_at, gm.front[0],
-                   gm.front[1], gm.slist, gm.bins, gm.far[0], gm.far[1], gm.hub};
-    for (void* q : mem)
-      if (q) (void)hipFree(q);
-  }
+  for (sssp_handle::AdjMem& am : h->adj_extra) free_adj_group(am);
+  for (GroupMem& gm : h->extra) free_group(gm);
   void* dev[] = {h->off, h->split, const_cast<uint4*>(p.rows), const_cast<uint64_t*>(p.edges),
                  p.qstamp, p.sstamp, p.bstamp, p.fstamp, p.ovf_at, p.front[0], p.front[1], p.slist, p.bins,
                  p.far[0], p.far[1], p.hub, h->ctls, h->perm, h->src_dev, const_cast<uint32_t*>(p.vid), p.tbuf[0],
@@ -583,16 +602,20 @@ sssp_status sssp_backward(sssp_handle* h, const int32_t* sources, int32_t k, con
   hipStream_t s = static_cast<hipStream_t>(stream);
   SSSP_TRY(hipSetDevice(h->device));
   const size_t un = static_cast<size_t>(h->n), um = static_cast<size_t>(h->m);
-  if (!h->adj_d) {
-    SSSP_TRY(dalloc(&h->adj_d, un));
-    SSSP_TRY(dalloc(&h->adj_parent, un));
-    SSSP_TRY(dalloc(&h->adj_cnt, un));
-    SSSP_TRY(dalloc(&h->adj_g, un));
-    SSSP_TRY(dalloc(&h->adj_grad64, um));
-    SSSP_TRY(dalloc(&h->adj_params_dev, sssp::kMaxGroups));
+  if (!h->adj_d) {  // allocated whole or not at all (a later call tests adj_d only)
     int occ = 0;
     SSSP_TRY(sssp::adjoint_occupancy(&occ));
     if (occ < 1) return SSSP_ERR_UNSUPPORTED;
+    hipError_t e = dalloc(&h->adj_d, un);
+    if (e == hipSuccess) e = dalloc(&h->adj_parent, un);
+    if (e == hipSuccess) e = dalloc(&h->adj_cnt, un);
+    if (e == hipSuccess) e = dalloc(&h->adj_g, un);
+    if (e == hipSuccess) e = dalloc(&h->adj_grad64, um);
+    if (e == hipSuccess) e = dalloc(&h->adj_params_dev, sssp::kMaxGroups);
+    if (e != hipSuccess) {
+      free_adj(h);
+      return from_hip(e);
+    }
     h->adj_grid = h->cus;
   }
   // sources share the launch as in the forward solve: one group per concurrent source
@@ -600,10 +623,15 @@ sssp_status sssp_backward(sssp_handle* h, const int32_t* sources, int32_t k, con
   while (h->adj_extra.size() + 1 < groups) {
     h->adj_extra.emplace_back();
     sssp_handle::AdjMem& am = h->adj_extra.back();
-    SSSP_TRY(dalloc(&am.d, un));
-    SSSP_TRY(dalloc(&am.parent, un));
-    SSSP_TRY(dalloc(&am.cnt, un));
-    SSSP_TRY(dalloc(&am.g, un));
+    hipError_t e = dalloc(&am.d, un);
+    if (e == hipSuccess) e = dalloc(&am.parent, un);
+    if (e == hipSuccess) e = dalloc(&am.cnt, un);
+    if (e == hipSuccess) e = dalloc(&am.g, un);
+    if (e != hipSuccess) {  // a partly allocated working set is not kept
+      free_adj_group(am);
+      h->adj_extra.pop_back();
+      return from_hip(e);
+    }
   }
   const sssp_status st = stage_sources(h, sources, k, s);
   if (st != SSSP_OK) return st;
@@ -677,14 +705,21 @@ sssp_status sssp_set_weights(sssp_handle* h, const void* weights, void* stream) 
   const uint32_t ring = ring_for(h, ws.wmax_bits);
   if (ring > p.ring) {  // a larger weight spread needs more near buckets (in every group)
     SSSP_TRY(hipDeviceSynchronize());
-    uint32_t* bins = nullptr;
-    SSSP_TRY(dalloc(&bins, un * ring));
+    // all the larger rings first: on a failure the handle keeps its old ones
+    std::vector<uint32_t*> bins(h->extra.size() + 1, nullptr);
+    hipError_t e = hipSuccess;
+    for (uint32_t*& b : bins)
+      if (e == hipSuccess) e = dalloc(&b, un * ring);
+    if (e != hipSuccess) {
+      for (uint32_t* b : bins)
+        if (b) (void)hipFree(b);
+      return from_hip(e);
+    }
     (void)hipFree(p.bins);
-    p.bins = bins;
-    for (GroupMem& gm : h->extra) {
-      (void)hipFree(gm.bins);
-      gm.bins = nullptr;
-      SSSP_TRY(dalloc(&gm.bins, un * ring));
+    p.bins = bins[0];
+    for (size_t g = 0; g < h->extra.size(); ++g) {
+      (void)hipFree(h->extra[g].bins);
+      h->extra[g].bins = bins[g + 1];
     }
     p.ring = ring;
     p.ring_mask = ring - 1;
@@ -746,6 +781,10 @@ sssp_status sssp_set_tuning(sssp_handle* h, const sssp_tuning* t) {
   while (st == SSSP_OK && h->extra.size() + 1 < groups) {
     h->extra.emplace_back();
     st = alloc_group(h, &h->extra.back());
+    if (st != SSSP_OK) {  // a partly allocated working set is not kept
+      free_group(h->extra.back());
+      h->extra.pop_back();
+    }
   }
   if (st != SSSP_OK) {
     h->tuning = old;
