@@ -15,7 +15,9 @@
  *   - Pointers documented as "device" are HIP device pointers on the device
  *     that is current when sssp_create is called; "host" pointers are ordinary
  *     host memory. The caller owns every pointer it passes; the library never
- *     frees caller memory and keeps no caller pointer after a call returns.
+ *     frees caller memory and keeps no caller pointer after a call returns,
+ *     except the trace buffer that sssp_set_trace attaches (kept until
+ *     detached or replaced).
  *   - stream: a hipStream_t passed as void* (NULL = the null stream). Work is
  *     enqueued on it; calls documented as synchronising wait for it.
  *   - On error, outputs are unspecified and a handle stays valid (except that
