@@ -6,6 +6,7 @@ ctypes and shares no code with the GPU library.
 
 Functions (each a plain, slow, obviously correct reading of the paper):
   dijkstra(g, s)               textbook binary-heap Dijkstra: the definition of the result
+  dijkstra_many(g, ss, t)      dijkstra from many sources on t host threads (CPU-baseline timing)
   delta_stepping_la(g, d, s)   linear-algebra delta-stepping of Fig. 1 (left), with a trace
   delta_stepping_sets(g, d, s) Meyer-Sanders bucket form of Fig. 1 (right), with a trace
   bellman_ford(g, s)           brute force, exact integer sums
@@ -25,7 +26,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCE = os.path.join(_HERE, "oracle.c")
 LIBRARY = os.path.join(_HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-          "-fexcess-precision=standard", "-Wall", "-Wno-maybe-uninitialized"]
+          "-fexcess-precision=standard", "-pthread", "-Wall", "-Wno-maybe-uninitialized"]
 
 KIND = {np.dtype(np.uint32): 0, np.dtype(np.float32): 1, np.dtype(np.float64): 2}
 OK, OVERFLOW, BADARG, NOMEM, CLOSED_BUCKET = 0, 1, 2, 3, 4
@@ -88,6 +89,8 @@ class Oracle:
         lib.orc_bucket_of.restype = ctypes.c_int64
         lib.orc_sp_gradient.argtypes = [I64, P, P, P, ctypes.c_int, ctypes.c_int32, P, P, P, P]
         lib.orc_sp_gradient.restype = ctypes.c_int
+        lib.orc_dijkstra_many.argtypes = [I64, P, P, P, ctypes.c_int, P, ctypes.c_int32, P, ctypes.c_int32]
+        lib.orc_dijkstra_many.restype = ctypes.c_int
         self.lib = lib
 
     def dijkstra(self, g, src: int) -> tuple[np.ndarray, int]:
@@ -95,6 +98,19 @@ class Oracle:
         rp, col, w, kind = _csr(g)
         out = np.empty(g.n, dtype=w.dtype)
         rc = self.lib.orc_dijkstra(g.n, _ptr(rp), _ptr(col), _ptr(w), kind, int(src), _ptr(out))
+        if rc == BADARG:
+            raise ValueError("bad graph or source")
+        return out, rc
+
+    def dijkstra_many(self, g, sources, threads: int) -> tuple[np.ndarray, int]:
+        """dijkstra for every source (rows of the result), run on ``threads`` host threads."""
+        rp, col, w, kind = _csr(g)
+        src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32).reshape(-1))
+        if src.size and (src.min() < 0 or src.max() >= g.n):
+            raise ValueError("bad source")
+        out = np.empty((src.size, g.n), dtype=w.dtype)
+        rc = self.lib.orc_dijkstra_many(g.n, _ptr(rp), _ptr(col), _ptr(w), kind, _ptr(src), int(src.size),
+                                        _ptr(out), int(threads))
         if rc == BADARG:
             raise ValueError("bad graph or source")
         return out, rc
@@ -178,6 +194,10 @@ def default() -> Oracle:
 
 def dijkstra(g, src):
     return default().dijkstra(g, src)
+
+
+def dijkstra_many(g, sources, threads):
+    return default().dijkstra_many(g, sources, threads)
 
 
 def bellman_ford(g, src):

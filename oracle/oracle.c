@@ -29,12 +29,14 @@
  *                     the relax procedure (Sec. III-C, Fig. 1 right);
  *   orc_bellman_ford  brute-force Bellman-Ford (n rounds over all edges);
  *   orc_certify       O(m) optimality certificate of a candidate distance vector;
- *   orc_sp_gradient   dL/dw by reverse accumulation over the shortest-path tree.
+ *   orc_sp_gradient   dL/dw by reverse accumulation over the shortest-path tree;
+ *   orc_dijkstra_many orc_dijkstra from many sources on host threads (timing aid).
  *
- * Build: gcc -O2 -fPIC -shared -ffp-contract=off -fno-fast-math (x86-64 SSE
+ * Build: gcc -O2 -fPIC -shared -pthread -ffp-contract=off -fno-fast-math (x86-64 SSE
  * arithmetic: float and double operations are rounded once, no excess precision).
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -562,13 +564,21 @@ int orc_certify(int64_t n, const int64_t *rp, const int32_t *col, const void *w,
 /*
  * Gradient of L = sum over reached v of grad_dist[v] * d(v) with respect to
  * the edge weights, through the shortest-path tree (reverse accumulation).
- *   parent of v != s (d(v) finite): the tight in-edge (d(u) finite and
- *   d(u) (+) w == d(v)) with the smallest edge index; d(v) is the fold of the
- *   weights along its tree path, so dd(v)/dw_e = 1 for the edges of that path
- *   and 0 otherwise, and dL/dw_e for e = (parent(v), v) is the sum of
- *   grad_dist over the subtree below v (grad_dist of s and of unreached
- *   vertices is ignored). Where several shortest paths tie, this is the
- *   gradient along the chosen tree (a subgradient).
+ *   parent of v != s (d(v) finite): a tight in-edge (d(u) finite and
+ *   d(u) (+) w == d(v)) from a strictly closer vertex (d(u) < d(v)), the one
+ *   with the smallest edge index. In exact arithmetic every tight edge is of
+ *   that kind. With rounding, d(u) (+) w can equal d(u) (absorption in
+ *   binary32 / binary64), so a vertex may be tight only through in-edges from
+ *   vertices at its own distance, and those edges can form cycles. Such
+ *   vertices take their parent in rounds: round 0 holds s and every vertex
+ *   with a strictly-closer parent; round k gives each still unresolved vertex
+ *   the smallest-index tight in-edge from a vertex resolved in round k - 1.
+ *   The parents then form a tree. d(v) is the fold of the weights along its
+ *   tree path, so dd(v)/dw_e = 1 for the edges of that path and 0 otherwise,
+ *   and dL/dw_e for e = (parent(v), v) is the sum of grad_dist over the
+ *   subtree below v (grad_dist of s and of unreached vertices is ignored).
+ *   Where several shortest paths tie, this is the gradient along the chosen
+ *   tree (a subgradient).
  * grad_w is ACCUMULATED (+=), in double. parent_edge (optional) receives the
  * chosen edge index of every vertex, -1 for s and unreached vertices.
  * Returns ORC_BADARG when dist is not a shortest-path vector (a reached vertex
@@ -581,13 +591,14 @@ int orc_sp_gradient(int64_t n, const int64_t *rp, const int32_t *col, const void
   int64_t *pe = malloc(sizeof(int64_t) * n), *pv = malloc(sizeof(int64_t) * n);
   int64_t *nchild = calloc(n + 1, sizeof(int64_t)), *child = malloc(sizeof(int64_t) * (n + 1));
   int64_t *stack = malloc(sizeof(int64_t) * (n + 1)), *order = malloc(sizeof(int64_t) * (n + 1));
-  if (!d || !g || !pe || !pv || !nchild || !child || !stack || !order) {
-    free(d); free(g); free(pe); free(pv); free(nchild); free(child); free(stack); free(order);
+  int64_t *round_of = malloc(sizeof(int64_t) * (n + 1));
+  if (!d || !g || !pe || !pv || !nchild || !child || !stack || !order || !round_of) {
+    free(d); free(g); free(pe); free(pv); free(nchild); free(child); free(stack); free(order); free(round_of);
     return ORC_NOMEM;
   }
   int rc = ORC_OK;
   for (int64_t v = 0; v < n; ++v) { d[v] = load_dist(kind, dist, v); pe[v] = -1; pv[v] = -1; }
-  /* parents: smallest-index tight in-edge */
+  /* parents: smallest-index tight in-edge from a strictly closer vertex */
   for (int64_t u = 0; u < n; ++u) {
     if (isinf(d[u])) continue;
     for (int64_t e = rp[u]; e < rp[u + 1]; ++e) {
@@ -595,8 +606,26 @@ int orc_sp_gradient(int64_t n, const int64_t *rp, const int32_t *col, const void
       if (v == src) continue;
       int ovf;
       double c = plus(kind, d[u], weight_of(kind, w, e), &ovf);
-      if (!ovf && c == d[v] && (pe[v] < 0 || e < pe[v])) { pe[v] = e; pv[v] = u; }
+      if (!ovf && c == d[v] && d[u] < d[v] && (pe[v] < 0 || e < pe[v])) { pe[v] = e; pv[v] = u; }
     }
+  }
+  /* vertices tight only through equal-distance in-edges: rounds from the resolved ones */
+  for (int64_t v = 0; v < n; ++v) round_of[v] = (!isinf(d[v]) && (v == src || pe[v] >= 0)) ? 0 : -1;
+  for (int64_t k = 1;; ++k) {
+    int grew = 0;
+    for (int64_t u = 0; u < n; ++u) {
+      if (round_of[u] != k - 1) continue;
+      for (int64_t e = rp[u]; e < rp[u + 1]; ++e) {
+        int64_t v = col[e];
+        if (v == src || isinf(d[v]) || (round_of[v] >= 0 && round_of[v] < k)) continue;
+        int ovf;
+        double c = plus(kind, d[u], weight_of(kind, w, e), &ovf);
+        if (ovf || c != d[v]) continue;
+        if (round_of[v] < 0) { round_of[v] = k; pe[v] = e; pv[v] = u; grew = 1; }
+        else if (e < pe[v]) { pe[v] = e; pv[v] = u; }
+      }
+    }
+    if (!grew) break;
   }
   int64_t reached = 0;
   for (int64_t v = 0; v < n; ++v) {
@@ -633,6 +662,63 @@ int orc_sp_gradient(int64_t n, const int64_t *rp, const int32_t *col, const void
     }
   }
   if (parent_edge) for (int64_t v = 0; v < n; ++v) parent_edge[v] = pe[v];
-  free(d); free(g); free(pe); free(pv); free(nchild); free(child); free(stack); free(order);
+  free(d); free(g); free(pe); free(pv); free(nchild); free(child); free(stack); free(order); free(round_of);
   return rc;
+}
+
+/* ------------------------------------------------------------ many sources on host threads */
+
+/*
+ * Timing aid for the CPU baseline: orc_dijkstra for each of k sources (row r of
+ * dist_out <- sources[r]), spread over `threads` POSIX threads, each taking the
+ * next source from a shared counter. The arithmetic is orc_dijkstra's, unchanged.
+ * Returns the first non-OK status of any row (ORC_OK if none).
+ */
+typedef struct {
+  int64_t n;
+  const int64_t *rp;
+  const int32_t *col;
+  const void *w;
+  int kind;
+  const int32_t *sources;
+  int32_t k;
+  char *out;
+  size_t row_bytes;
+  int32_t next;
+  int rc;
+  pthread_mutex_t lock;
+} many_job;
+
+static void *many_worker(void *arg) {
+  many_job *j = arg;
+  for (;;) {
+    pthread_mutex_lock(&j->lock);
+    int32_t r = j->next++;
+    pthread_mutex_unlock(&j->lock);
+    if (r >= j->k) break;
+    int rc = orc_dijkstra(j->n, j->rp, j->col, j->w, j->kind, j->sources[r], j->out + (size_t)r * j->row_bytes);
+    if (rc != ORC_OK) {
+      pthread_mutex_lock(&j->lock);
+      if (j->rc == ORC_OK) j->rc = rc;
+      pthread_mutex_unlock(&j->lock);
+    }
+  }
+  return NULL;
+}
+
+int orc_dijkstra_many(int64_t n, const int64_t *rp, const int32_t *col, const void *w, int kind,
+                      const int32_t *sources, int32_t k, void *dist_out, int32_t threads) {
+  if (k < 0 || threads < 1 || !sources || !dist_out || kind < 0 || kind > 2) return ORC_BADARG;
+  many_job j = {n, rp, col, w, kind, sources, k, dist_out, (size_t)n * (kind == ORC_F64 ? 8 : 4), 0, ORC_OK,
+                PTHREAD_MUTEX_INITIALIZER};
+  if (threads > k) threads = k > 0 ? k : 1;
+  pthread_t *tid = malloc(sizeof(pthread_t) * threads);
+  if (!tid) return ORC_NOMEM;
+  int started = 0;
+  for (int t = 0; t < threads; ++t)
+    if (pthread_create(&tid[t], NULL, many_worker, &j) == 0) ++started;
+  if (started == 0) many_worker(&j);
+  for (int t = 0; t < started; ++t) pthread_join(tid[t], NULL);
+  free(tid);
+  return j.rc;
 }

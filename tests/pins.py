@@ -388,7 +388,10 @@ ALL_PINS = [pin_golden_worked_example, pin_golden_fp32, pin_tiny_random_agree, p
 # ---------------------------------------------------------------- adjoint (dL/dw) pins
 
 def _tree_parents_bruteforce(g, s, d):
-    """Parent of every reached v != s: the tight in-edge with the smallest edge index (numpy)."""
+    """Parent of every reached v != s (numpy): the smallest-index tight in-edge from a strictly
+    closer vertex; vertices tight only through equal-distance in-edges (rounding absorption)
+    take, round by round, the smallest-index tight in-edge from a vertex resolved in the
+    previous round (round 0: s and every vertex with a strictly-closer parent)."""
     src = g.edge_src()
     fin = finite(d)
     wd = g.w.astype(np.float64)
@@ -399,8 +402,19 @@ def _tree_parents_bruteforce(g, s, d):
         cand = dd[src] + wd
     tight = fin[src] & (cand == dd[g.col]) & (g.col != s)
     parent = np.full(g.n, -1, dtype=np.int64)
-    for e in np.nonzero(tight)[0][::-1]:  # descending, so the smallest index is written last
+    strict = tight & (dd[src] < dd[g.col])
+    for e in np.nonzero(strict)[0][::-1]:  # descending, so the smallest index is written last
         parent[g.col[e]] = e
+    rnd = np.where(fin & ((np.arange(g.n) == s) | (parent >= 0)), 0, -1)
+    k = 1
+    while True:
+        grow = tight & (rnd[src] == k - 1) & (rnd[g.col] < 0)
+        if not grow.any():
+            break
+        for e in np.nonzero(grow)[0][::-1]:
+            parent[g.col[e]] = e
+        rnd[g.col[grow]] = k
+        k += 1
     return parent, src
 
 
@@ -436,7 +450,7 @@ def pin_gradient_closed_forms(o) -> list[str]:
         gw, pe = o.sp_gradient(g, s, d, ones)
         parent, src = _tree_parents_bruteforce(g, s, d)
         if not np.array_equal(pe, parent):
-            fails.append(f"adjoint parents ({dt.__name__}): not the smallest tight in-edge")
+            fails.append(f"adjoint parents ({dt.__name__}): not the smallest strictly-closer tight in-edge")
             continue
         want = np.zeros(g.m)
         for t in np.nonzero(finite(d))[0]:
@@ -503,4 +517,30 @@ def pin_gradient_ties(o) -> list[str]:
     return []
 
 
-ALL_PINS += [pin_gradient_closed_forms, pin_gradient_finite_differences, pin_gradient_ties]
+def pin_gradient_absorption(o) -> list[str]:
+    """The hand-worked binary32 absorption case (tests/golden/fp32_absorption_adjoint.json): two
+    vertices at equal distance whose tight edges form a cycle; the tree goes through the
+    strictly closer vertex first."""
+    gd = _load_golden("fp32_absorption_adjoint.json")
+    g = _graph_from_edges(gd["n"], gd["edges"], np.float32)
+    want_d = np.array(gd["dist"], dtype=np.float32)
+    fails = []
+    d, rc = o.dijkstra(g, gd["source"])
+    if rc or not np.array_equal(bits(d), bits(want_d)):
+        fails.append(f"absorption golden: distances {d} != {want_d}")
+        return fails
+    if o.certify(g, gd["source"], want_d) != 0:
+        fails.append("absorption golden: certificate rejects the fp32 distances")
+    try:
+        gw, pe = o.sp_gradient(g, gd["source"], want_d, np.array(gd["grad_dist"], dtype=np.float64))
+    except ValueError as e:
+        return fails + [f"absorption golden: gradient refused the distances ({e})"]
+    if pe.tolist() != gd["parent_edge"] or gw.tolist() != gd["grad_w"]:
+        fails.append(f"absorption golden: parents {pe.tolist()} grad {gw.tolist()}")
+    parent, _ = _tree_parents_bruteforce(g, gd["source"], want_d)
+    if parent.tolist() != gd["parent_edge"]:
+        fails.append(f"absorption golden: numpy parents {parent.tolist()}")
+    return fails
+
+
+ALL_PINS += [pin_gradient_closed_forms, pin_gradient_finite_differences, pin_gradient_ties, pin_gradient_absorption]

@@ -48,8 +48,14 @@ PLANTED = [
     ("S accumulated from the next frontier",
      "      /* S = (S + tB) > 0 */\n      for (int64_t v = 0; v < n; ++v)\n        if (tb[v]) { S[v] = 1; trace_s_member(tr, v, (int64_t)i); }\n",
      ""),
-    ("adjoint parent is the largest tight edge", "if (!ovf && c == d[v] && (pe[v] < 0 || e < pe[v])) { pe[v] = e; pv[v] = u; }",
-     "if (!ovf && c == d[v] && (pe[v] < 0 || e > pe[v])) { pe[v] = e; pv[v] = u; }"),
+    ("adjoint parent is the largest tight edge",
+     "if (!ovf && c == d[v] && d[u] < d[v] && (pe[v] < 0 || e < pe[v])) { pe[v] = e; pv[v] = u; }",
+     "if (!ovf && c == d[v] && d[u] < d[v] && (pe[v] < 0 || e > pe[v])) { pe[v] = e; pv[v] = u; }"),
+    ("adjoint parent taken from an equal-distance vertex",
+     "if (!ovf && c == d[v] && d[u] < d[v] && (pe[v] < 0 || e < pe[v])) { pe[v] = e; pv[v] = u; }",
+     "if (!ovf && c == d[v] && (pe[v] < 0 || e < pe[v])) { pe[v] = e; pv[v] = u; }"),
+    ("adjoint leaves absorbed vertices without a parent",
+     "if (round_of[v] < 0) { round_of[v] = k; pe[v] = e; pv[v] = u; grew = 1; }", "if (0) {}"),
     ("adjoint drops the vertex's own coefficient", "for (int64_t v = 0; v < n; ++v) g[v] = (isinf(d[v]) || v == src) ? 0.0 : grad_dist[v];",
      "for (int64_t v = 0; v < n; ++v) g[v] = 0.0;"),
     ("adjoint does not pass subtree sums up", "        g[pv[v]] += g[v];\n", "\n"),
