@@ -38,7 +38,8 @@ typedef enum {
   SSSP_ERR_INVALID_ARGUMENT = 1, /* null pointer, bad sizes, malformed CSR, bad delta or source */
   SSSP_ERR_INVALID_WEIGHT = 2,   /* a weight that is zero, negative, NaN or infinite */
   SSSP_ERR_OUT_OF_MEMORY = 3,    /* device allocation failed */
-  SSSP_ERR_DEVICE = 4,           /* a HIP runtime error or an aborted device schedule */
+  SSSP_ERR_DEVICE = 4,           /* a HIP runtime error or an aborted device schedule (a barrier wait
+                                    without progress past its limit, or an internal queue over capacity) */
   SSSP_ERR_OVERFLOW = 5,         /* a reachable vertex's distance is not representable */
   SSSP_ERR_NO_FORWARD = 6,       /* sssp_backward before any successful sssp_solve */
   SSSP_ERR_UNSUPPORTED = 7,      /* a size or type outside what this build handles */
@@ -94,12 +95,22 @@ typedef struct {
                                 more = two of 512 threads. Concurrent sources always run two
                                 512-thread workgroups per compute unit */
   int32_t ring_buckets;      /* buckets held in the near ring, power of two in [2, 64] (default: fit max weight) */
-  int32_t inline_edges;      /* phases scanning at most this many edges (and at most 512 list entries,
-                                256 in groups of 128 or more workgroups)
-                                run on one workgroup without a device-wide barrier (default 4096) */
+  int32_t inline_edges;      /* phases scanning at most this many edges (and at most inline_entries list
+                                entries) run on one workgroup without a device-wide barrier (default 4096) */
   int32_t concurrent_sources; /* sources solved at the same time, each by its own group of workgroups
                                  (a power of two dividing the launch's workgroup counts, at most 256; default 1).
                                  Each extra group holds its own working set, about (11 + ring) * 4 * n bytes */
+  int32_t wait_limit_ms;     /* a device-wide barrier wait that sees neither the release nor progress of the
+                                workgroup running steps alone inside the barrier for this long aborts the
+                                solve with SSSP_ERR_DEVICE instead of hanging (default 30000) */
+  int32_t hub_edges;         /* tile schedule: a vertex with at least this many edges in a phase is cut into
+                                pieces that the whole group relaxes (a hub step); power of two in
+                                [256, 65536] (default 1024) */
+  int32_t chunk_entries;     /* tile schedule: most list entries a workgroup claims and expands at a time;
+                                power of two in [32, 512] (default 512, 256 in groups of 128 or more
+                                workgroups) */
+  int32_t inline_entries;    /* tile schedule: most list entries of a phase that one workgroup runs alone
+                                inside the barrier, in [1, 512] (default: the chunk size) */
 } sssp_tuning;
 
 typedef struct sssp_handle sssp_handle;
@@ -201,9 +212,18 @@ sssp_status sssp_solve_status(sssp_handle *h, void *stream);
  *     dL/dw_e = sum over sources of the sum of grad_dist over the tree's
  *               subtree below e        (0 for edges in no tree).
  *   The tree is recomputed from dist: the parent of v is its tight in-edge
- *   (dist(u) (+) w == dist(v)) with the smallest caller edge index, which makes
- *   the result well defined under ties. grad_dist at unreachable vertices and
- *   at the source is ignored. Sums run in fp64; grad_w is written in fp32.
+ *   (dist(u) (+) w == dist(v)) from a strictly closer vertex (dist(u) <
+ *   dist(v)) with the smallest caller edge index, which makes the result well
+ *   defined under ties. Under fp32 rounding a weight can be absorbed (d (+) w
+ *   == d), so a vertex may be tight only through in-edges from vertices at its
+ *   own distance; such vertices are resolved in rounds, each taking the
+ *   smallest-index tight in-edge from a vertex resolved in the round before
+ *   (round 0: the source and the vertices with a strictly closer parent).
+ *   dist is checked on the device to be the shortest-path vector: dist(s) =
+ *   +0, no edge out of a reached vertex can lower its target (dist(v) <=
+ *   dist(u) (+) w), and every reached vertex hangs below s in the tree.
+ *   grad_dist at unreachable vertices and at the source is ignored. Sums run
+ *   in fp64; grad_w is written in fp32.
  *   sources: HOST int32 [k].  dist: DEVICE [k][n] float.  grad_dist: DEVICE
  *   [k][n] float.  grad_w: DEVICE [m] float, caller edge order, overwritten.
  *   With concurrent_sources = G (sssp_set_tuning), G sources are processed at
@@ -236,6 +256,13 @@ sssp_status sssp_last_stats(const sssp_handle *h, sssp_stats *out);
  * workgroup counts), OUT_OF_MEMORY.
  */
 sssp_status sssp_set_tuning(sssp_handle *h, const sssp_tuning *t);
+
+/*
+ * sssp_get_tuning -- the handle's schedule parameters with every default
+ *   resolved for a launch of its current concurrent-source count (out: HOST
+ *   struct, caller-owned). Errors: INVALID_ARGUMENT.
+ */
+sssp_status sssp_get_tuning(const sssp_handle *h, sssp_tuning *out);
 
 /*
  * sssp_set_trace -- attach a step trace (profiling aid; NULL/0 detaches).

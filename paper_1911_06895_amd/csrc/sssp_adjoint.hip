@@ -3,8 +3,19 @@
 // subtree hanging below e in each source's shortest-path tree (d(v) is the
 // fold of the weights along its tree path). Parents are recomputed from the
 // distances (no state is kept from the forward pass):
-//   1. parent of v = the tight in-edge (d(u) (+) w == d(v)) with the smallest
-//      caller edge index -- atomicMin over edges;
+//   1. every edge out of a reached vertex is checked for feasibility,
+//      d(y) <= d(x) (+) w, and d(s) must be +0: with tight parents leading back
+//      to s (checked below) this proves that the distances are the shortest
+//      ones (Sec. III-C: no relaxation can lower them);
+//      the parent of y is its tight in-edge (d(x) (+) w == d(y)) from a
+//      strictly closer vertex (d(x) < d(y)) with the smallest caller edge
+//      index -- atomicMin over edges. In exact arithmetic every tight edge is
+//      of that kind; with rounding, d(x) (+) w can equal d(x) (w absorbed), so
+//      a vertex may be tight only through in-edges from vertices at its own
+//      distance, which can form cycles. Those vertices are resolved in rounds:
+//      round 0 holds s and the vertices with a strictly closer parent; round k
+//      gives each unresolved vertex the smallest-index tight in-edge from a
+//      vertex resolved in round k - 1;
 //   2. children are counted; vertices without children form the first level;
 //   3. level by level, each vertex adds its accumulated value g(v) to its
 //      parent edge and to g(parent) (fp64 atomics); a parent whose last child
@@ -25,6 +36,15 @@ __device__ void adjoint_leader_level(Ctl* c, uint32_t cur) {
     st_agent(&c->in_count, ld_agent(&c->fcount[nxt]));
     st_agent(&c->fcount[cur], 0u);
     st_agent(&c->out_buf, nxt);
+  }
+}
+
+// The count gathered in scount by the step that just ended becomes in_count
+// (read by every workgroup after the barrier); scount restarts at zero.
+__device__ inline void adjoint_leader_count(Ctl* c) {
+  if (threadIdx.x == 0) {
+    st_agent(&c->in_count, ld_agent(&c->scount));
+    st_agent(&c->scount, 0u);
   }
 }
 
@@ -51,15 +71,21 @@ __global__ __launch_bounds__(kWG) void adjoint_kernel(const AdjParams* __restric
         st_agent(&c->source_index, r < static_cast<uint32_t>(k) ? r : kNone);
         st_agent(&c->fcount[0], 0u);
         st_agent(&c->fcount[1], 0u);
+        st_agent(&c->scount, 0u);
       }
     });
     if (threadIdx.x == 0) s_row = ld_agent(&c->source_index);
     __syncthreads();
     const uint32_t r = s_row;
     if (!alive || r == kNone) break;
+    const int32_t src = ldg(&sources[r]);
+    if (src < 0 || static_cast<uint32_t>(src) >= n) {  // every workgroup of the group skips the row
+      if (rank == 0 && threadIdx.x == 0) st_agent(&c->bad_source, 1u);
+      continue;
+    }
     const uint32_t* drow = dist + static_cast<size_t>(r) * n;
     const float* grow = grad_dist + static_cast<size_t>(r) * n;
-    const uint32_t s = ldg(&a.vid[ldg(&sources[r])]);
+    const uint32_t s = ldg(&a.vid[src]);
     // distances and coefficients in solver ids
     for (uint32_t x = tid; x < n; x += nthreads) {
       const uint32_t v = ldg(&a.inv[x]);
@@ -68,26 +94,81 @@ __global__ __launch_bounds__(kWG) void adjoint_kernel(const AdjParams* __restric
       st_agent(&a.parent[x], kNoParent);
       st_agent(&a.cnt[x], 0u);
       st_agent(&a.g[x], (dx < W::kInf && x != s) ? static_cast<double>(ldg(&grow[v])) : 0.0);
+      if (x == s && dx != 0u) st_agent(&c->ovf_real, 1u);  // d(s) must be +0
     }
     alive = grid_sync(c, size, rank, s_bar, [] {});
     if (!alive) break;
-    // 1. parents: one wave per row, lanes over the row's edges
+    // 1. feasibility, and parents from strictly closer vertices: one wave per row, lanes over its edges
     {
       const uint32_t wave = tid >> 6, nwaves = nthreads >> 6, l = lane();
       for (uint32_t x = wave; x < n; x += nwaves) {
         const uint32_t dx = ld_agent(&a.d[x]);
         if (dx >= W::kInf) continue;
         const uint4 row = ldg(&a.rows[x]);
+        bool infeasible = false;
         for (uint32_t p = row.x + l; p < row.z; p += 64) {
           const uint64_t ed = ldg(&a.edges[p]);
           const uint32_t y = static_cast<uint32_t>(ed);
           uint32_t cand;
-          if (y != s && W::add(dx, static_cast<uint32_t>(ed >> 32), &cand) && cand == ld_agent(&a.d[y]))
+          if (!W::add(dx, static_cast<uint32_t>(ed >> 32), &cand)) continue;  // the request does not fit: no bound
+          const uint32_t dy = ld_agent(&a.d[y]);
+          if (dy > cand) infeasible = true;  // an edge could still lower d(y)
+          else if (cand == dy && dx < dy && y != s)
             g_min(&a.parent[y], static_cast<unsigned long long>(ldg(&a.perm[p])) << 32 | x);
         }
+        if (__ballot(infeasible) && l == 0) st_agent(&c->ovf_real, 1u);
       }
     }
     alive = grid_sync(c, size, rank, s_bar, [] {});
+    if (!alive) break;
+    // 1b. round 0: s and the vertices with a strictly closer parent; the other reached vertices are unresolved
+    for (uint32_t it = 0, iters = (n + nthreads - 1) / nthreads; it < iters; ++it) {
+      const uint32_t y = it * nthreads + tid;
+      bool open = false;
+      if (y < n) {
+        open = y != s && ld_agent(&a.d[y]) < W::kInf && ld_agent(&a.parent[y]) == kNoParent;
+        st_agent(&a.lvl[y], open ? kNone : 0u);
+      }
+      const uint32_t cnt = static_cast<uint32_t>(__popcll(__ballot(open)));
+      if (cnt && lane() == 0) g_add(&c->scount, cnt);
+    }
+    alive = grid_sync(c, size, rank, s_bar, [&] { adjoint_leader_count(c); });
+    // 1c. rounds k = 1, 2, ... while unresolved vertices gain a parent
+    for (uint32_t rnd = 1; alive; ++rnd) {
+      if (threadIdx.x == 0) s_count = ld_agent(&c->in_count);
+      __syncthreads();
+      if (s_count == 0) break;
+      {
+        const uint32_t wave = tid >> 6, nwaves = nthreads >> 6, l = lane();
+        for (uint32_t x = wave; x < n; x += nwaves) {
+          if (ld_agent(&a.lvl[x]) != rnd - 1) continue;
+          const uint32_t dx = ld_agent(&a.d[x]);
+          if (dx >= W::kInf) continue;
+          const uint4 row = ldg(&a.rows[x]);
+          for (uint32_t p = row.x + l; p < row.z; p += 64) {
+            const uint64_t ed = ldg(&a.edges[p]);
+            const uint32_t y = static_cast<uint32_t>(ed);
+            uint32_t cand;
+            if (ld_agent(&a.lvl[y]) == kNone && W::add(dx, static_cast<uint32_t>(ed >> 32), &cand) &&
+                cand == ld_agent(&a.d[y]))
+              g_min(&a.parent[y], static_cast<unsigned long long>(ldg(&a.perm[p])) << 32 | x);
+          }
+        }
+      }
+      alive = grid_sync(c, size, rank, s_bar, [] {});
+      if (!alive) break;
+      for (uint32_t it = 0, iters = (n + nthreads - 1) / nthreads; it < iters; ++it) {
+        const uint32_t y = it * nthreads + tid;
+        bool grew = false;
+        if (y < n && ld_agent(&a.lvl[y]) == kNone && ld_agent(&a.parent[y]) != kNoParent) {
+          st_agent(&a.lvl[y], rnd);
+          grew = true;
+        }
+        const uint32_t cnt = static_cast<uint32_t>(__popcll(__ballot(grew)));
+        if (cnt && lane() == 0) g_add(&c->scount, cnt);
+      }
+      alive = grid_sync(c, size, rank, s_bar, [&] { adjoint_leader_count(c); });
+    }
     if (!alive) break;
     // 2. children per vertex; a reached vertex other than s must have a parent
     for (uint32_t y = tid; y < n; y += nthreads) {

@@ -9,6 +9,7 @@
 #include "sssp.h"
 #include "sssp_internal.h"
 
+
 // Working set of one extra concurrent group (the first group's lives in Params).
 struct GroupMem {
   void* tbuf[2] = {nullptr, nullptr};
@@ -33,6 +34,7 @@ struct sssp_handle {
   int grid = 0;         // workgroups of a launch of one source at a time (kWG threads each)
   int grid_groups = 0;  // workgroups of a launch of concurrent sources (kWGGroups threads, two per CU; 0: none)
   int cus = 0;
+  int wallclock_khz = 100000;  // device wall-clock rate (wall_clock64 ticks per millisecond)
   int occupancy = 0;
   int occupancy_groups = 0;
   sssp_tuning tuning{};
@@ -59,23 +61,43 @@ struct sssp_handle {
   uint32_t* adj_d = nullptr;
   unsigned long long* adj_parent = nullptr;
   uint32_t* adj_cnt = nullptr;
+  uint32_t* adj_lvl = nullptr;
   double* adj_g = nullptr;
   double* adj_grad64 = nullptr;
   struct AdjMem {  // adjoint working set of an extra concurrent group
     uint32_t* d = nullptr;
     unsigned long long* parent = nullptr;
     uint32_t* cnt = nullptr;
+    uint32_t* lvl = nullptr;
     double* g = nullptr;
   };
   std::vector<AdjMem> adj_extra;
   sssp::AdjParams* adj_params_dev = nullptr;  // [kMaxGroups]
-  unsigned long long* aux = nullptr;  // [2] small device scratch for status reads
+  sssp::AdjParams adj_host[sssp::kMaxGroups];  // host copy of the groups' adjoint launch parameters
+  unsigned long long* aux = nullptr;       // [2] small device scratch for status reads
+  unsigned long long* aux_host = nullptr;  // [2] pinned host copy of aux
   int adj_grid = 0;
 };
 
 namespace {
 
 constexpr uint32_t kDefaultInlineEdges = 4096;
+constexpr int32_t kDefaultWaitLimitMs = 30000;
+
+// The tile schedule of the handle's tuning (0 fields: the defaults) in its launch parameters.
+void apply_tile_tuning(sssp_handle* h) {
+  const sssp_tuning& t = h->tuning;
+  h->p.inline_edges = t.inline_edges > 0 ? static_cast<uint32_t>(t.inline_edges) : kDefaultInlineEdges;
+  h->p.hub_edges = t.hub_edges > 0 ? static_cast<uint32_t>(t.hub_edges) : sssp::kHub;
+  h->p.chunk_entries = static_cast<uint32_t>(t.chunk_entries);
+  h->p.inline_entries = static_cast<uint32_t>(t.inline_entries);
+}
+
+// A barrier wait that sees no progress for longer than this aborts the schedule (wall-clock ticks).
+unsigned long long wait_ticks(const sssp_handle* h) {
+  const int32_t ms = h->tuning.wait_limit_ms > 0 ? h->tuning.wait_limit_ms : kDefaultWaitLimitMs;
+  return static_cast<unsigned long long>(ms) * static_cast<unsigned long long>(h->wallclock_khz);
+}
 
 sssp_status from_hip(hipError_t e) {
   if (e == hipSuccess) return SSSP_OK;
@@ -104,7 +126,7 @@ void free_group(GroupMem& gm) {
 }
 
 void free_adj_group(sssp_handle::AdjMem& am) {
-  void* mem[] = {am.d, am.parent, am.cnt, am.g};
+  void* mem[] = {am.d, am.parent, am.cnt, am.lvl, am.g};
   for (void* q : mem)
     if (q) (void)hipFree(q);
   am = sssp_handle::AdjMem{};
@@ -112,12 +134,13 @@ void free_adj_group(sssp_handle::AdjMem& am) {
 
 // The first group's adjoint working set (all of it or none of it).
 void free_adj(sssp_handle* h) {
-  void* mem[] = {h->adj_d, h->adj_parent, h->adj_cnt, h->adj_g, h->adj_grad64, h->adj_params_dev};
+  void* mem[] = {h->adj_d, h->adj_parent, h->adj_cnt, h->adj_lvl, h->adj_g, h->adj_grad64, h->adj_params_dev};
   for (void* q : mem)
     if (q) (void)hipFree(q);
   h->adj_d = nullptr;
   h->adj_parent = nullptr;
   h->adj_cnt = nullptr;
+  h->adj_lvl = nullptr;
   h->adj_g = nullptr;
   h->adj_grad64 = nullptr;
   h->adj_params_dev = nullptr;
@@ -140,6 +163,7 @@ void free_handle(sssp_handle* h) {
     if (q) (void)hipFree(q);
   if (h->src_host) (void)hipHostFree(h->src_host);
   if (h->ctl_host) (void)hipHostFree(h->ctl_host);
+  if (h->aux_host) (void)hipHostFree(h->aux_host);
   delete h;
 }
 
@@ -319,6 +343,11 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   SSSP_TRY(hipGetDeviceProperties(&prop, h->device));
   if (!prop.cooperativeLaunch) return SSSP_ERR_UNSUPPORTED;
   h->cus = prop.multiProcessorCount;
+  {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device) == hipSuccess && khz > 0)
+      h->wallclock_khz = khz;
+  }
   SSSP_TRY(sssp::solver_occupancy(g->wtype, sssp::kWG, &h->occupancy));
   SSSP_TRY(sssp::solver_occupancy(g->wtype, sssp::kWGGroups, &h->occupancy_groups));
 
@@ -375,11 +404,12 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   SSSP_TRY(dalloc(&p.bstamp, un));
   SSSP_TRY(dalloc(&p.fstamp, un));
   SSSP_TRY(dalloc(&p.ovf_at, un));
-  // each vertex appears at most once in a phase's list, so the pieces of its
-  // high-degree vertices number at most m / kPieceMin + m / kHub (pieces of the smaller workgroup)
-  p.hub_cap = static_cast<uint32_t>(um / sssp::kPieceMin + um / sssp::kHub + 16);
+  // each vertex appears at most once in a phase's list, so the pieces of its high-degree
+  // vertices number at most m / kPieceMin + m / kHubMin (pieces of the smaller workgroup,
+  // the smallest hub threshold a tuning may set)
+  p.hub_cap = static_cast<uint32_t>(um / sssp::kPieceMin + um / sssp::kHubMin + 16);
   SSSP_TRY(dalloc(&p.hub, 2 * static_cast<size_t>(p.hub_cap)));
-  p.inline_edges = h->tuning.inline_edges > 0 ? static_cast<uint32_t>(h->tuning.inline_edges) : kDefaultInlineEdges;
+  apply_tile_tuning(h);
   SSSP_TRY(dalloc(&p.front[0], un));
   SSSP_TRY(dalloc(&p.front[1], un));
   SSSP_TRY(dalloc(&p.slist, un));
@@ -398,7 +428,7 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   SSSP_TRY(hipMemsetAsync(p.fstamp, 0, un * sizeof(uint32_t), stream));
   SSSP_TRY(hipMemsetAsync(p.ovf_at, 0, un * sizeof(uint32_t), stream));
   SSSP_TRY(hipMemsetAsync(h->ctls, 0, sizeof(sssp::Ctl) * sssp::kMaxGroups, stream));
-  SSSP_TRY(sssp::launch_ctl_reset(h->ctls, sssp::kMaxGroups, 1, nullptr, 0, stream));
+  SSSP_TRY(sssp::launch_ctl_reset(h->ctls, sssp::kMaxGroups, 1, nullptr, 0, wait_ticks(h), stream));
 
   // 4. relabel by in-degree, then the light/heavy split (A_L, A_H)
   uint32_t* vid = nullptr;
@@ -416,6 +446,13 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   if (be == hipSuccess) be = dalloc(&h->inv, un);
   if (be == hipSuccess) be = sssp::launch_inverse(vid, n, h->inv, stream);
   if (be == hipSuccess) be = dalloc(&h->aux, 2);
+  if (be == hipSuccess)
+    be = hipHostMalloc(reinterpret_cast<void**>(&h->aux_host), 2 * sizeof(unsigned long long), hipHostMallocDefault);
+  if (be == hipSuccess) {
+    int occ = 0;
+    be = sssp::adjoint_occupancy(&occ);
+    h->adj_grid = occ >= 1 ? h->cus : 0;
+  }
   if (be == hipSuccess) be = hipStreamSynchronize(stream);
   (void)hipFree(build);
   SSSP_TRY(be);
@@ -463,7 +500,7 @@ sssp_status enqueue_solve(sssp_handle* h, const int32_t* sources_dev, int32_t k,
     reset_epochs = 1;
     h->stamps_dirty = false;
   }
-  SSSP_TRY(sssp::launch_ctl_reset(h->ctls, groups, reset_epochs, h->trace, h->trace_cap, s));
+  SSSP_TRY(sssp::launch_ctl_reset(h->ctls, groups, reset_epochs, h->trace, h->trace_cap, wait_ticks(h), s));
   // concurrent sources run on two smaller workgroups per CU; one source (or one
   // multi-source row) on one full workgroup per CU
   const bool small = small_workgroups(h, groups, multi);
@@ -507,6 +544,56 @@ sssp_status read_status(sssp_handle* h, hipStream_t s) {
   if (bad) return SSSP_ERR_INVALID_ARGUMENT;
   if (ovf) return SSSP_ERR_OVERFLOW;
   h->solved = true;
+  return SSSP_OK;
+}
+
+// Launch the adjoint over `groups` groups whose working sets are already in
+// h->adj_host (d, parent, cnt, lvl, g) and read its outcome. params_dev: device
+// room for the groups' launch parameters; grad64: the fp64 dL/dw accumulator
+// [m]; sources: DEVICE [k] (checked on the device). Allocates nothing.
+sssp_status run_adjoint(sssp_handle* h, uint32_t groups, sssp::AdjParams* params_dev, double* grad64,
+                        const int32_t* sources, int32_t k, const void* dist, const float* grad_dist, float* grad_w,
+                        hipStream_t s) {
+  for (uint32_t gi = 0; gi < groups; ++gi) {
+    sssp::AdjParams& a = h->adj_host[gi];
+    a.n = static_cast<uint32_t>(h->n);
+    a.m = static_cast<uint64_t>(h->m);
+    a.vid = h->p.vid;
+    a.inv = h->inv;
+    a.rows = h->p.rows;
+    a.edges = h->p.edges;
+    a.perm = h->perm;
+    a.grad64 = grad64;
+    a.ctl = h->ctls + gi;
+    a.next_source = &h->ctls[0].next_source;
+    // the level lists reuse the frontier buffers of the group's solver working set
+    a.front[0] = gi == 0 ? h->p.front[0] : h->extra[gi - 1].front[0];
+    a.front[1] = gi == 0 ? h->p.front[1] : h->extra[gi - 1].front[1];
+  }
+  SSSP_TRY(hipMemcpyAsync(params_dev, h->adj_host, sizeof(sssp::AdjParams) * groups, hipMemcpyHostToDevice, s));
+  SSSP_TRY(sssp::launch_fill(reinterpret_cast<uint32_t*>(h->aux), 4, 0u, s));
+  SSSP_TRY(sssp::launch_count_reached(static_cast<const uint32_t*>(dist), static_cast<uint32_t>(h->n), k, h->wtype,
+                                      h->aux, s));
+  SSSP_TRY(sssp::launch_ctl_reset(h->ctls, groups, 0, nullptr, 0, wait_ticks(h), s));
+  SSSP_TRY(sssp::launch_adjoint(params_dev, groups, sources, k, static_cast<const uint32_t*>(dist), grad_dist, grad_w,
+                                static_cast<uint64_t>(h->m), grad64, h->adj_grid, s));
+  SSSP_TRY(hipMemcpyAsync(h->ctl_host, h->ctls, sizeof(sssp::Ctl) * groups, hipMemcpyDeviceToHost, s));
+  SSSP_TRY(hipMemcpyAsync(h->aux_host, h->aux, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  SSSP_TRY(hipStreamSynchronize(s));
+  const unsigned long long reached = *h->aux_host;
+  bool abort = false, bad = false, bad_source = false;
+  unsigned long long released = 0;
+  for (uint32_t gi = 0; gi < groups; ++gi) {
+    const sssp::Ctl& c = h->ctl_host[gi];
+    abort |= c.abort != 0;
+    bad |= c.ovf_real != 0;
+    bad_source |= c.bad_source != 0;
+    released += c.adj_released;
+  }
+  if (abort) return SSSP_ERR_DEVICE;
+  if (bad_source) return SSSP_ERR_INVALID_ARGUMENT;
+  // an infeasible edge, a reached vertex without a tight in-edge, d(s) != 0, or parents that never lead to s
+  if (bad || released != reached) return SSSP_ERR_INVALID_ARGUMENT;
   return SSSP_OK;
 }
 
@@ -597,18 +684,16 @@ sssp_status sssp_solve_status(sssp_handle* h, void* stream) {
 sssp_status sssp_backward(sssp_handle* h, const int32_t* sources, int32_t k, const void* dist,
                           const float* grad_dist, float* grad_w, void* stream) {
   if (!h || !sources || k < 1 || !dist || !grad_dist || !grad_w) return SSSP_ERR_INVALID_ARGUMENT;
-  if (h->wtype != SSSP_WEIGHT_F32) return SSSP_ERR_UNSUPPORTED;
+  if (h->wtype != SSSP_WEIGHT_F32 || h->adj_grid < 1) return SSSP_ERR_UNSUPPORTED;
   if (!h->solved) return SSSP_ERR_NO_FORWARD;
   hipStream_t s = static_cast<hipStream_t>(stream);
   SSSP_TRY(hipSetDevice(h->device));
   const size_t un = static_cast<size_t>(h->n), um = static_cast<size_t>(h->m);
   if (!h->adj_d) {  // allocated whole or not at all (a later call tests adj_d only)
-    int occ = 0;
-    SSSP_TRY(sssp::adjoint_occupancy(&occ));
-    if (occ < 1) return SSSP_ERR_UNSUPPORTED;
     hipError_t e = dalloc(&h->adj_d, un);
     if (e == hipSuccess) e = dalloc(&h->adj_parent, un);
     if (e == hipSuccess) e = dalloc(&h->adj_cnt, un);
+    if (e == hipSuccess) e = dalloc(&h->adj_lvl, un);
     if (e == hipSuccess) e = dalloc(&h->adj_g, un);
     if (e == hipSuccess) e = dalloc(&h->adj_grad64, um);
     if (e == hipSuccess) e = dalloc(&h->adj_params_dev, sssp::kMaxGroups);
@@ -616,7 +701,6 @@ sssp_status sssp_backward(sssp_handle* h, const int32_t* sources, int32_t k, con
       free_adj(h);
       return from_hip(e);
     }
-    h->adj_grid = h->cus;
   }
   // sources share the launch as in the forward solve: one group per concurrent source
   const uint32_t groups = h->adj_grid % static_cast<int>(h->groups) == 0 ? h->groups : 1u;
@@ -626,6 +710,7 @@ sssp_status sssp_backward(sssp_handle* h, const int32_t* sources, int32_t k, con
     hipError_t e = dalloc(&am.d, un);
     if (e == hipSuccess) e = dalloc(&am.parent, un);
     if (e == hipSuccess) e = dalloc(&am.cnt, un);
+    if (e == hipSuccess) e = dalloc(&am.lvl, un);
     if (e == hipSuccess) e = dalloc(&am.g, un);
     if (e != hipSuccess) {  // a partly allocated working set is not kept
       free_adj_group(am);
@@ -635,59 +720,24 @@ sssp_status sssp_backward(sssp_handle* h, const int32_t* sources, int32_t k, con
   }
   const sssp_status st = stage_sources(h, sources, k, s);
   if (st != SSSP_OK) return st;
-  std::vector<sssp::AdjParams> all(groups);
   for (uint32_t gi = 0; gi < groups; ++gi) {
-    sssp::AdjParams& a = all[gi];
-    a.n = static_cast<uint32_t>(h->n);
-    a.m = static_cast<uint64_t>(h->m);
-    a.vid = h->p.vid;
-    a.inv = h->inv;
-    a.rows = h->p.rows;
-    a.edges = h->p.edges;
-    a.perm = h->perm;
-    a.grad64 = h->adj_grad64;
-    a.ctl = h->ctls + gi;
-    a.next_source = &h->ctls[0].next_source;
+    sssp::AdjParams& a = h->adj_host[gi];
     if (gi == 0) {
       a.d = h->adj_d;
       a.parent = h->adj_parent;
       a.cnt = h->adj_cnt;
+      a.lvl = h->adj_lvl;
       a.g = h->adj_g;
-      a.front[0] = h->p.front[0];
-      a.front[1] = h->p.front[1];
-    } else {  // the level lists reuse the frontier buffers of the group's solver working set
+    } else {
       const sssp_handle::AdjMem& am = h->adj_extra[gi - 1];
       a.d = am.d;
       a.parent = am.parent;
       a.cnt = am.cnt;
+      a.lvl = am.lvl;
       a.g = am.g;
-      a.front[0] = h->extra[gi - 1].front[0];
-      a.front[1] = h->extra[gi - 1].front[1];
     }
   }
-  SSSP_TRY(hipMemcpyAsync(h->adj_params_dev, all.data(), sizeof(sssp::AdjParams) * groups, hipMemcpyHostToDevice, s));
-  SSSP_TRY(hipMemsetAsync(h->aux, 0, 2 * sizeof(unsigned long long), s));
-  SSSP_TRY(sssp::launch_count_reached(static_cast<const uint32_t*>(dist), static_cast<uint32_t>(h->n), k, h->wtype,
-                                      h->aux, s));
-  SSSP_TRY(sssp::launch_ctl_reset(h->ctls, groups, 0, nullptr, 0, s));
-  SSSP_TRY(sssp::launch_adjoint(h->adj_params_dev, groups, h->src_dev, k, static_cast<const uint32_t*>(dist), grad_dist,
-                                grad_w, static_cast<uint64_t>(h->m), h->adj_grad64, h->adj_grid, s));
-  unsigned long long reached = 0;
-  SSSP_TRY(hipMemcpyAsync(h->ctl_host, h->ctls, sizeof(sssp::Ctl) * groups, hipMemcpyDeviceToHost, s));
-  SSSP_TRY(hipMemcpyAsync(&reached, h->aux, sizeof(reached), hipMemcpyDeviceToHost, s));
-  SSSP_TRY(hipStreamSynchronize(s));
-  bool abort = false, bad = false;
-  unsigned long long released = 0;
-  for (uint32_t gi = 0; gi < groups; ++gi) {
-    const sssp::Ctl& c = h->ctl_host[gi];
-    abort |= c.abort != 0;
-    bad |= c.ovf_real != 0;
-    released += c.adj_released;
-  }
-  if (abort) return SSSP_ERR_DEVICE;
-  // a reached vertex without a tight in-edge, or parents that never lead to the source
-  if (bad || released != reached) return SSSP_ERR_INVALID_ARGUMENT;
-  return SSSP_OK;
+  return run_adjoint(h, groups, h->adj_params_dev, h->adj_grad64, h->src_dev, k, dist, grad_dist, grad_w, s);
 }
 
 sssp_status sssp_set_weights(sssp_handle* h, const void* weights, void* stream) {
@@ -765,8 +815,17 @@ sssp_status sssp_last_stats(const sssp_handle* h, sssp_stats* out) {
 
 sssp_status sssp_set_tuning(sssp_handle* h, const sssp_tuning* t) {
   if (!h || !t) return SSSP_ERR_INVALID_ARGUMENT;
-  if (t->workgroups_per_cu < 0 || t->ring_buckets < 0 || t->inline_edges < 0 || t->concurrent_sources < 0)
+  if (t->workgroups_per_cu < 0 || t->ring_buckets < 0 || t->inline_edges < 0 || t->concurrent_sources < 0 ||
+      t->wait_limit_ms < 0 || t->hub_edges < 0 || t->chunk_entries < 0 || t->inline_entries < 0)
     return SSSP_ERR_INVALID_ARGUMENT;
+  const auto pow2 = [](int32_t x) { return (x & (x - 1)) == 0; };
+  if (t->hub_edges != 0 && (t->hub_edges < static_cast<int32_t>(sssp::kHubMin) || t->hub_edges > 65536 ||
+                            !pow2(t->hub_edges)))
+    return SSSP_ERR_INVALID_ARGUMENT;
+  if (t->chunk_entries != 0 && (t->chunk_entries < static_cast<int32_t>(sssp::kMinChunk) ||
+                                t->chunk_entries > static_cast<int32_t>(sssp::kChunk) || !pow2(t->chunk_entries)))
+    return SSSP_ERR_INVALID_ARGUMENT;
+  if (t->inline_entries > static_cast<int32_t>(sssp::kChunk)) return SSSP_ERR_INVALID_ARGUMENT;
   if (t->ring_buckets != 0 && t->ring_buckets != static_cast<int32_t>(h->p.ring))
     return SSSP_ERR_UNSUPPORTED;  // the ring is sized at create time
   SSSP_TRY(hipSetDevice(h->device));
@@ -793,8 +852,27 @@ sssp_status sssp_set_tuning(sssp_handle* h, const sssp_tuning* t) {
     return st;
   }
   h->groups = groups;
-  h->p.inline_edges = t->inline_edges > 0 ? static_cast<uint32_t>(t->inline_edges) : kDefaultInlineEdges;
+  apply_tile_tuning(h);
   return upload_params(h);
+}
+
+sssp_status sssp_get_tuning(const sssp_handle* h, sssp_tuning* out) {
+  if (!h || !out) return SSSP_ERR_INVALID_ARGUMENT;
+  sssp_tuning t{};
+  const uint32_t groups = h->groups;
+  const bool small = small_workgroups(h, groups, 0);
+  const uint32_t size = static_cast<uint32_t>(small ? h->grid_groups : h->grid) / groups;
+  t.workgroups_per_cu = small ? 2 : 1;
+  t.ring_buckets = static_cast<int32_t>(h->p.ring);
+  t.inline_edges = static_cast<int32_t>(h->p.inline_edges);
+  t.concurrent_sources = static_cast<int32_t>(groups);
+  t.wait_limit_ms = h->tuning.wait_limit_ms > 0 ? h->tuning.wait_limit_ms : kDefaultWaitLimitMs;
+  t.hub_edges = static_cast<int32_t>(h->p.hub_edges);
+  const uint32_t chunk = h->p.chunk_entries ? h->p.chunk_entries : (size >= 128 ? sssp::kChunk / 2 : sssp::kChunk);
+  t.chunk_entries = static_cast<int32_t>(chunk);
+  t.inline_entries = static_cast<int32_t>(h->p.inline_entries ? h->p.inline_entries : chunk);
+  *out = t;
+  return SSSP_OK;
 }
 
 sssp_status sssp_set_trace(sssp_handle* h, uint64_t* device_buffer, int64_t capacity) {

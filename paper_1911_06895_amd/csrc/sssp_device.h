@@ -174,8 +174,6 @@ struct WeightF64 {
 
 // ------------------------------------------------------------------ barrier
 
-constexpr unsigned long long kWaitLimitTicks = 3000000000ull;  // 30 s of the 100 MHz wall clock
-
 // Every wave's device-scope stores and atomics complete (are acknowledged by
 // the device-coherent level) before its workgroup arrives: s_waitcnt with all
 // counters zero.
@@ -207,17 +205,22 @@ __device__ inline void record_trace(Ctl* c, unsigned long long* trace, uint32_t 
 // before releasing the others by advancing the generation word. `b` (LDS) is
 // this workgroup's copy of the generation (every workgroup passes every
 // barrier, so no load of the word is needed before arriving) and of the trace
-// buffer pointer, both loaded by init_barrier at kernel start. Returns false
-// when the schedule was aborted (a wait ran past kWaitLimitTicks).
+// buffer pointer and of the wait limit, loaded by init_barrier at kernel
+// start. Returns false when the schedule was aborted: by another workgroup, or
+// because a wait saw neither the release nor a new heartbeat of the leader
+// (which it bumps at every step it runs alone inside the barrier) for longer
+// than the wait limit.
 struct BarrierState {
   uint32_t gen;
   unsigned long long* trace;
+  unsigned long long wait_ticks;
 };
 
 __device__ inline void init_barrier(Ctl* c, BarrierState& b) {
   if (threadIdx.x == 0) {
     b.gen = ld_agent(&c->bar_gen);
     b.trace = ldg(&c->trace);
+    b.wait_ticks = ldg(&c->wait_ticks);
   }
   __syncthreads();
 }
@@ -244,13 +247,19 @@ __device__ bool grid_sync(Ctl* c, uint32_t size, uint32_t rank, BarrierState& b,
     s_is_leader = last ? 1u : 0u;
     uint32_t ok = 1;
     if (!last) {
-      // the generation and the abort flag are loaded together: one round trip per poll
-      const unsigned long long t0 = wall_clock64();
+      // the generation, the abort flag and the heartbeat are loaded together: one round trip per poll
+      unsigned long long t0 = wall_clock64();
+      uint32_t beat = ld_agent(&c->heartbeat);
       for (;;) {
         const uint32_t g_now = ld_agent(&c->bar_gen);
         const uint32_t abort_now = ld_agent(&c->abort);
+        const uint32_t beat_now = ld_agent(&c->heartbeat);
         if (g_now != gen) break;
-        if (abort_now != 0u || wall_clock64() - t0 > kWaitLimitTicks) {
+        if (beat_now != beat) {  // the leader is still making progress
+          beat = beat_now;
+          t0 = wall_clock64();
+        }
+        if (abort_now != 0u || wall_clock64() - t0 > b.wait_ticks) {
           st_agent(&c->abort, 1u);
           ok = 0;
           break;

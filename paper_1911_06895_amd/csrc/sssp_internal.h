@@ -9,11 +9,12 @@ namespace sssp {
 constexpr int kWG = 1024;              // larger solver workgroup (on request; the adjoint's): 16 wave64s, one per CU
 constexpr int kWGGroups = 512;         // default solver workgroup: 8 wave64s, two per CU
 constexpr int kAuxWG = 256;            // workgroup of the create-time kernels
-constexpr uint32_t kChunk = 512;       // most list entries a workgroup expands at a time
+constexpr uint32_t kChunk = 512;       // most list entries a workgroup expands at a time (LDS tile bound)
 constexpr uint32_t kMinChunk = 32;     // fewest list entries per claimed chunk
 constexpr uint32_t kILP = 4;           // edges per lane in flight
 constexpr uint32_t kPieceMin = kWGGroups * kILP;  // edges of the smaller hub piece (one round of a workgroup)
-constexpr uint32_t kHub = 1024;        // a vertex with at least this many edges in a phase goes to the hub step
+constexpr uint32_t kHub = 1024;        // default: a vertex with at least this many edges in a phase goes to the hub step
+constexpr uint32_t kHubMin = 256;      // smallest hub threshold a tuning may set (sizes the hub queues)
 constexpr uint32_t kBarGroups = 8;     // arrival sub-counters of the grid barrier
 constexpr uint32_t kRingMax = 64;      // near-bucket ring capacity
 constexpr uint32_t kDegClasses = 65536;  // in-degree classes of the relabelling (the last one open-ended)
@@ -88,6 +89,7 @@ struct Ctl {
   alignas(128) uint32_t bar_arrive;
   alignas(128) uint32_t bar_gen;  // polled by the waiting workgroups
   uint32_t abort;
+  uint32_t heartbeat;     // bumped by the leader at each step it runs alone inside a barrier
   uint32_t source_index;  // source (row) the group is solving, kNone when the batch is done
   alignas(128) uint32_t chunk_next;  // dynamic chunk counter of the current step
   alignas(128) uint32_t hub_count;   // hub pieces queued by the current phase
@@ -116,13 +118,16 @@ struct Ctl {
   alignas(128) uint32_t scount;
   alignas(128) uint32_t farcount[2];
   alignas(128) uint32_t ovf_seen;  // some candidate did not fit the distance type
-  uint32_t ovf_real;     // a reachable vertex has an unrepresentable distance
+  uint32_t ovf_real;     // a reachable vertex has an unrepresentable distance (adjoint: dist is not a
+                         // shortest-path vector)
   uint32_t trace_len;    // step records written (may exceed trace_cap)
   unsigned long long* trace;  // optional step trace: 4 words per record
   unsigned long long tr_edges, tr_impr;  // edges scanned and improvements of the running step (traced runs)
   uint32_t trace_cap;
   uint32_t next_source;  // batch-wide source counter (used in the first group's block only)
   uint32_t bad_source;   // a source index outside [0, n) was given
+  uint32_t hub_full;     // a hub queue ran out of room (the schedule was aborted)
+  unsigned long long wait_ticks;  // a barrier wait without progress longer than this aborts the schedule
   alignas(128) uint32_t bincount[kRingMax][32];  // ring-slot sizes, one per 128-byte line ([slot][0])
   // statistics (summed over sources)
   alignas(128) unsigned long long sources, buckets, light_phases, heavy_phases, far_phases;
@@ -155,6 +160,9 @@ struct Params {
   uint64_t* hub;          // [2][hub_cap] pieces (vertex | piece index << 32), two alternating queues
   uint32_t hub_cap;
   uint32_t inline_edges;  // steps with at most this many edges run on the leader workgroup alone
+  uint32_t hub_edges;     // a vertex with at least this many edges in a phase is cut into hub pieces
+  uint32_t chunk_entries; // list entries per claimed chunk at most (power of two <= kChunk; 0: by group size)
+  uint32_t inline_entries;  // list entries of a step the leader runs alone at most (<= kChunk; 0: the chunk cap)
   uint32_t groups;        // workgroup groups of the launch, each solving its own sources
   uint32_t no_heavy;      // every weight is <= delta: A_H is empty, no S and no heavy phases
   Ctl* ctl;               // this group's control block
@@ -173,6 +181,7 @@ struct AdjParams {
   uint32_t* d;                // [n] distances
   unsigned long long* parent; // [n] (caller edge index << 32 | parent solver id), all ones = none
   uint32_t* cnt;              // [n] children still to report
+  uint32_t* lvl;              // [n] round in which a vertex got its parent (kNone: unresolved)
   double* g;                  // [n] accumulated coefficients
   uint32_t* front[2];         // [n] level lists
   double* grad64;             // [m] dL/dw in caller edge order (shared by every group)
@@ -204,7 +213,7 @@ hipError_t launch_relabel_and_split(const int64_t* row_ptr, const int32_t* col, 
 hipError_t solver_occupancy(int wtype, int wg, int* blocks_per_cu);
 hipError_t launch_pack_rows(const uint32_t* off, const uint32_t* split, int64_t n, uint4* rows, hipStream_t s);
 hipError_t launch_ctl_reset(Ctl* c, uint32_t groups, int reset_epochs, unsigned long long* trace, uint32_t trace_cap,
-                            hipStream_t s);
+                            unsigned long long wait_ticks, hipStream_t s);
 hipError_t launch_fill(uint32_t* p, size_t count, uint32_t value, hipStream_t s);
 // `params` is a device array of one Params per group; grid must be a multiple of
 // groups; wg (kWG or kWGGroups) is the workgroup size. multi = 0: row r of dist

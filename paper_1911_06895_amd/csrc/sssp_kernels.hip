@@ -550,7 +550,7 @@ __device__ inline uint32_t claim_next(uint32_t* counter, uint32_t prev, uint32_t
   return *s_claim;
 }
 
-// Queue the pieces of one high-degree vertex (kHub or more edges in this phase).
+// Queue the pieces of one high-degree vertex (hub_edges or more edges in this phase).
 template <class W>
 __device__ inline void queue_hub(uint32_t u, uint32_t deg) {
   const Lds<W> L = lds<W>();
@@ -558,17 +558,27 @@ __device__ inline void queue_hub(uint32_t u, uint32_t deg) {
   const uint32_t pieces = (deg + W::kPiece - 1) / W::kPiece;
   uint64_t* queue = p.hub + static_cast<size_t>(1u - L.s.hub_in) * p.hub_cap;
   const uint32_t base = g_add(&p.ctl->hub_count, pieces);
+  if (base + pieces > p.hub_cap) {  // cannot happen within the capacity bound; never drop work silently
+    st_agent(&p.ctl->hub_full, 1u);
+    st_agent(&p.ctl->abort, 1u);
+  }
   for (uint32_t k = 0; k < pieces && base + k < p.hub_cap; ++k)
     st_agent(&queue[base + k], static_cast<uint64_t>(u) | (static_cast<uint64_t>(k) << 32));
 }
 
 // A group of at least this many workgroups (most of the device) hands hub
-// pieces over between light phases, claims chunks of at most kChunk / 2
-// entries (more chunks per workgroup: better balance over many workgroups)
-// and runs steps of at most kChunk / 2 entries on the leader alone; smaller
-// groups use kChunk for both.
+// pieces over between light phases, and by default claims chunks of at most
+// kChunk / 2 entries (more chunks per workgroup: better balance over many
+// workgroups) and runs steps of at most kChunk / 2 entries on the leader
+// alone; smaller groups use kChunk for both. A tuning may set either limit.
 constexpr uint32_t kHandOverMinGroup = 128;  // workgroups
-__device__ inline uint32_t chunk_cap(uint32_t size) { return size >= kHandOverMinGroup ? kChunk / 2 : kChunk; }
+__device__ inline uint32_t chunk_cap(const Params& p, uint32_t size) {
+  if (p.chunk_entries) return p.chunk_entries;
+  return size >= kHandOverMinGroup ? kChunk / 2 : kChunk;
+}
+__device__ inline uint32_t inline_cap(const Params& p, uint32_t size) {
+  return p.inline_entries ? p.inline_entries : chunk_cap(p, size);
+}
 
 // List entries per claimed chunk: enough chunks for about four per workgroup.
 // Chunk sizes are powers of two (the edge-to-entry search relies on it).
@@ -606,8 +616,8 @@ __device__ void hub_pieces(typename W::T* t, bool light);
 // min-merge into t (the paper's fusion of the Hadamard product into vxm).
 // Edges are balanced over the workgroup: the degrees of kChunk list entries
 // are prefix-summed in LDS and the lanes walk the concatenated edge ranges, so
-// consecutive lanes read consecutive edges of a row. Vertices with kHub or
-// more edges are queued as pieces for a grid-wide hub step instead.
+// consecutive lanes read consecutive edges of a row. Vertices with hub_edges
+// or more edges are queued as pieces for a grid-wide hub step instead.
 template <class W, bool kLight>
 __device__ __attribute__((always_inline)) void phase(typename W::T* t, bool solo, bool preloaded = false,
                                                      Entry<typename W::T> pre = Entry<typename W::T>{}) {
@@ -626,7 +636,7 @@ __device__ __attribute__((always_inline)) void phase(typename W::T* t, bool solo
   const uint32_t count = s.in_count;
   const uint64_t near_end = static_cast<uint64_t>(s.bucket) + p.ring;  // no wrap near 2^32
   const uint32_t size = grp_size(p);
-  const uint32_t chunk = solo ? solo_chunk(count) : chunk_for(count, size, chunk_cap(size));
+  const uint32_t chunk = solo ? solo_chunk(count) : chunk_for(count, size, chunk_cap(p, size));
   const uint32_t nchunks = (count + chunk - 1) / chunk;
   if constexpr (kLight) {
     if (!solo && s.hub_backlog > 0) hub_pieces<W>(t, true);  // the previous light phase's pieces
@@ -661,7 +671,7 @@ __device__ __attribute__((always_inline)) void phase(typename W::T* t, bool solo
       stage_push<W>(to_s, kSlotS, u);
       stage_room<W>();
     }
-    if (!solo && deg >= kHub) {
+    if (!solo && deg >= p.hub_edges) {
       queue_hub<W>(u, deg);
       count_add(kLight ? &L.st.light_edges : &L.st.heavy_edges, deg);
       count_add(&L.st.step_edges, deg);
@@ -1061,7 +1071,7 @@ __device__ void after_step() {
   __syncthreads();
 }
 
-// Edges a light or heavy step would scan (its list has at most kChunk entries);
+// Edges a light or heavy step would scan (its list has at most inline_cap <= kChunk entries);
 // each thread keeps its entry for the phase that may follow on this workgroup.
 template <bool kLight, class W>
 __device__ uint32_t step_edges(const typename W::T* t, uint32_t* s_wsum, Entry<typename W::T>* e) {
@@ -1092,13 +1102,14 @@ __device__ void lead(typename W::T* t, bool schedule_first) {
   if (schedule_first) after_step<W>();
   for (;;) {  // *s is the current schedule (set by leader_start or after_step)
     const bool light = s->action == kActLight;
-    if (!(light || s->action == kActHeavy) || s->in_count > chunk_cap(grp_size(p)) || s->hub_backlog > 0) break;
+    if (!(light || s->action == kActHeavy) || s->in_count > inline_cap(p, grp_size(p)) || s->hub_backlog > 0) break;
     Entry<typename W::T> e{};
     const uint32_t edges = light ? step_edges<true, W>(t, s_wsum, &e) : step_edges<false, W>(t, s_wsum, &e);
     if (edges > p.inline_edges) break;
     drain_stores();  // the counter resets of after_step land before this step's appends
     __syncthreads();
     if (threadIdx.x == 0) record_trace(p.ctl, L.bar.trace, 0x80u);
+    if (threadIdx.x == 0) g_add(&p.ctl->heartbeat, 1u);  // the waiting workgroups see progress
     if (light) phase_solo<W, true>(t, e);
     else phase_solo<W, false>(t, e);
     trace_step_counts<W>(p.ctl);
@@ -1205,7 +1216,7 @@ __global__ __launch_bounds__(W::kWG, 4) void solver_kernel(const Params* __restr
 // counters, the abort flag and the batch's source counter (and the tags when
 // the de-duplication stamps were just cleared). Only the first group traces.
 __global__ void ctl_reset_kernel(Ctl* ctls, uint32_t groups, int reset_epochs, unsigned long long* trace,
-                                 uint32_t trace_cap) {
+                                 uint32_t trace_cap, unsigned long long wait_ticks) {
   const uint32_t g = threadIdx.x;
   if (g >= groups) return;
   Ctl* c = ctls + g;
@@ -1220,6 +1231,8 @@ __global__ void ctl_reset_kernel(Ctl* ctls, uint32_t groups, int reset_epochs, u
   c->ovf_real = 0;
   c->next_source = 0;
   c->bad_source = 0;
+  c->hub_full = 0;
+  c->wait_ticks = wait_ticks;
   c->source_index = kNone;
   c->sources = c->buckets = c->light_phases = c->heavy_phases = c->far_phases = 0;
   c->light_edges = c->heavy_edges = c->improvements = c->barriers = 0;
@@ -1242,9 +1255,10 @@ __global__ void fill_kernel(uint32_t* p, size_t count, uint32_t value) {
 // ------------------------------------------------------------------ launchers
 
 hipError_t launch_ctl_reset(Ctl* c, uint32_t groups, int reset_epochs, unsigned long long* trace, uint32_t trace_cap,
-                            hipStream_t s) {
+                            unsigned long long wait_ticks, hipStream_t s) {
   if (groups < 1 || groups > kMaxGroups) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(ctl_reset_kernel, dim3(1), dim3(kMaxGroups), 0, s, c, groups, reset_epochs, trace, trace_cap);
+  hipLaunchKernelGGL(ctl_reset_kernel, dim3(1), dim3(kMaxGroups), 0, s, c, groups, reset_epochs, trace, trace_cap,
+                     wait_ticks);
   return hipGetLastError();
 }
 

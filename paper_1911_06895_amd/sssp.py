@@ -29,7 +29,8 @@ SSSP_WEIGHT_F64 = 2
 
 EXPORTS = ("sssp_create", "sssp_solve", "sssp_solve_async", "sssp_solve_multi", "sssp_solve_multi_async",
            "sssp_solve_status", "sssp_backward", "sssp_set_weights", "sssp_last_stats", "sssp_set_tuning",
-           "sssp_set_trace", "sssp_graph_info", "sssp_destroy", "sssp_status_string", "sssp_autotune")
+           "sssp_set_trace", "sssp_graph_info", "sssp_destroy", "sssp_status_string", "sssp_autotune",
+           "sssp_get_tuning")
 
 
 class SsspGraph(ctypes.Structure):
@@ -43,9 +44,12 @@ class SsspStats(ctypes.Structure):
                  "improvements", "barriers", "trace_records")]
 
 
+TUNING_FIELDS = ("workgroups_per_cu", "ring_buckets", "inline_edges", "concurrent_sources", "wait_limit_ms",
+                 "hub_edges", "chunk_entries", "inline_entries")
+
+
 class SsspTuning(ctypes.Structure):
-    _fields_ = [("workgroups_per_cu", ctypes.c_int32), ("ring_buckets", ctypes.c_int32),
-                ("inline_edges", ctypes.c_int32), ("concurrent_sources", ctypes.c_int32)]
+    _fields_ = [(name, ctypes.c_int32) for name in TUNING_FIELDS]
 
 
 class SsspAutotuneResult(ctypes.Structure):
@@ -91,6 +95,8 @@ def load_library(path: str = LIBRARY) -> ctypes.CDLL:
     lib.sssp_last_stats.restype = ctypes.c_int
     lib.sssp_set_tuning.argtypes = [P, ctypes.POINTER(SsspTuning)]
     lib.sssp_set_tuning.restype = ctypes.c_int
+    lib.sssp_get_tuning.argtypes = [P, ctypes.POINTER(SsspTuning)]
+    lib.sssp_get_tuning.restype = ctypes.c_int
     lib.sssp_set_trace.argtypes = [P, P, ctypes.c_int64]
     lib.sssp_set_trace.restype = ctypes.c_int
     lib.sssp_graph_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
@@ -240,12 +246,24 @@ def sssp_solve_status(handle, stream=None) -> None:
     _check(load_library().sssp_solve_status(handle, _stream(stream)), "sssp_solve_status")
 
 
-def sssp_backward(handle, sources, dist, grad_dist, grad_w, stream=None) -> None:
-    """dL/dw into grad_w (GPU float32 [m], caller edge order) for dL/ddist = grad_dist ([k, n])."""
-    src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32).reshape(-1))
+def _check_adjoint_args(handle, k, dist, grad_dist, grad_w) -> None:
+    import torch
+
     for t in (dist, grad_dist, grad_w):
         if not t.is_cuda or not t.is_contiguous():
             raise ValueError("dist, grad_dist and grad_w must be contiguous GPU tensors")
+    n, m, _ = sssp_graph_info(handle)
+    _check_rows(handle, dist, k)
+    if grad_dist.dtype != torch.float32 or grad_dist.numel() < k * n:
+        raise ValueError(f"grad_dist must hold [k={k}, n={n}] float32 elements")
+    if grad_w.dtype != torch.float32 or grad_w.numel() < m:
+        raise ValueError(f"grad_w must hold m={m} float32 elements")
+
+
+def sssp_backward(handle, sources, dist, grad_dist, grad_w, stream=None) -> None:
+    """dL/dw into grad_w (GPU float32 [m], caller edge order) for dL/ddist = grad_dist ([k, n])."""
+    src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32).reshape(-1))
+    _check_adjoint_args(handle, int(src.size), dist, grad_dist, grad_w)
     _check(load_library().sssp_backward(handle, src.ctypes.data_as(ctypes.c_void_p), int(src.size),
                                         ctypes.c_void_p(dist.data_ptr()), ctypes.c_void_p(grad_dist.data_ptr()),
                                         ctypes.c_void_p(grad_w.data_ptr()), _stream(stream)), "sssp_backward")
@@ -265,11 +283,20 @@ def sssp_last_stats(handle) -> dict:
     return {name: int(getattr(st, name)) for name, _ in SsspStats._fields_}
 
 
-def sssp_set_tuning(handle, workgroups_per_cu: int = 0, ring_buckets: int = 0, inline_edges: int = 0,
-                    concurrent_sources: int = 0) -> None:
-    t = SsspTuning(workgroups_per_cu=workgroups_per_cu, ring_buckets=ring_buckets, inline_edges=inline_edges,
-                   concurrent_sources=concurrent_sources)
+def sssp_set_tuning(handle, **fields) -> None:
+    """Schedule parameters (sssp_tuning); omitted fields are 0 (the library default)."""
+    unknown = set(fields) - set(TUNING_FIELDS)
+    if unknown:
+        raise TypeError(f"unknown tuning fields {sorted(unknown)}")
+    t = SsspTuning(**{k: int(v) for k, v in fields.items()})
     _check(load_library().sssp_set_tuning(handle, ctypes.byref(t)), "sssp_set_tuning")
+
+
+def sssp_get_tuning(handle) -> dict:
+    """The handle's schedule parameters with every default resolved (sssp_get_tuning)."""
+    t = SsspTuning()
+    _check(load_library().sssp_get_tuning(handle, ctypes.byref(t)), "sssp_get_tuning")
+    return {name: int(getattr(t, name)) for name in TUNING_FIELDS}
 
 
 def sssp_set_trace(handle, buffer, capacity: int) -> None:
@@ -327,6 +354,7 @@ class DeltaStepping:
         self.m = int(col.shape[0])
         self.device = device
         self.handle = sssp_create(rp, ci, wt, delta)
+        self.weights_version = 0  # bumped by every set_weights (the autograd wrapper checks it)
         torch.cuda.synchronize()
 
     def solve(self, sources, out=None):
@@ -355,6 +383,7 @@ class DeltaStepping:
         if isinstance(w, np.ndarray):
             w = self.torch.from_numpy(w.view(np.int32) if w.dtype == np.uint32 else w).to(self.device)
         sssp_set_weights(self.handle, w.contiguous())
+        self.weights_version += 1
 
     def backward(self, sources, dist, grad_dist):
         """dL/dw (float32 [m]) for dL/ddist = grad_dist, dist from solve(sources)."""
@@ -381,20 +410,32 @@ def shortest_paths(w, solver: DeltaStepping, sources):
     """Differentiable distances: dist = SSSP(w) from ``sources`` ([k, n], float32), with
     dL/dw computed by the shortest-path-tree adjoint (sssp_backward) in the backward pass.
     ``w`` is a float32 GPU tensor [m] in the caller's edge order; the solver's weights are
-    replaced by it (sssp_set_weights) before the solve."""
+    replaced by it (sssp_set_weights) before the solve. The weights are saved for the
+    backward pass (torch rejects a backward after an in-place change of ``w``); when the
+    solver has been given other weights since this forward pass (another forward on the
+    same solver), the backward pass puts these weights back and solves again before the
+    adjoint, so every node differentiates its own forward."""
     import torch
+
+    src = [int(x) for x in np.asarray(sources, dtype=np.int64).reshape(-1)]
 
     class _Sssp(torch.autograd.Function):
         @staticmethod
         def forward(ctx, weights):
             solver.set_weights(weights.detach())
-            dist = solver.solve(sources)
-            ctx.save_for_backward(dist)
+            dist = solver.solve(src)
+            ctx.version = solver.weights_version
+            ctx.save_for_backward(weights, dist)
             return dist
 
         @staticmethod
         def backward(ctx, grad_dist):
-            (dist,) = ctx.saved_tensors
-            return solver.backward(sources, dist, grad_dist)
+            weights, dist = ctx.saved_tensors
+            if solver.weights_version != ctx.version:
+                solver.set_weights(weights.detach())
+                again = solver.solve(src)
+                if not torch.equal(again.view(torch.int32), dist.view(torch.int32)):
+                    raise RuntimeError("shortest_paths: the forward distances cannot be reproduced")
+            return solver.backward(src, dist, grad_dist)
 
     return _Sssp.apply(w)

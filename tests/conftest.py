@@ -8,6 +8,23 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+# Figures a passing test reports (largest differences of tolerance comparisons), printed in the
+# terminal summary of every run.
+REPORT: list[str] = []
+
+
+def report(line: str) -> None:
+    REPORT.append(line)
+    print(line, flush=True)
+
+
+def pytest_terminal_summary(terminalreporter, exitstatus, config):
+    if REPORT:
+        terminalreporter.section("reported differences")
+        for line in REPORT:
+            terminalreporter.write_line(line)
+
+
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")

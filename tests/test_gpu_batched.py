@@ -272,6 +272,8 @@ def test_bfs_mode_unit_weights():
         st = solver.stats()
     finally:
         solver.close()
+    orc, rc = oracle.dijkstra(g, src)
+    assert rc == oracle.OK and np.array_equal(got, orc), "BFS mode differs from the oracle's Dijkstra"
     a = sp.csr_matrix((np.ones(g.m), g.col, g.row_ptr), shape=(g.n, g.n))
     hops = shortest_path(a, method="D", unweighted=True, indices=src)
     want = np.where(np.isfinite(hops), hops, 2.0 ** 32 - 1).astype(np.uint32)

@@ -5,6 +5,9 @@ non-decreasing), so every comparison is bit-exact: uint32 for integer weights
 and 0 ulp for fp32 weights. A nonzero fp32 difference would be reported with
 its size; the allowed relative tolerance 1e-6 is never used because none is seen.
 """
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
@@ -51,6 +54,14 @@ def assert_exact(g, got, src, label=""):
             detail = f" max rel diff {rel.max() if rel.size else 'n/a'}"
         raise AssertionError(f"{label} source {src}: {bad.size} vertices differ, first {bad[:5]}: "
                              f"got {got[bad[:5]]} want {want[bad[:5]]}{detail}")
+
+
+def certify_rows(g, srcs, rows, label=""):
+    """Every row through the oracle's O(m) optimality certificate, on host threads."""
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        codes = list(ex.map(lambda r: oracle.certify(g, int(srcs[r]), rows[r]), range(len(srcs))))
+    bad = [(r, c) for r, c in enumerate(codes) if c != oracle.CERT_OK]
+    assert not bad, f"{label}: rows not certified (row, code): {bad[:8]}"
 
 
 def test_er_1024_all_deltas():
@@ -110,6 +121,53 @@ def test_rmat_s14(delta):
         light += int((mask & (g.w <= delta)).sum())
     assert st["heavy_edges"] == heavy
     assert st["light_edges"] >= light
+
+
+def _heavy_phase_records(g, delta, src):
+    """(bucket, input entries) of every heavy phase of one traced solve: the input of bucket i's
+    heavy phase is S_i, the vertices expanded in bucket i (Sec. IV-D)."""
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, delta)
+    try:
+        cap = 1 << 16
+        buf = torch.zeros(4 * cap, dtype=torch.int64, device="cuda")
+        sssp.sssp_set_trace(solver.handle, buf, cap)
+        d = solver.solve_numpy([src])[0]
+        st = solver.stats()
+        sssp.sssp_set_trace(solver.handle, None, 0)
+        words = buf.cpu().numpy().view(np.uint64).reshape(-1, 4)[:min(cap, st["trace_records"])]
+    finally:
+        solver.close()
+    assert st["trace_records"] <= cap
+    what = words[:, 1]
+    action = (what & np.uint64(0x7F)).astype(np.int64)
+    bucket = ((what >> np.uint64(8)) & np.uint64(0xFFFFFF)).astype(np.int64)
+    entries = (what >> np.uint64(32)).astype(np.int64)
+    heavy = action == 2
+    return d, bucket[heavy], entries[heavy]
+
+
+@pytest.mark.parametrize("kind,delta", [("rmat", 8), ("rmat", 32), ("rmat", 128), ("grid", 50), ("er", 16)])
+def test_bucket_schedule_matches_oracle_trace(kind, delta):
+    """Schedule invariants of Fig. 1 on the GPU (integer weights, where no bucket is repeated):
+    the non-empty buckets and each |S_i| equal those of the oracle's literal linear-algebra run,
+    and S_i = {v : floor(d(v) / delta) = i}."""
+    if kind == "rmat":
+        g = G.rmat_graph(14, 16, cfg=2)
+    elif kind == "grid":
+        g = G.grid_graph(64, 64, cfg=3)
+    else:
+        g = G.workload("er_n1024_m8192")
+    src = int(G.sources_with_outedges(g, 1, cfg=7)[0])
+    d, buckets, sizes = _heavy_phase_records(g, delta, src)
+    want_d, rc, tr = oracle.delta_stepping_la(g, delta, src)
+    assert rc == oracle.OK and np.array_equal(d, want_d)
+    nz = sizes > 0  # a bucket whose ring slot held only vertices that had moved lower expands nothing
+    assert np.array_equal(buckets[nz], tr["buckets"]), "non-empty buckets differ from the oracle trace"
+    assert np.array_equal(sizes[nz], tr["s_size"]), "|S_i| differs from the oracle trace"
+    fin = d != np.uint32(0xFFFFFFFF)
+    by_dist = np.bincount((d[fin] // delta).astype(np.int64))
+    assert np.array_equal(np.nonzero(by_dist)[0], tr["buckets"])
+    assert np.array_equal(by_dist[by_dist > 0], sizes[nz])
 
 
 def test_grid_many_buckets():
@@ -243,6 +301,73 @@ def test_fp32_bucket_indices_above_2_29():
         assert_exact(g, got[0], 0, f"delta={delta}")
 
 
+def test_long_inline_run_with_short_wait_limit():
+    """A path of 300k vertices at delta 1: every bucket holds one vertex, so the whole solve runs
+    as steps of the leader workgroup alone inside a single device-wide barrier, while every other
+    workgroup waits in it. With a 100 ms wait limit, the leader's heartbeat (one per step) is what
+    keeps the waits from aborting the solve; distances are the prefix sums."""
+    n = 300_000
+    g = G.path_graph(n, np.ones(n - 1, dtype=np.uint32))
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, 1)
+    try:
+        solver.set_tuning(wait_limit_ms=100)
+        assert sssp.sssp_get_tuning(solver.handle)["wait_limit_ms"] == 100
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        got = solver.solve_numpy([0])[0]
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        st = solver.stats()
+    finally:
+        solver.close()
+    print(f"[parity] path n={n} delta=1: {ms:.1f} ms, {st['barriers']} barriers, {st['buckets']} buckets", flush=True)
+    assert np.array_equal(got, np.arange(n, dtype=np.uint32))
+    assert st["buckets"] == n
+    assert ms > 200.0, "the solve ended before the wait limit could matter"
+
+
+@pytest.mark.parametrize("tile", [{"hub_edges": 256}, {"hub_edges": 65536}, {"chunk_entries": 32},
+                                  {"chunk_entries": 128, "inline_entries": 64},
+                                  {"inline_entries": 1, "inline_edges": 1},
+                                  {"hub_edges": 512, "chunk_entries": 64, "inline_entries": 512,
+                                   "inline_edges": 65536, "workgroups_per_cu": 1}])
+def test_tile_schedules_exact(tile):
+    """Every tile schedule the autotuner may pick (hub threshold, chunk size, the limits of the
+    steps one workgroup runs alone) gives the oracle's distances, u32 and fp32."""
+    g = G.rmat_graph(14, 16, cfg=2)
+    srcs = G.sources_with_outedges(g, 3, cfg=2)
+    got, _ = gpu_solve(g, 32, srcs, tuning=tile)
+    for r, s in enumerate(srcs):
+        assert_exact(g, got[r], s, f"tile {tile}")
+    gf = G.rmat_graph(13, 16, cfg=41, weights="f32_loguniform", wlo=1e-2, whi=1e2)
+    sf = G.sources_with_outedges(gf, 2, cfg=41)
+    got, _ = gpu_solve(gf, 0.5, sf, tuning={**tile, "concurrent_sources": 2})
+    for r, s in enumerate(sf):
+        assert_exact(gf, got[r], s, f"f32 tile {tile}")
+
+
+def test_tuning_fields_resolved_and_checked():
+    g = G.workload("er_n1024_m8192")
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, 32)
+    try:
+        t = sssp.sssp_get_tuning(solver.handle)
+        assert t["hub_edges"] == 1024 and t["inline_edges"] == 4096 and t["wait_limit_ms"] == 30000
+        assert t["chunk_entries"] in (256, 512) and t["inline_entries"] == t["chunk_entries"]
+        assert t["concurrent_sources"] == 1 and t["workgroups_per_cu"] == 2
+        for bad in ({"hub_edges": 100}, {"hub_edges": 3000}, {"chunk_entries": 1024}, {"chunk_entries": 48},
+                    {"inline_entries": 513}, {"wait_limit_ms": -1}):
+            with pytest.raises(sssp.SsspError) as e:
+                solver.set_tuning(**bad)
+            assert e.value.status == sssp.SSSP_ERR_INVALID_ARGUMENT, bad
+        solver.set_tuning(hub_edges=4096, chunk_entries=64, inline_entries=100)
+        t = sssp.sssp_get_tuning(solver.handle)
+        assert (t["hub_edges"], t["chunk_entries"], t["inline_entries"]) == (4096, 64, 100)
+        assert_exact(g, solver.solve_numpy([9])[0], 9)
+    finally:
+        solver.close()
+
+
 def test_tuning_variants_agree():
     g = G.rmat_graph(12, 16, cfg=2)
     s = int(G.sources_with_outedges(g, 1, cfg=3)[0])
@@ -257,32 +382,48 @@ def rmat_s22():
 
 
 def test_rmat_s22_bench_configuration(rmat_s22):
-    """The benchmark's launch: R-MAT scale 22, 64 sources in one call, delta 64. Two rows are
-    compared with the oracle vertex by vertex, eight are checked by the optimality certificate."""
+    """The benchmark's launch: R-MAT scale 22, 64 sources in one call, delta 64. Rows 0, 1 and 63
+    are compared with the oracle's Dijkstra vertex by vertex; all 64 rows are checked by the
+    optimality certificate (a proof of exactness)."""
+    print("[parity] rmat s22 delta=64, 64 sources", flush=True)
     g = rmat_s22
     srcs = G.sources_with_outedges(g, 64, cfg=2)
     got, st = gpu_solve(g, 64, srcs)
     assert st["sources"] == 64
-    for r in range(2):
+    for r in (0, 1, 63):
         assert_exact(g, got[r], srcs[r], "rmat s22 delta=64")
-    for r in range(2, 8):
-        assert oracle.certify(g, int(srcs[r]), got[r]) == oracle.CERT_OK, f"row {r}"
+    certify_rows(g, srcs, got, "rmat s22 delta=64")
 
 
-def test_rmat_s22_small_delta(rmat_s22):
+@pytest.mark.parametrize("delta", [8, 16, 32, 128])
+def test_rmat_s22_swept_deltas(rmat_s22, delta):
+    """Every other delta of the benchmark's sweep: two of the 64 sources per delta, each compared
+    with Dijkstra vertex by vertex (a different pair of rows for every delta)."""
+    print(f"[parity] rmat s22 delta={delta}", flush=True)
     g = rmat_s22
-    srcs = G.sources_with_outedges(g, 64, cfg=2)[-1:]
-    got, _ = gpu_solve(g, 8, srcs)
-    assert_exact(g, got[0], srcs[0], "rmat s22 delta=8")
+    all_srcs = G.sources_with_outedges(g, 64, cfg=2)
+    pick = {8: (63, 5), 16: (10, 40), 32: (20, 50), 128: (30, 60)}[delta]
+    srcs = all_srcs[list(pick)]
+    got, _ = gpu_solve(g, delta, srcs)
+    for r, s in enumerate(srcs):
+        assert_exact(g, got[r], s, f"rmat s22 delta={delta}")
 
 
-def test_grid_4096_many_buckets():
-    """The high-diameter grid: about 10^4 buckets with small frontiers (corner source)."""
-    g = G.workload("grid4096_u32")
-    got, st = gpu_solve(g, 400, [0])
+@pytest.fixture(scope="module")
+def grid4096():
+    return G.workload("grid4096_u32")
+
+
+@pytest.mark.parametrize("delta", [50, 100, 400])
+def test_grid_4096_many_buckets(grid4096, delta):
+    """The high-diameter grid at each delta of the benchmark (about 4.7k to 37k buckets with small
+    frontiers, corner source): certified, and compared with Dijkstra vertex by vertex."""
+    print(f"[parity] grid 4096 delta={delta}", flush=True)
+    g = grid4096
+    got, st = gpu_solve(g, delta, [0])
     assert oracle.certify(g, 0, got[0]) == oracle.CERT_OK
-    assert_exact(g, got[0], 0, "grid4096 delta=400")
-    assert st["buckets"] >= len(np.unique(got[0] // 400))
+    assert_exact(g, got[0], 0, f"grid4096 delta={delta}")
+    assert st["buckets"] >= len(np.unique(got[0] // delta))
 
 
 # ---------------------------------------------------------------- fp64 weights (the paper's GrB_FP64)
