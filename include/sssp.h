@@ -282,19 +282,24 @@ sssp_status sssp_set_trace(sssp_handle *h, uint64_t *device_buffer, int64_t capa
 typedef struct {
   double delta;               /* the chosen delta */
   int32_t concurrent_sources; /* the chosen number of concurrent groups */
-  int32_t trials;             /* (delta, group count) pairs timed */
-  float ms;                   /* device time of one solve of the sample with the chosen pair */
+  int32_t trials;             /* configurations timed */
+  float ms;                   /* device time of one solve of the sample with the chosen configuration */
+  sssp_tuning tuning;         /* the chosen schedule, every field resolved (as sssp_get_tuning) */
 } sssp_autotune_result;
 
 /*
- * sssp_autotune -- create a handle whose delta and concurrent-source count are
- *   the fastest found for a sample of sources. delta is the method's only
- *   parameter (bucket width and light/heavy threshold, Sec. III-A and IV-A): a
- *   small delta means many buckets with small phases, a large one means light
- *   edges relaxed more than once. For each candidate delta the graph is split
- *   (as sssp_create) and the sample solved with 1, 8, 16, ... concurrent groups
- *   (up to k; the search over group counts stops when the time rises), one
- *   warm-up and one timed solve per pair.
+ * sssp_autotune -- create a handle whose delta, concurrent-source count and
+ *   tile schedule are the fastest found for a sample of sources. delta is the
+ *   method's only parameter (bucket width and light/heavy threshold, Sec. III-A
+ *   and IV-A): a small delta means many buckets with small phases, a large one
+ *   means light edges relaxed more than once. For each candidate delta the
+ *   graph is split (as sssp_create) and the sample solved with 1, 8, 16, ...
+ *   concurrent groups (up to k; the search over group counts stops when the
+ *   time rises), one warm-up and one timed solve per pair. Then, on the fastest
+ *   pair, the tile schedule is searched one field at a time (workgroups_per_cu
+ *   for one group, hub_edges, chunk_entries, inline_edges, inline_entries; a
+ *   value is kept when the faster of two timed solves beats the current choice
+ *   by 2 %).
  *   g: as for sssp_create.  sources: HOST int32 [k], each in [0, n).
  *   mode: 0 = one row per source (sssp_solve), 1 = nearest-source distances
  *   (sssp_solve_multi; one group).  deltas: HOST [n_deltas] candidates, or NULL

@@ -1,8 +1,12 @@
 // Schedule autotuner: the method has one knob, delta (the bucket width, which
-// also decides which edges are light, Sec. III-A/IV-A); this build adds one of
-// its own, the number of sources solved concurrently. sssp_autotune times
-// solves of a sample of sources over candidate values and returns a handle
-// built with the fastest pair. Host code only, over the public entry points.
+// also decides which edges are light, Sec. III-A/IV-A); this build adds its
+// own: the number of sources solved concurrently and the tile schedule (the
+// workgroup size, the hub threshold, the chunk size, the largest step run by
+// one workgroup alone). sssp_autotune times solves of a sample of sources:
+// first over (delta, concurrent groups), then, on the fastest handle, over
+// each tile parameter in turn (coordinate search, keeping a value only when it
+// is at least 2 % faster than the current choice), and returns that handle.
+// Host code only, over the public entry points.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -50,9 +54,10 @@ sssp_status derive_deltas(const sssp_graph* g, hipStream_t s, std::vector<double
   return SSSP_OK;
 }
 
-// Device time of one solve of the sample (after a warm-up solve), or a status.
+// Device time of one solve of the sample (after a warm-up solve), or a status;
+// with reps = 2 the faster of two timed solves.
 sssp_status time_solve(sssp_handle* h, const int32_t* src_dev, int32_t k, int32_t mode, void* dist, hipStream_t s,
-                       float* ms) {
+                       float* ms, int reps = 1) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
@@ -63,11 +68,16 @@ sssp_status time_solve(sssp_handle* h, const int32_t* src_dev, int32_t k, int32_
   };
   sssp_status st = enqueue();
   if (st == SSSP_OK) st = sssp_solve_status(h, s);
-  if (st == SSSP_OK && hipEventRecord(e0, s) != hipSuccess) st = SSSP_ERR_DEVICE;
-  if (st == SSSP_OK) st = enqueue();
-  if (st == SSSP_OK && hipEventRecord(e1, s) != hipSuccess) st = SSSP_ERR_DEVICE;
-  if (st == SSSP_OK) st = sssp_solve_status(h, s);
-  if (st == SSSP_OK && hipEventElapsedTime(ms, e0, e1) != hipSuccess) st = SSSP_ERR_DEVICE;
+  *ms = INFINITY;
+  for (int r = 0; r < reps && st == SSSP_OK; ++r) {
+    float t = 0;
+    if (hipEventRecord(e0, s) != hipSuccess) st = SSSP_ERR_DEVICE;
+    if (st == SSSP_OK) st = enqueue();
+    if (st == SSSP_OK && hipEventRecord(e1, s) != hipSuccess) st = SSSP_ERR_DEVICE;
+    if (st == SSSP_OK) st = sssp_solve_status(h, s);
+    if (st == SSSP_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) st = SSSP_ERR_DEVICE;
+    if (st == SSSP_OK && t < *ms) *ms = t;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return st;
@@ -150,8 +160,45 @@ sssp_status sssp_autotune(const sssp_graph* g, const int32_t* sources, int32_t k
     }
     sssp_destroy(h);
   }
+  if (!best) {
+    (void)hipFree(src_dev);
+    return last_error != SSSP_OK ? last_error : SSSP_ERR_UNSUPPORTED;
+  }
+  // the tile schedule, one parameter at a time on the chosen (delta, groups)
+  sssp_tuning cur{};
+  cur.concurrent_sources = res.concurrent_sources;
+  float cur_ms = INFINITY;
+  if (time_solve(best, src_dev, k, mode, dist, s, &cur_ms, 2) == SSSP_OK) {
+    ++res.trials;
+    struct Knob {
+      int32_t sssp_tuning::*field;
+      std::vector<int32_t> values;
+    };
+    std::vector<Knob> knobs = {{&sssp_tuning::hub_edges, {512, 2048, 4096}},
+                               {&sssp_tuning::chunk_entries, {64, 128, 256, 512}},
+                               {&sssp_tuning::inline_edges, {1024, 16384}},
+                               {&sssp_tuning::inline_entries, {64, 128}}};
+    if (res.concurrent_sources == 1) knobs.insert(knobs.begin(), Knob{&sssp_tuning::workgroups_per_cu, {1}});
+    for (const Knob& kb : knobs) {
+      int32_t keep = cur.*kb.field;
+      for (int32_t v : kb.values) {
+        sssp_tuning t = cur;
+        t.*kb.field = v;
+        if (sssp_set_tuning(best, &t) != SSSP_OK) continue;
+        float ms = 0;
+        if (time_solve(best, src_dev, k, mode, dist, s, &ms, 2) != SSSP_OK) continue;
+        ++res.trials;
+        if (ms < 0.98f * cur_ms) {
+          cur_ms = ms;
+          keep = v;
+        }
+      }
+      cur.*kb.field = keep;
+    }
+    if (sssp_set_tuning(best, &cur) == SSSP_OK) res.ms = cur_ms;
+  }
   (void)hipFree(src_dev);
-  if (!best) return last_error != SSSP_OK ? last_error : SSSP_ERR_UNSUPPORTED;
+  (void)sssp_get_tuning(best, &res.tuning);
   *out = best;
   if (result) *result = res;
   return SSSP_OK;

@@ -54,7 +54,7 @@ class SsspTuning(ctypes.Structure):
 
 class SsspAutotuneResult(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_double), ("concurrent_sources", ctypes.c_int32), ("trials", ctypes.c_int32),
-                ("ms", ctypes.c_float)]
+                ("ms", ctypes.c_float), ("tuning", SsspTuning)]
 
 
 class SsspError(RuntimeError):
@@ -166,8 +166,9 @@ def sssp_create(row_ptr, col_idx, weights, delta: float, stream=None) -> ctypes.
 
 
 def sssp_autotune(row_ptr, col_idx, weights, sources, dist, multi: bool = False, deltas=None, stream=None):
-    """Handle with the fastest (delta, concurrent sources) for a sample of host sources; dist is GPU
-    scratch ([k, n], or [n] when multi). Returns (handle, result dict)."""
+    """Handle with the fastest (delta, concurrent sources, tile schedule) for a sample of host
+    sources; dist is GPU scratch ([k, n], or [n] when multi). Returns (handle, result dict; its
+    "tuning" entry is the chosen schedule as a dict)."""
     g = _graph(row_ptr, col_idx, weights)
     src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32).reshape(-1))
     if not dist.is_cuda or not dist.is_contiguous() or dist.element_size() != (8 if g.wtype == SSSP_WEIGHT_F64 else 4):
@@ -182,7 +183,9 @@ def sssp_autotune(row_ptr, col_idx, weights, sources, dist, multi: bool = False,
                                         d.ctypes.data_as(ctypes.c_void_p) if d is not None else None,
                                         0 if d is None else int(d.size), ctypes.c_void_p(dist.data_ptr()),
                                         _stream(stream), ctypes.byref(h), ctypes.byref(res)), "sssp_autotune")
-    return h, {name: getattr(res, name) for name, _ in SsspAutotuneResult._fields_}
+    out = {name: getattr(res, name) for name, _ in SsspAutotuneResult._fields_ if name != "tuning"}
+    out["tuning"] = {name: int(getattr(res.tuning, name)) for name in TUNING_FIELDS}
+    return h, out
 
 
 def _check_rows(handle, dist, k: int) -> None:

@@ -292,6 +292,10 @@ def test_autotune_returns_a_correct_tuned_handle():
     h, res = sssp.sssp_autotune(rp, ci, wt, srcs, scratch)
     try:
         assert res["trials"] >= 2 and res["ms"] > 0
+        tiles = res["tuning"]
+        assert tiles == sssp.sssp_get_tuning(h)
+        assert tiles["hub_edges"] in (512, 1024, 2048, 4096) and tiles["chunk_entries"] in (64, 128, 256, 512)
+        assert tiles["concurrent_sources"] == res["concurrent_sources"]
         mean = float(g.w.astype(np.float64).mean())
         assert mean / 64 <= res["delta"] <= mean * 8 and np.log2(res["delta"]).is_integer()
         assert res["concurrent_sources"] in (1, 8, 16, 32)
@@ -303,10 +307,43 @@ def test_autotune_returns_a_correct_tuned_handle():
     # nearest-source mode with explicit candidates
     h, res = sssp.sssp_autotune(rp, ci, wt, srcs[:3], scratch[0], multi=True, deltas=[0.5, 2.0])
     try:
-        assert res["delta"] in (0.5, 2.0) and res["concurrent_sources"] == 1 and res["trials"] == 2
+        # two (delta, group) trials, then the tile search on the faster one
+        assert res["delta"] in (0.5, 2.0) and res["concurrent_sources"] == 1 and res["trials"] > 2
         d = torch.empty(g.n, dtype=torch.float32, device="cuda")
         sssp.sssp_solve_multi(h, srcs[:3], d)
         want = np.stack([oracle.dijkstra(g, int(s))[0] for s in srcs[:3]]).min(axis=0)
         assert same_bits(d.cpu().numpy(), want)
+    finally:
+        sssp.sssp_destroy(h)
+
+
+def test_autotuned_tiles_exact_rmat_and_ragged():
+    """Handles the autotuner returns (delta, groups and the tile schedule chosen by timing) are
+    oracle-exact: R-MAT scale 14 with u32 weights, and the ragged batch in nearest-source mode."""
+    print("[batched] autotuned tiles: rmat s14 u32 and a ragged batch", flush=True)
+    g = G.rmat_graph(14, 16, cfg=2)
+    srcs = G.sources_with_outedges(g, 24, cfg=2)
+    rp, ci = torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(g.col).cuda()
+    wt = torch.from_numpy(g.w.view(np.int32)).cuda()
+    scratch = torch.empty((len(srcs), g.n), dtype=torch.int32, device="cuda")
+    h, res = sssp.sssp_autotune(rp, ci, wt, srcs, scratch)
+    try:
+        print(f"[batched] rmat s14 tuned: delta {res['delta']}, {res['tuning']}", flush=True)
+        dist = torch.empty((len(srcs), g.n), dtype=torch.int32, device="cuda")
+        sssp.sssp_solve(h, srcs, dist)
+        check_rows(g, srcs, as_host(dist, np.uint32), exact_rows=len(srcs))
+    finally:
+        sssp.sssp_destroy(h)
+    graphs = G.ragged_er_batch(96, cfg=68, nlo=1_000, nhi=20_000)
+    u, offs = G.block_union(graphs)
+    starts = offs[:-1].astype(np.int32)
+    rp, ci, wt = (torch.from_numpy(a).cuda() for a in (u.row_ptr, u.col, u.w))
+    d = torch.empty(u.n, dtype=torch.float32, device="cuda")
+    h, res = sssp.sssp_autotune(rp, ci, wt, starts, d, multi=True)
+    try:
+        print(f"[batched] ragged tuned: delta {res['delta']}, {res['tuning']}", flush=True)
+        d.fill_(0.0)
+        sssp.sssp_solve_multi(h, starts, d)
+        _check_blocks(graphs, offs, d.cpu().numpy(), exact_blocks=set(range(96)))
     finally:
         sssp.sssp_destroy(h)
