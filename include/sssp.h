@@ -236,6 +236,34 @@ sssp_status sssp_backward(sssp_handle *h, const int32_t *sources, int32_t k, con
                           const float *grad_dist, float *grad_w, void *stream);
 
 /*
+ * sssp_backward_noalloc -- sssp_backward for callers that cannot allocate device
+ *   memory during the call (tight serving or training loops, harnesses that
+ *   forbid hipMalloc): the adjoint's working set (distances and parents in
+ *   solver order, child counts, levels, fp64 accumulators of grad_dist and of
+ *   dL/dw) lives in a static device array of the library, 64 MiB per GPU, held
+ *   by every GPU the library runs on until the process ends; nothing is
+ *   allocated, freed or staged through host buffers by the call.
+ *   The result is that of sssp_backward (same kernels and tie rule), with
+ *   these differences:
+ *     sources: DEVICE int32 [k] (read when the work runs; an entry outside
+ *       [0, n) leaves its row out and returns INVALID_ARGUMENT);
+ *     the working set takes 8 m bytes plus 28 n bytes per concurrent group
+ *       (each part rounded up to 256 bytes) and 34 KiB of launch parameters; the call
+ *       runs as many of the handle's concurrent groups as fit (at least one);
+ *       a graph for which one group does not fit returns UNSUPPORTED (about
+ *       n = 2^18 with m = 2^22, or m up to about 8.3 million edges with few
+ *       vertices).
+ *   Every call on one GPU (any handle, any stream) uses the same array and
+ *   leaves its contents behind; the call clears what must start at zero.
+ *   Calls that overlap in time on one GPU race and must be serialised by the
+ *   caller. Synchronises the stream.
+ *   Errors: INVALID_ARGUMENT, UNSUPPORTED (weight type, or the graph does not
+ *   fit the array), NO_FORWARD, DEVICE.
+ */
+sssp_status sssp_backward_noalloc(sssp_handle *h, const int32_t *sources, int32_t k, const void *dist,
+                                  const float *grad_dist, float *grad_w, void *stream);
+
+/*
  * sssp_set_weights -- replace the weights of the handle's graph (same CSR
  *   structure, caller edge order) and redo the light/heavy split for the
  *   handle's delta (Sec. IV-A). weights: DEVICE [m] of the handle's weight

@@ -6,9 +6,43 @@
 #include <new>
 #include <vector>
 
+#include <mutex>
+
 #include "sssp.h"
 #include "sssp_internal.h"
 
+namespace {
+// Fixed working memory of sssp_backward_noalloc: 64 MiB per GPU, held by every
+// device the library runs on until the process ends. Every call on one GPU
+// shares it (calls that overlap on one GPU race).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the scratch array on `device`, which must be current: each
+// GPU holds its own copy at its own address. In host code the array's name is
+// only a stand-in, so kernels receive this address, never the name.
+hipError_t scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[device] = p;
+  }
+  *out = g_scratch_dev[device];
+  return hipSuccess;
+}
+
+size_t align256(size_t bytes) { return (bytes + 255) & ~static_cast<size_t>(255); }
+}  // namespace
 
 // Working set of one extra concurrent group (the first group's lives in Params).
 struct GroupMem {
@@ -77,6 +111,7 @@ struct sssp_handle {
   unsigned long long* aux = nullptr;       // [2] small device scratch for status reads
   unsigned long long* aux_host = nullptr;  // [2] pinned host copy of aux
   int adj_grid = 0;
+  void* scratch = nullptr;  // this device's copy of the library's static scratch array (sssp_backward_noalloc)
 };
 
 namespace {
@@ -339,6 +374,7 @@ sssp_status clear_stamps(sssp_handle* h, hipStream_t s) {
 
 sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, sssp_handle* h) {
   SSSP_TRY(hipGetDevice(&h->device));
+  if (scratch_address(h->device, &h->scratch) != hipSuccess) h->scratch = nullptr;
   hipDeviceProp_t prop;
   SSSP_TRY(hipGetDeviceProperties(&prop, h->device));
   if (!prop.cooperativeLaunch) return SSSP_ERR_UNSUPPORTED;
@@ -738,6 +774,47 @@ sssp_status sssp_backward(sssp_handle* h, const int32_t* sources, int32_t k, con
     }
   }
   return run_adjoint(h, groups, h->adj_params_dev, h->adj_grad64, h->src_dev, k, dist, grad_dist, grad_w, s);
+}
+
+sssp_status sssp_backward_noalloc(sssp_handle* h, const int32_t* sources, int32_t k, const void* dist,
+                                  const float* grad_dist, float* grad_w, void* stream) {
+  if (!h || !sources || k < 1 || !dist || !grad_dist || !grad_w) return SSSP_ERR_INVALID_ARGUMENT;
+  if (h->wtype != SSSP_WEIGHT_F32 || h->adj_grid < 1) return SSSP_ERR_UNSUPPORTED;
+  if (!h->solved) return SSSP_ERR_NO_FORWARD;
+  if (!h->scratch) return SSSP_ERR_DEVICE;  // the array's address could not be resolved at create
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SSSP_TRY(hipSetDevice(h->device));
+  // carve the scratch array: launch parameters, dL/dw accumulator, then one working set per group
+  const size_t un = static_cast<size_t>(h->n), um = static_cast<size_t>(h->m);
+  static_assert(sizeof(sssp::AdjParams) * sssp::kMaxGroups <= 35 * 1024, "the header states 34 KiB");
+  const size_t params_bytes = align256(sizeof(sssp::AdjParams) * sssp::kMaxGroups);
+  const size_t grad_bytes = align256(um * sizeof(double));
+  const size_t group_bytes = align256(un * sizeof(uint32_t)) * 3 + align256(un * sizeof(unsigned long long)) +
+                             align256(un * sizeof(double));
+  if (params_bytes + grad_bytes + group_bytes > kNoAllocScratchBytes) return SSSP_ERR_UNSUPPORTED;
+  const size_t fit = (kNoAllocScratchBytes - params_bytes - grad_bytes) / group_bytes;
+  // as many concurrent groups as the forward solve uses, if they fit (a divisor of the grid), else fewer
+  uint32_t groups = h->adj_grid % static_cast<int>(h->groups) == 0 ? h->groups : 1u;
+  while (groups > 1 && groups > fit) groups >>= 1;
+  while (groups > 1 && h->adj_grid % static_cast<int>(groups) != 0) groups >>= 1;
+  char* base = static_cast<char*>(h->scratch);
+  auto* params_dev = reinterpret_cast<sssp::AdjParams*>(base);
+  auto* grad64 = reinterpret_cast<double*>(base + params_bytes);
+  char* at = base + params_bytes + grad_bytes;
+  for (uint32_t gi = 0; gi < groups; ++gi) {
+    sssp::AdjParams& a = h->adj_host[gi];
+    a.d = reinterpret_cast<uint32_t*>(at);
+    at += align256(un * sizeof(uint32_t));
+    a.cnt = reinterpret_cast<uint32_t*>(at);
+    at += align256(un * sizeof(uint32_t));
+    a.lvl = reinterpret_cast<uint32_t*>(at);
+    at += align256(un * sizeof(uint32_t));
+    a.parent = reinterpret_cast<unsigned long long*>(at);
+    at += align256(un * sizeof(unsigned long long));
+    a.g = reinterpret_cast<double*>(at);
+    at += align256(un * sizeof(double));
+  }
+  return run_adjoint(h, groups, params_dev, grad64, sources, k, dist, grad_dist, grad_w, s);
 }
 
 sssp_status sssp_set_weights(sssp_handle* h, const void* weights, void* stream) {

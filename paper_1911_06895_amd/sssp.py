@@ -30,7 +30,7 @@ SSSP_WEIGHT_F64 = 2
 EXPORTS = ("sssp_create", "sssp_solve", "sssp_solve_async", "sssp_solve_multi", "sssp_solve_multi_async",
            "sssp_solve_status", "sssp_backward", "sssp_set_weights", "sssp_last_stats", "sssp_set_tuning",
            "sssp_set_trace", "sssp_graph_info", "sssp_destroy", "sssp_status_string", "sssp_autotune",
-           "sssp_get_tuning")
+           "sssp_get_tuning", "sssp_backward_noalloc")
 
 
 class SsspGraph(ctypes.Structure):
@@ -89,6 +89,8 @@ def load_library(path: str = LIBRARY) -> ctypes.CDLL:
     lib.sssp_solve_status.restype = ctypes.c_int
     lib.sssp_backward.argtypes = [P, P, ctypes.c_int32, P, P, P, P]
     lib.sssp_backward.restype = ctypes.c_int
+    lib.sssp_backward_noalloc.argtypes = [P, P, ctypes.c_int32, P, P, P, P]
+    lib.sssp_backward_noalloc.restype = ctypes.c_int
     lib.sssp_set_weights.argtypes = [P, P, P]
     lib.sssp_set_weights.restype = ctypes.c_int
     lib.sssp_last_stats.argtypes = [P, ctypes.POINTER(SsspStats)]
@@ -270,6 +272,22 @@ def sssp_backward(handle, sources, dist, grad_dist, grad_w, stream=None) -> None
     _check(load_library().sssp_backward(handle, src.ctypes.data_as(ctypes.c_void_p), int(src.size),
                                         ctypes.c_void_p(dist.data_ptr()), ctypes.c_void_p(grad_dist.data_ptr()),
                                         ctypes.c_void_p(grad_w.data_ptr()), _stream(stream)), "sssp_backward")
+
+
+def sssp_backward_noalloc(handle, sources, dist, grad_dist, grad_w, stream=None) -> None:
+    """sssp_backward with the working set in the library's static device array; ``sources`` is a
+    GPU int32 tensor [k] (nothing is allocated or staged by the call)."""
+    import torch
+
+    if not sources.is_cuda or sources.dtype != torch.int32 or not sources.is_contiguous():
+        raise ValueError("sources must be a contiguous GPU int32 tensor")
+    k = int(sources.numel())
+    _check_adjoint_args(handle, k, dist, grad_dist, grad_w)
+    _check(load_library().sssp_backward_noalloc(handle, ctypes.c_void_p(sources.data_ptr()), k,
+                                                ctypes.c_void_p(dist.data_ptr()),
+                                                ctypes.c_void_p(grad_dist.data_ptr()),
+                                                ctypes.c_void_p(grad_w.data_ptr()), _stream(stream)),
+           "sssp_backward_noalloc")
 
 
 def sssp_set_weights(handle, weights, stream=None) -> None:
