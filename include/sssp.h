@@ -84,6 +84,8 @@ typedef struct {
   uint64_t light_edges;  /* light edges scanned */
   uint64_t heavy_edges;  /* heavy edges scanned */
   uint64_t improvements; /* relaxations that lowered a tentative distance */
+  uint64_t attempts;     /* atomic min operations on tentative distances (requests that passed the
+                            cached comparison; attempts - improvements lost to a lower value) */
   uint64_t barriers;     /* device-wide synchronisations */
   uint64_t trace_records; /* step records produced (see sssp_set_trace) */
 } sssp_stats;

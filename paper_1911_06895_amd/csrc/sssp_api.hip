@@ -47,6 +47,7 @@ size_t align256(size_t bytes) { return (bytes + 255) & ~static_cast<size_t>(255)
 // Working set of one extra concurrent group (the first group's lives in Params).
 struct GroupMem {
   void* tbuf[2] = {nullptr, nullptr};
+  void* texp = nullptr;
   uint32_t *qstamp = nullptr, *sstamp = nullptr, *bstamp = nullptr, *fstamp = nullptr, *ovf_at = nullptr;
   uint32_t* front[2] = {nullptr, nullptr};
   uint32_t* slist = nullptr;
@@ -153,7 +154,7 @@ hipError_t dalloc(T** p, size_t count) {
 }
 
 void free_group(GroupMem& gm) {
-  void* mem[] = {gm.tbuf[0], gm.tbuf[1], gm.qstamp, gm.sstamp, gm.bstamp, gm.fstamp, gm.ovf_at, gm.front[0],
+  void* mem[] = {gm.tbuf[0], gm.tbuf[1], gm.texp, gm.qstamp, gm.sstamp, gm.bstamp, gm.fstamp, gm.ovf_at, gm.front[0],
                  gm.front[1], gm.slist, gm.bins, gm.far[0], gm.far[1], gm.hub};
   for (void* q : mem)
     if (q) (void)hipFree(q);
@@ -193,7 +194,7 @@ void free_handle(sssp_handle* h) {
   void* dev[] = {h->off, h->split, const_cast<uint4*>(p.rows), const_cast<uint64_t*>(p.edges),
                  p.qstamp, p.sstamp, p.bstamp, p.fstamp, p.ovf_at, p.front[0], p.front[1], p.slist, p.bins,
                  p.far[0], p.far[1], p.hub, h->ctls, h->perm, h->src_dev, const_cast<uint32_t*>(p.vid), p.tbuf[0],
-                 p.tbuf[1]};
+                 p.tbuf[1], p.texp};
   for (void* q : dev)
     if (q) (void)hipFree(q);
   if (h->src_host) (void)hipHostFree(h->src_host);
@@ -310,7 +311,9 @@ sssp_status alloc_group(sssp_handle* h, GroupMem* gm) {
   uint32_t** words[] = {&gm->qstamp, &gm->sstamp, &gm->bstamp, &gm->fstamp, &gm->ovf_at,
                         &gm->front[0], &gm->front[1], &gm->slist, &gm->far[0], &gm->far[1]};
   for (uint32_t** q : words) SSSP_TRY(dalloc(q, un));
-  for (void** q : {&gm->tbuf[0], &gm->tbuf[1]}) SSSP_TRY(hipMalloc(q, un * dist_bytes(h->wtype)));
+  // distance words are 64-bit for every type (32-bit distances carry the frontier tag)
+  for (void** q : {&gm->tbuf[0], &gm->tbuf[1]}) SSSP_TRY(hipMalloc(q, un * sizeof(uint64_t)));
+  SSSP_TRY(hipMalloc(&gm->texp, un * dist_bytes(h->wtype)));
   SSSP_TRY(dalloc(&gm->bins, un * h->p.ring));
   SSSP_TRY(dalloc(&gm->hub, 2 * static_cast<size_t>(h->p.hub_cap)));
   uint32_t* zero[] = {gm->qstamp, gm->sstamp, gm->fstamp, gm->ovf_at};
@@ -332,6 +335,7 @@ sssp_status upload_params(sssp_handle* h) {
     const GroupMem& gm = h->extra[g - 1];
     q.tbuf[0] = gm.tbuf[0];
     q.tbuf[1] = gm.tbuf[1];
+    q.texp = gm.texp;
     q.qstamp = gm.qstamp;
     q.sstamp = gm.sstamp;
     q.bstamp = gm.bstamp;
@@ -470,8 +474,9 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   uint32_t* vid = nullptr;
   SSSP_TRY(dalloc(&vid, un));
   p.vid = vid;
-  SSSP_TRY(hipMalloc(&p.tbuf[0], un * dist_bytes(g->wtype)));
-  SSSP_TRY(hipMalloc(&p.tbuf[1], un * dist_bytes(g->wtype)));
+  SSSP_TRY(hipMalloc(&p.tbuf[0], un * sizeof(uint64_t)));  // 64-bit distance words (see the kernels)
+  SSSP_TRY(hipMalloc(&p.tbuf[1], un * sizeof(uint64_t)));
+  SSSP_TRY(hipMalloc(&p.texp, un * dist_bytes(g->wtype)));
   if (g->wtype == SSSP_WEIGHT_F64) SSSP_TRY(dalloc(&h->w64, um));
   p.w64 = h->w64;
   uint32_t* build = nullptr;
@@ -569,6 +574,7 @@ sssp_status read_status(sssp_handle* h, hipStream_t s) {
     st.light_edges += c.light_edges;
     st.heavy_edges += c.heavy_edges;
     st.improvements += c.improvements;
+    st.attempts += c.attempts;
     st.barriers += c.barriers;
     st.trace_records += c.trace_len;
   }

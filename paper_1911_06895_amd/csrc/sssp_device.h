@@ -113,6 +113,7 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t* total, uin
 // weight bits.
 struct WeightU32 {
   static constexpr bool kInteger = true;
+  static constexpr bool kPacked = true;  // distance words carry the frontier tag (see dist_word)
   using T = uint32_t;
   using Wt = uint32_t;
   static constexpr T kInf = kInfU32;
@@ -127,6 +128,7 @@ struct WeightU32 {
 
 struct WeightF32 {
   static constexpr bool kInteger = false;
+  static constexpr bool kPacked = true;
   using T = uint32_t;
   using Wt = uint32_t;
   static constexpr T kInf = kInfF32;
@@ -151,6 +153,7 @@ struct WeightF32 {
 
 struct WeightF64 {
   static constexpr bool kInteger = false;
+  static constexpr bool kPacked = false;  // the distance fills the word; the frontier uses qstamp
   using T = uint64_t;
   using Wt = uint64_t;
   static constexpr T kInf = kInfF64;
@@ -171,6 +174,38 @@ struct WeightF64 {
   }
   __device__ static Wt weight(const Params& p, uint64_t, uint32_t pos) { return ldg(&p.w64[pos]); }
 };
+
+// Tentative distances are 64-bit words. For 32-bit distances (u32, fp32 bits)
+// the word is (distance << 32) | tag, where tag is the frontier tag of the
+// step that last re-inserted the vertex into the current bucket's frontier (0
+// after an update that filed it elsewhere): one 64-bit atomic min then both
+// decides the update and tells whether the vertex is already queued for the
+// next light phase. For fp64 the word is the distance alone.
+template <class W>
+__device__ inline typename W::T word_dist(uint64_t w) {
+  if constexpr (W::kPacked) return static_cast<typename W::T>(w >> 32);
+  else return w;
+}
+template <class W>
+__device__ inline uint64_t dist_word(typename W::T x, uint32_t tag) {
+  if constexpr (W::kPacked) return (static_cast<uint64_t>(x) << 32) | tag;
+  else return x;
+}
+// the distance of v, device-scope
+template <class W>
+__device__ inline typename W::T tload(const uint64_t* t, uint32_t v) {
+  return word_dist<W>(ld_agent(&t[v]));
+}
+// the distance of v through the caches (possibly stale, never below the current value)
+template <class W>
+__device__ inline typename W::T tload_cached(const uint64_t* t, uint32_t v) {
+  if constexpr (W::kPacked) return ldg(reinterpret_cast<const uint32_t*>(t) + 2 * static_cast<size_t>(v) + 1);
+  else return ldg(&t[v]);
+}
+template <class W>
+__device__ inline void tstore(uint64_t* t, uint32_t v, typename W::T x) {
+  st_agent(&t[v], dist_word<W>(x, 0u));
+}
 
 // ------------------------------------------------------------------ barrier
 

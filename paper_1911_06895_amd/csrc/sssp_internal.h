@@ -131,7 +131,7 @@ struct Ctl {
   alignas(128) uint32_t bincount[kRingMax][32];  // ring-slot sizes, one per 128-byte line ([slot][0])
   // statistics (summed over sources)
   alignas(128) unsigned long long sources, buckets, light_phases, heavy_phases, far_phases;
-  unsigned long long light_edges, heavy_edges, improvements, barriers;
+  unsigned long long light_edges, heavy_edges, improvements, attempts, barriers;
   unsigned long long adj_released;  // adjoint: vertices released (equals the reached count)
 };
 
@@ -144,7 +144,8 @@ struct Params {
   double delta_d;       // f32: (double)(float)delta; f64: delta
   double inv_delta_d;   // 1 / delta_d (an estimate; bucket indices are corrected exactly)
   const uint32_t* vid;    // [n] solver id of each caller vertex (decreasing in-degree order)
-  void* tbuf[2];          // [n] tentative distances (32- or 64-bit) in solver ids (alternating between sources)
+  void* tbuf[2];          // [n] 64-bit tentative-distance words in solver ids (alternating between sources)
+  void* texp;             // [n] distance of each vertex at its last light expansion in the current row
   const uint4* rows;      // [n] row u of the split copy: (start, end of light edges, end, 0)
   const uint64_t* edges;  // [m] (destination | weight bits << 32); fp64: destination only
   const uint64_t* w64;    // [m] fp64 weight bits at the same positions (fp64 handles)

@@ -41,7 +41,7 @@ struct Sched {
 };
 
 struct WgStats {
-  unsigned long long light_edges, heavy_edges, improvements;
+  unsigned long long light_edges, heavy_edges, improvements, attempts;
   unsigned long long step_edges, step_impr;  // since the last traced step boundary
 };
 
@@ -137,6 +137,13 @@ struct Lds {
 template <class W>
 __device__ __attribute__((always_inline)) inline Lds<W> lds() {
   return Lds<W>{lds_params<W>(), lds_sched<W>(), lds_stage<W>(), lds_stats<W>(), lds_barrier<W>(), lds_queue<W>()};
+}
+
+// The group's record of each vertex's distance at its last light expansion in
+// the current row (kInf: not expanded yet); typed like the distances.
+template <class W>
+__device__ __attribute__((always_inline)) inline typename W::T* texp(const Params& p) {
+  return static_cast<typename W::T*>(p.texp);
 }
 
 __device__ inline void count_add(unsigned long long* field, unsigned long long v) {
@@ -374,23 +381,43 @@ __device__ void stage_flush_now(uint32_t n) {
 
 // The atomic part for kILP candidates per lane (their atomics overlap in flight).
 template <class W>
-__device__ inline void relax_candidates(typename W::T* t, const bool (&active)[kILP],
+__device__ inline void relax_candidates(uint64_t* t, const bool (&active)[kILP],
                                         const typename W::T (&cand)[kILP], const uint32_t (&v)[kILP],
                                         uint64_t near_end) {
   const Lds<W> L = lds<W>();
   const Params& p = L.p;
   const Sched& s = L.s;
   bool win[kILP];
+  uint32_t jj[kILP];
+  uint64_t old[kILP];
+  if constexpr (W::kPacked) {
+    // the word carries the frontier tag: one atomic decides the update and the re-insertion
 #pragma unroll
-  for (uint32_t q = 0; q < kILP; ++q) win[q] = active[q] && cand[q] < g_min(&t[v[q]], cand[q]);
+    for (uint32_t q = 0; q < kILP; ++q) jj[q] = active[q] ? W::bucket(cand[q], p) : kNone;
+#pragma unroll
+    for (uint32_t q = 0; q < kILP; ++q) {
+      const uint32_t tag = jj[q] <= s.bucket ? s.step + 1u : 0u;
+      old[q] = active[q] ? g_min(&t[v[q]], dist_word<W>(cand[q], tag)) : 0ull;
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < kILP; ++q) win[q] = active[q] && cand[q] < word_dist<W>(old[q]);
+  } else {
+#pragma unroll
+    for (uint32_t q = 0; q < kILP; ++q) win[q] = active[q] && cand[q] < g_min(&t[v[q]], cand[q]);
+#pragma unroll
+    for (uint32_t q = 0; q < kILP; ++q) jj[q] = win[q] ? W::bucket(cand[q], p) : kNone;
+  }
   uint32_t slot[kILP];
 #pragma unroll
   for (uint32_t q = 0; q < kILP; ++q) {
     slot[q] = kNoSlot;
     if (win[q]) {
-      const uint32_t j = W::bucket(cand[q], p);
+      const uint32_t j = jj[q];
       if (j <= s.bucket) {
-        if (g_exch(&p.qstamp[v[q]], s.step + 1u) != s.step + 1u) slot[q] = kSlotFront;
+        bool first;
+        if constexpr (W::kPacked) first = static_cast<uint32_t>(old[q]) != s.step + 1u;
+        else first = g_exch(&p.qstamp[v[q]], s.step + 1u) != s.step + 1u;
+        if (first) slot[q] = kSlotFront;
       } else if (j < near_end) {
         if (g_min(&p.bstamp[v[q]], j) > j) slot[q] = j & p.ring_mask;
       } else {
@@ -399,14 +426,16 @@ __device__ inline void relax_candidates(typename W::T* t, const bool (&active)[k
       }
     }
   }
-  uint32_t nwin = 0;
+  uint32_t nwin = 0, natt = 0;
 #pragma unroll
   for (uint32_t q = 0; q < kILP; ++q) {
     nwin += static_cast<uint32_t>(__popcll(__ballot(win[q])));
+    natt += static_cast<uint32_t>(__popcll(__ballot(active[q])));
     stage_push<W>(slot[q] != kNoSlot, slot[q], v[q]);
   }
   if (lane() == 0) {
     count_add(&L.st.improvements, nwin);
+    count_add(&L.st.attempts, natt);
     count_add(&L.st.step_impr, nwin);
   }
 }
@@ -432,7 +461,7 @@ __device__ inline bool queue_push(bool pass, uint32_t v, uint64_t c) {
 
 // The prefilter for kILP requests (v, t(u) (+) w) per lane.
 template <class W>
-__device__ inline void relax_batch(typename W::T* t, const bool (&active)[kILP], const typename W::T (&tu)[kILP],
+__device__ inline void relax_batch(uint64_t* t, const bool (&active)[kILP], const typename W::T (&tu)[kILP],
                                    const uint32_t (&v)[kILP], const typename W::Wt (&w)[kILP], uint64_t near_end) {
   const Lds<W> L = lds<W>();
   using T = typename W::T;
@@ -446,7 +475,7 @@ __device__ inline void relax_batch(typename W::T* t, const bool (&active)[kILP],
       st_agent(&p.ovf_at[v[q]], 1u);
       st_agent(&p.ctl->ovf_seen, 1u);
     }
-    tv[q] = ok[q] ? ldg(&t[v[q]]) : T(0);  // may be stale, but never below the current value
+    tv[q] = ok[q] ? tload_cached<W>(t, v[q]) : T(0);  // may be stale, but never below the current value
   }
   bool direct[kILP];
   bool any = false;
@@ -480,7 +509,7 @@ __device__ inline void stage_room() {
 // Relax the `queued` candidates (read with read_counts) and empty the queue.
 // All threads call it; the staging has room for W::kQueue appends.
 template <class W>
-__device__ void drain_queue(typename W::T* t, uint64_t near_end, uint32_t queued) {
+__device__ void drain_queue(uint64_t* t, uint64_t near_end, uint32_t queued) {
   const Lds<W> L = lds<W>();
   using T = typename W::T;
   static_assert(W::kQueue <= W::kWG * kILP, "one pass drains the queue");
@@ -508,7 +537,7 @@ __device__ void drain_queue(typename W::T* t, uint64_t near_end, uint32_t queued
 // so fewer later requests pass the prefilter only to lose), and with `force`
 // (the end of a step) drain and flush everything.
 template <class W>
-__device__ inline void round_end(typename W::T* t, uint64_t near_end, bool force) {
+__device__ inline void round_end(uint64_t* t, uint64_t near_end, bool force) {
   uint32_t staged, queued;
   read_counts<W>(&staged, &queued);
   if (staged > W::kStage - W::kWG * kILP - W::kQueue) {
@@ -604,11 +633,12 @@ template <class T>
 struct Entry {
   uint32_t u;
   T tu;
+  T te;  // the vertex's distance at its last light expansion (light steps)
   uint4 row;
 };
 
 template <class W>
-__device__ void hub_pieces(typename W::T* t, bool light);
+__device__ void hub_pieces(uint64_t* t, bool light);
 
 // One relaxation phase: every vertex u of the input list sends t(u) (+) w along
 // its light (kLight) or heavy out-edges -- the masked min-plus product
@@ -619,7 +649,7 @@ __device__ void hub_pieces(typename W::T* t, bool light);
 // consecutive lanes read consecutive edges of a row. Vertices with hub_edges
 // or more edges are queued as pieces for a grid-wide hub step instead.
 template <class W, bool kLight>
-__device__ __attribute__((always_inline)) void phase(typename W::T* t, bool solo, bool preloaded = false,
+__device__ __attribute__((always_inline)) void phase(uint64_t* t, bool solo, bool preloaded = false,
                                                      Entry<typename W::T> pre = Entry<typename W::T>{}) {
   using T = typename W::T;
   const Lds<W> L = lds<W>();
@@ -649,13 +679,24 @@ __device__ __attribute__((always_inline)) void phase(typename W::T* t, bool solo
     bool take = false;
     if (threadIdx.x < chunk && k < count) {
       u = preloaded ? pre.u : ld_agent(&list[k]);
-      tu = preloaded ? pre.tu : ld_agent(&t[u]);
-      // a ring slot may hold vertices that have since moved to a lower bucket
-      take = !from_bin || in_bucket<W>(tu, s, p);
+      T te = W::kInf;
+      if (preloaded) {
+        tu = pre.tu;
+        te = pre.te;
+      } else {
+        tu = tload<W>(t, u);
+        if (kLight && !from_bin) te = ld_agent(&texp<W>(p)[u]);
+      }
+      // a ring slot may hold vertices that have since moved to a lower bucket; a frontier vertex
+      // whose light edges were already relaxed with its current distance has nothing new to send
+      // (a ring-slot entry is the vertex's first expansion in the bucket: a frontier entry of the
+      // same bucket always carries a lower distance, so ring-slot expansions need no record)
+      take = from_bin ? in_bucket<W>(tu, s, p) : (!kLight || tu != te);
       if (take) {
         const uint4 row = preloaded ? pre.row : ldg(&p.rows[u]);
         beg = kLight ? row.x : row.y;
         deg = (kLight ? row.y : row.z) - beg;
+        if (kLight && !from_bin) st_agent(&texp<W>(p)[u], tu);
       }
     }
     if (kLight && !p.no_heavy) {  // S = (S + t_Bi) > 0: each expanded vertex joins S once per round
@@ -738,7 +779,7 @@ __device__ __attribute__((always_inline)) void phase(typename W::T* t, bool solo
 // that their workgroups do not save and restore registers around a call at
 // every step.
 template <class W, bool kLight>
-__device__ __attribute__((noinline)) void phase_solo(typename W::T* t, Entry<typename W::T> pre) {
+__device__ __attribute__((noinline)) void phase_solo(uint64_t* t, Entry<typename W::T> pre) {
   phase<W, kLight>(t, true, true, pre);
 }
 
@@ -749,7 +790,7 @@ __device__ __attribute__((noinline)) void phase_solo(typename W::T* t, Entry<typ
 // work of the next light phase (relaxations commute, and the phase's
 // re-insertions are simply found one phase later).
 template <class W>
-__device__ void hub_pieces(typename W::T* t, bool light) {
+__device__ void hub_pieces(uint64_t* t, bool light) {
   const Lds<W> L = lds<W>();
   using T = typename W::T;
   const Params& p = L.p;
@@ -773,7 +814,7 @@ __device__ void hub_pieces(typename W::T* t, bool light) {
       const uint32_t u = static_cast<uint32_t>(rec);
       const uint32_t piece = static_cast<uint32_t>(rec >> 32);
       const uint4 row = ldg(&p.rows[u]);
-      const T tu = ld_agent(&t[u]);
+      const T tu = tload<W>(t, u);
       rec = nc < count ? ld_agent(&queue[nc]) : 0ull;
       const uint32_t b = light ? row.x : row.y;
       const uint32_t e = light ? row.y : row.z;
@@ -811,7 +852,7 @@ __device__ void hub_pieces(typename W::T* t, bool light) {
 // Far-list redistribution: far vertices whose bucket is now within the ring
 // move into it; the rest move to the other far list.
 template <class W>
-__device__ void far_step(typename W::T* t) {
+__device__ void far_step(uint64_t* t) {
   const Lds<W> L = lds<W>();
   const Params& p = L.p;
   const Sched& s = L.s;
@@ -829,7 +870,7 @@ __device__ void far_step(typename W::T* t) {
       v = ld_agent(&list[k]);
       // still only filed far (never moved into the ring since)?
       if (ld_agent(&p.bstamp[v]) == kNone) {
-        j = W::bucket(ld_agent(&t[v]), p);
+        j = W::bucket(tload<W>(t, v), p);
         if (j < near_end) {
           to_ring = g_min(&p.bstamp[v], j) > j;
         } else {
@@ -846,12 +887,12 @@ __device__ void far_step(typename W::T* t) {
 // A candidate that did not fit marked its target; the distance of that target
 // is unrepresentable exactly when no other path reached it.
 template <class W>
-__device__ void overflow_step(typename W::T* t) {
+__device__ void overflow_step(uint64_t* t) {
   const Lds<W> L = lds<W>();
   const Params& p = L.p;
   for (uint32_t v = grp_rank(p) * W::kWG + threadIdx.x; v < p.n; v += grp_size(p) * W::kWG) {
     if (ld_agent(&p.ovf_at[v])) {
-      if (ld_agent(&t[v]) == W::kInf) st_agent(&p.ctl->ovf_real, 1u);
+      if (tload<W>(t, v) == W::kInf) st_agent(&p.ctl->ovf_real, 1u);
       st_agent(&p.ovf_at[v], 0u);
     }
   }
@@ -913,7 +954,7 @@ __device__ void choose_next(const Counters& k, uint32_t from, uint32_t len, uint
 // is left in *s and published. `reset_tags`: the group's stamps were just
 // cleared, so the de-duplication tags restart.
 template <class W>
-__device__ void leader_start(typename W::T* t, const int32_t* seeds, int nseeds, bool reset_tags) {
+__device__ void leader_start(uint64_t* t, const int32_t* seeds, int nseeds, bool reset_tags) {
   const Lds<W> L = lds<W>();
   const Params& p = L.p;
   Sched* s = &L.s;
@@ -953,7 +994,7 @@ __device__ void leader_start(typename W::T* t, const int32_t* seeds, int nseeds,
       continue;
     }
     const uint32_t u = ldg(&p.vid[src]);
-    st_agent(&t[u], typename W::T(0));
+    tstore<W>(t, u, typename W::T(0));
     if (g_min(&p.bstamp[u], 0u) != 0u) st_agent(&p.bins[g_add(&c->bincount[0][0], 1u)], u);
   }
   drain_stores();
@@ -1074,7 +1115,7 @@ __device__ void after_step() {
 // Edges a light or heavy step would scan (its list has at most inline_cap <= kChunk entries);
 // each thread keeps its entry for the phase that may follow on this workgroup.
 template <bool kLight, class W>
-__device__ uint32_t step_edges(const typename W::T* t, uint32_t* s_wsum, Entry<typename W::T>* e) {
+__device__ uint32_t step_edges(const uint64_t* t, uint32_t* s_wsum, Entry<typename W::T>* e) {
   const Lds<W> L = lds<W>();
   const Params& p = L.p;
   const Sched& s = L.s;
@@ -1082,9 +1123,11 @@ __device__ uint32_t step_edges(const typename W::T* t, uint32_t* s_wsum, Entry<t
   uint32_t deg = 0;
   if (threadIdx.x < s.in_count) {
     e->u = ld_agent(&list[threadIdx.x]);
-    e->tu = ld_agent(&t[e->u]);
+    e->tu = tload<W>(t, e->u);
+    e->te = kLight && s.in_kind != kInBin ? ld_agent(&texp<W>(p)[e->u]) : W::kInf;
     e->row = ldg(&p.rows[e->u]);
     deg = kLight ? e->row.y - e->row.x : e->row.z - e->row.y;
+    if (kLight && e->tu == e->te) deg = 0;  // nothing new to send (the phase skips it)
   }
   uint32_t total;
   (void)block_exclusive_scan<W::kWG>(deg, &total, s_wsum);
@@ -1094,7 +1137,7 @@ __device__ uint32_t step_edges(const typename W::T* t, uint32_t* s_wsum, Entry<t
 // The leader's part of a barrier: schedule the step after `s`; while that step
 // is a small light or heavy phase, run it on this workgroup alone and schedule again.
 template <class W>
-__device__ void lead(typename W::T* t, bool schedule_first) {
+__device__ void lead(uint64_t* t, bool schedule_first) {
   const Lds<W> L = lds<W>();
   const Params& p = L.p;
   Sched* s = &L.s;
@@ -1123,7 +1166,7 @@ __device__ void lead(typename W::T* t, bool schedule_first) {
 // the batch and initialise its solve, or mark the group finished. A row is one
 // source, or (multi) all k sources at once in a single row.
 template <class W>
-__device__ void leader_claim(typename W::T* t, const int32_t* sources, int k, int multi, bool reset_tags) {
+__device__ void leader_claim(uint64_t* t, const int32_t* sources, int k, int multi, bool reset_tags) {
   const Lds<W> L = lds<W>();
   const Params& p = L.p;
   __shared__ uint32_t s_row;
@@ -1152,7 +1195,7 @@ __global__ __launch_bounds__(W::kWG, 4) void solver_kernel(const Params* __restr
     L.p = params[blockIdx.x % groups];
     L.sg.n = 0;
     L.q.n = 0;
-    L.st = WgStats{0, 0, 0, 0, 0};
+    L.st = WgStats{0, 0, 0, 0, 0, 0};
   }
   __syncthreads();
   const Params& p = L.p;
@@ -1169,9 +1212,10 @@ __global__ __launch_bounds__(W::kWG, 4) void solver_kernel(const Params* __restr
                             ld_agent(&c->far_epoch) > kEpochLimit;
     // distances live in solver ids; a group's consecutive sources alternate
     // buffers so that copying out one row never races with initialising the next
-    T* t = static_cast<T*>(p.tbuf[it & 1]);
+    uint64_t* t = static_cast<uint64_t*>(p.tbuf[it & 1]);
     for (uint32_t v = rank * W::kWG + threadIdx.x; v < p.n; v += size * W::kWG) {
-      st_agent(&t[v], W::kInf);
+      tstore<W>(t, v, W::kInf);
+      st_agent(&texp<W>(p)[v], W::kInf);
       st_agent(&p.bstamp[v], kNone);
       if (reset_tags) {
         st_agent(&p.qstamp[v], 0u);
@@ -1200,7 +1244,8 @@ __global__ __launch_bounds__(W::kWG, 4) void solver_kernel(const Params* __restr
     }
     if (alive) {  // the source's row of the output, in the caller's vertex numbering
       T* out = static_cast<T*>(dist) + static_cast<size_t>(row) * p.n;
-      for (uint32_t v = rank * W::kWG + threadIdx.x; v < p.n; v += size * W::kWG) *gp(&out[v]) = ld_agent(&t[ldg(&p.vid[v])]);
+      for (uint32_t v = rank * W::kWG + threadIdx.x; v < p.n; v += size * W::kWG)
+        *gp(&out[v]) = tload<W>(t, ldg(&p.vid[v]));
     }
   }
   // add this workgroup's counters to the group's control block
@@ -1209,6 +1254,7 @@ __global__ __launch_bounds__(W::kWG, 4) void solver_kernel(const Params* __restr
     if (L.st.light_edges) g_add(&c->light_edges, L.st.light_edges);
     if (L.st.heavy_edges) g_add(&c->heavy_edges, L.st.heavy_edges);
     if (L.st.improvements) g_add(&c->improvements, L.st.improvements);
+    if (L.st.attempts) g_add(&c->attempts, L.st.attempts);
   }
 }
 
@@ -1235,7 +1281,7 @@ __global__ void ctl_reset_kernel(Ctl* ctls, uint32_t groups, int reset_epochs, u
   c->wait_ticks = wait_ticks;
   c->source_index = kNone;
   c->sources = c->buckets = c->light_phases = c->heavy_phases = c->far_phases = 0;
-  c->light_edges = c->heavy_edges = c->improvements = c->barriers = 0;
+  c->light_edges = c->heavy_edges = c->improvements = c->attempts = c->barriers = 0;
   c->adj_released = 0;
   if (reset_epochs) {
     c->step = 0;

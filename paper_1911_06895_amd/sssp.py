@@ -41,7 +41,7 @@ class SsspGraph(ctypes.Structure):
 class SsspStats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint64) for name in
                 ("sources", "buckets", "light_phases", "heavy_phases", "far_phases", "light_edges", "heavy_edges",
-                 "improvements", "barriers", "trace_records")]
+                 "improvements", "attempts", "barriers", "trace_records")]
 
 
 TUNING_FIELDS = ("workgroups_per_cu", "ring_buckets", "inline_edges", "concurrent_sources", "wait_limit_ms",
