@@ -306,13 +306,15 @@ __device__ bool grid_sync(Ctl* c, uint32_t size, uint32_t rank, BarrierState& b,
   }
   __syncthreads();
   if (s_is_leader) {
+    if (threadIdx.x == 0) g_add(&c->barriers, 1ull);  // completes with the leader's own stores below
     leader();
     drain_stores();
     __syncthreads();
     if (threadIdx.x == 0) {
-      g_add(&c->barriers, 1ull);
-      record_trace(c, b.trace, 0u);
-      drain_stores();
+      if (b.trace) {
+        record_trace(c, b.trace, 0u);
+        drain_stores();
+      }
       st_agent(&c->bar_gen, gen + 1u);
     }
   }

@@ -98,6 +98,7 @@ struct Ctl {
   alignas(128) uint32_t hub_parent;  // action of the phase that queued them
   uint32_t hub_backlog;  // pieces to process (a hub step, or a light phase finishing the previous one's)
   uint32_t hub_in;       // queue buffer holding them; a phase appends to the other one
+  uint32_t redo;         // the current round repeats its bucket (fp32 heavy requests fell back into it)
   // schedule
   alignas(128) uint32_t action;
   uint32_t bucket;       // current bucket i

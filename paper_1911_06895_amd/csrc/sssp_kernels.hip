@@ -37,6 +37,7 @@ __device__ inline uint32_t grp_size(const Params& p) { return gridDim.x / p.grou
 struct Sched {
   uint32_t action, bucket, in_kind, in_count, out_buf, step, round, far_epoch, far_cur, far_base;
   uint32_t hub_parent, hub_backlog, hub_in;
+  uint32_t redo;  // the current round repeats its bucket (heavy requests fell back into it; fp32)
   uint64_t lo_u, hi_u;
 };
 
@@ -169,7 +170,7 @@ __device__ inline void load_sched(Ctl* c) {
                    round = ld_agent(&c->round), far_epoch = ld_agent(&c->far_epoch),
                    far_cur = ld_agent(&c->far_cur), far_base = ld_agent(&c->far_base),
                    hub_parent = ld_agent(&c->hub_parent), hub_backlog = ld_agent(&c->hub_backlog),
-                   hub_in = ld_agent(&c->hub_in);
+                   hub_in = ld_agent(&c->hub_in), redo = ld_agent(&c->redo);
     const uint64_t lo_u = ld_agent(&c->lo_u), hi_u = ld_agent(&c->hi_u);
     s->action = action;
     s->bucket = bucket;
@@ -184,6 +185,7 @@ __device__ inline void load_sched(Ctl* c) {
     s->hub_parent = hub_parent;
     s->hub_backlog = hub_backlog;
     s->hub_in = hub_in;
+    s->redo = redo;
     s->lo_u = lo_u;
     s->hi_u = hi_u;
   }
@@ -205,6 +207,7 @@ __device__ inline void publish_sched(Ctl* c, const Sched& s) {
   st_agent(&c->hub_parent, s.hub_parent);
   st_agent(&c->hub_backlog, s.hub_backlog);
   st_agent(&c->hub_in, s.hub_in);
+  st_agent(&c->redo, s.redo);
   st_agent(&c->lo_u, s.lo_u);
   st_agent(&c->hi_u, s.hi_u);
 }
@@ -475,8 +478,10 @@ __device__ inline void relax_batch(uint64_t* t, const bool (&active)[kILP], cons
       st_agent(&p.ovf_at[v[q]], 1u);
       st_agent(&p.ctl->ovf_seen, 1u);
     }
-    tv[q] = ok[q] ? tload_cached<W>(t, v[q]) : T(0);  // may be stale, but never below the current value
   }
+#pragma unroll
+  for (uint32_t q = 0; q < kILP; ++q)
+    tv[q] = ok[q] ? tload_cached<W>(t, v[q]) : T(0);  // may be stale, but never below the current value
   bool direct[kILP];
   bool any = false;
 #pragma unroll
@@ -676,10 +681,10 @@ __device__ __attribute__((always_inline)) void phase(uint64_t* t, bool solo, boo
     const uint32_t k = c * chunk + threadIdx.x;
     uint32_t beg = 0, deg = 0, u = 0;
     T tu = W::kInf;
+    T te = W::kInf;
     bool take = false;
     if (threadIdx.x < chunk && k < count) {
       u = preloaded ? pre.u : ld_agent(&list[k]);
-      T te = W::kInf;
       if (preloaded) {
         tu = pre.tu;
         te = pre.te;
@@ -689,23 +694,26 @@ __device__ __attribute__((always_inline)) void phase(uint64_t* t, bool solo, boo
       }
       // a ring slot may hold vertices that have since moved to a lower bucket; a frontier vertex
       // whose light edges were already relaxed with its current distance has nothing new to send
-      // (a ring-slot entry is the vertex's first expansion in the bucket: a frontier entry of the
-      // same bucket always carries a lower distance, so ring-slot expansions need no record)
+      // (a ring-slot entry is the vertex's first expansion in the bucket)
       take = from_bin ? in_bucket<W>(tu, s, p) : (!kLight || tu != te);
       if (take) {
         const uint4 row = preloaded ? pre.row : ldg(&p.rows[u]);
         beg = kLight ? row.x : row.y;
         deg = (kLight ? row.y : row.z) - beg;
-        if (kLight && !from_bin) st_agent(&texp<W>(p)[u], tu);
+        if (kLight) st_agent(&texp<W>(p)[u], tu);
       }
     }
     if (kLight && !p.no_heavy) {  // S = (S + t_Bi) > 0: each expanded vertex joins S once per round
       bool to_s = false;
       if (take) {
-        if (from_bin) {  // the first phase of a round: ring-slot entries are distinct and new to S
-          st_agent(&p.sstamp[u], s.round);
+        if (from_bin) {  // the first phase of a bucket: ring-slot entries are distinct and new to S
           to_s = true;
-        } else if (ld_agent(&p.sstamp[u]) != s.round) {
+        } else if (!s.redo) {
+          // in the bucket's first round a vertex joins S at its first light expansion in the row:
+          // an earlier expansion (recorded) can only have been in this bucket, since distances
+          // only decrease and earlier buckets are settled
+          to_s = te == W::kInf;
+        } else if (ld_agent(&p.sstamp[u]) != s.round) {  // a repeated round (fp32): S starts empty
           to_s = g_exch(&p.sstamp[u], s.round) != s.round;
         }
       }
@@ -938,6 +946,7 @@ __device__ void choose_next(const Counters& k, uint32_t from, uint32_t len, uint
     } else {  // B_i = {v : i*delta <= t(v) < (i+1)*delta} for the smallest non-empty i
       set_bucket<W>(jn);
       s->action = kActLight;
+      s->redo = 0u;
       s->in_kind = kInBin;
       s->in_count = k.bins[jn & p.ring_mask];
       s->out_buf = 0u;
@@ -1082,6 +1091,7 @@ __device__ void after_step() {
           n.in_kind = o.out_buf;
           n.in_count = n_redo;
           n.out_buf = 1u - o.out_buf;
+          n.redo = 1u;
         } else {
           next = 1;
         }
