@@ -11,7 +11,7 @@ constexpr int kWGGroups = 512;         // default solver workgroup: 8 wave64s, t
 constexpr int kAuxWG = 256;            // workgroup of the create-time kernels
 constexpr uint32_t kChunk = 512;       // most list entries a workgroup expands at a time (LDS tile bound)
 constexpr uint32_t kMinChunk = 32;     // fewest list entries per claimed chunk
-constexpr uint32_t kILP = 4;           // edges per lane in flight
+constexpr uint32_t kILP = 2;           // edges per lane per round (2 measured faster than 3, 4 and 8)
 constexpr uint32_t kPieceMin = kWGGroups * kILP;  // edges of the smaller hub piece (one round of a workgroup)
 constexpr uint32_t kHub = 1024;        // default: a vertex with at least this many edges in a phase goes to the hub step
 constexpr uint32_t kHubMin = 256;      // smallest hub threshold a tuning may set (sizes the hub queues)

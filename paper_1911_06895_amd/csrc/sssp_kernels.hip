@@ -81,7 +81,7 @@ template <class Wt, uint32_t WG>
 struct Cfg : Wt {
   static constexpr uint32_t kWG = WG;
   static constexpr uint32_t kPiece = WG * kILP;  // edges of one hub piece (one round of a workgroup)
-  static constexpr uint32_t kQueue = 2 * WG;     // LDS candidates; drained once a quarter full
+  static constexpr uint32_t kQueue = WG;         // LDS candidates (one per thread); drained once a quarter full
   // LDS staging for list appends: room for a round and a drain above the flush threshold
   static constexpr uint32_t kStage = WG * kILP + kQueue + 2048;
 };
