@@ -227,9 +227,6 @@ bool small_workgroups(const sssp_handle* h, uint32_t groups, int multi) {
   return groups > 1 || h->tuning.workgroups_per_cu != 1;
 }
 
-// Bytes of one distance (and one weight) of the handle's type.
-size_t dist_bytes(int32_t wtype) { return wtype == SSSP_WEIGHT_F64 ? 8 : 4; }
-
 // A weight (as bits) and delta as doubles (exact for every type).
 double weight_of(const sssp_handle* h, uint64_t bits) {
   if (h->wtype == SSSP_WEIGHT_U32) return static_cast<double>(bits);
@@ -313,7 +310,7 @@ sssp_status alloc_group(sssp_handle* h, GroupMem* gm) {
   for (uint32_t** q : words) SSSP_TRY(dalloc(q, un));
   // distance words are 64-bit for every type (32-bit distances carry the frontier tag)
   for (void** q : {&gm->tbuf[0], &gm->tbuf[1]}) SSSP_TRY(hipMalloc(q, un * sizeof(uint64_t)));
-  SSSP_TRY(hipMalloc(&gm->texp, un * dist_bytes(h->wtype)));
+  if (h->wtype == SSSP_WEIGHT_F64) SSSP_TRY(hipMalloc(&gm->texp, un * sizeof(uint64_t)));  // fp64 only
   SSSP_TRY(dalloc(&gm->bins, un * h->p.ring));
   SSSP_TRY(dalloc(&gm->hub, 2 * static_cast<size_t>(h->p.hub_cap)));
   uint32_t* zero[] = {gm->qstamp, gm->sstamp, gm->fstamp, gm->ovf_at};
@@ -476,7 +473,7 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
   p.vid = vid;
   SSSP_TRY(hipMalloc(&p.tbuf[0], un * sizeof(uint64_t)));  // 64-bit distance words (see the kernels)
   SSSP_TRY(hipMalloc(&p.tbuf[1], un * sizeof(uint64_t)));
-  SSSP_TRY(hipMalloc(&p.texp, un * dist_bytes(g->wtype)));
+  if (g->wtype == SSSP_WEIGHT_F64) SSSP_TRY(hipMalloc(&p.texp, un * sizeof(uint64_t)));  // fp64 only
   if (g->wtype == SSSP_WEIGHT_F64) SSSP_TRY(dalloc(&h->w64, um));
   p.w64 = h->w64;
   uint32_t* build = nullptr;

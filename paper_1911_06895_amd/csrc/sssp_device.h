@@ -54,6 +54,12 @@ template <typename T, typename U>
 __device__ inline T g_exch(T* p, U v) {
   return __hip_atomic_exchange(gp(p), static_cast<T>(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// compare-and-swap; returns true when *p held `expected` and now holds `desired`
+template <typename T>
+__device__ inline bool g_cas(T* p, T expected, T desired) {
+  return __hip_atomic_compare_exchange_strong(gp(p), &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // number of set bits of `mask` in lanes below this one
 __device__ inline uint32_t lanes_below(uint64_t mask) {
@@ -176,11 +182,18 @@ struct WeightF64 {
 };
 
 // Tentative distances are 64-bit words. For 32-bit distances (u32, fp32 bits)
-// the word is (distance << 32) | tag, where tag is the frontier tag of the
-// step that last re-inserted the vertex into the current bucket's frontier (0
-// after an update that filed it elsewhere): one 64-bit atomic min then both
-// decides the update and tells whether the vertex is already queued for the
-// next light phase. For fp64 the word is the distance alone.
+// the word is (distance << 32) | tag. The tag names the step whose frontier
+// last received the vertex in the current bucket: (step << 1) | 1 when queued,
+// (step << 1) once the vertex has been expanded at this very distance while
+// queued (its queued entry then has nothing new to send), 0 after an update
+// that filed it elsewhere. One 64-bit atomic min both decides an update and
+// tells whether the vertex is already queued for the next light phase; at an
+// equal distance a candidate (queued tag) never replaces a word, since the
+// expanded form of the same step sorts below it and earlier steps sort lower
+// still. For fp64 the word is the distance alone.
+__device__ inline uint32_t queued_tag(uint32_t step) { return (step << 1) | 1u; }
+__device__ inline uint32_t tag_step(uint32_t tag) { return tag >> 1; }
+__device__ inline bool tag_expanded(uint32_t tag) { return (tag & 1u) == 0u; }
 template <class W>
 __device__ inline typename W::T word_dist(uint64_t w) {
   if constexpr (W::kPacked) return static_cast<typename W::T>(w >> 32);

@@ -146,7 +146,7 @@ struct Params {
   double inv_delta_d;   // 1 / delta_d (an estimate; bucket indices are corrected exactly)
   const uint32_t* vid;    // [n] solver id of each caller vertex (decreasing in-degree order)
   void* tbuf[2];          // [n] 64-bit tentative-distance words in solver ids (alternating between sources)
-  void* texp;             // [n] distance of each vertex at its last light expansion in the current row
+  void* texp;             // fp64: [n] distance of each vertex at its last light expansion in the current row
   const uint4* rows;      // [n] row u of the split copy: (start, end of light edges, end, 0)
   const uint64_t* edges;  // [m] (destination | weight bits << 32); fp64: destination only
   const uint64_t* w64;    // [m] fp64 weight bits at the same positions (fp64 handles)

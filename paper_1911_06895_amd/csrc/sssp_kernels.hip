@@ -53,6 +53,11 @@ constexpr uint32_t kSlotFar = kRingMax + 1;   // the far list
 constexpr uint32_t kSlotS = kRingMax + 2;     // S, the vertices expanded in this bucket
 constexpr uint32_t kSlots = kRingMax + 3;     // ring slots 0..kRingMax-1, then the three above
 constexpr uint32_t kNoSlot = 0xFFu;
+// A frontier-list entry is a vertex id (below 2^31), for 32-bit distances with
+// this bit set when the update that queued it brought the vertex into the
+// current bucket from above: its first entry in the bucket, which makes it a
+// member of S.
+constexpr uint32_t kFreshBit = 0x80000000u;
 
 template <uint32_t N>
 struct Stage {
@@ -156,6 +161,14 @@ template <class W>
 __device__ inline bool in_bucket(typename W::T x, const Sched& s, const Params& p) {
   if constexpr (W::kInteger) return x >= s.lo_u && x < s.hi_u;
   else return W::bucket(x, p) == s.bucket;
+}
+
+// x lies above the current bucket i ((i+1)*delta <= x), or is unreachable
+template <class W>
+__device__ inline bool above_bucket(typename W::T x, const Sched& s, const Params& p) {
+  if (x == W::kInf) return true;
+  if constexpr (W::kInteger) return x >= s.hi_u;
+  else return W::bucket(x, p) > s.bucket;
 }
 
 // Every workgroup's copy of the schedule the leader published. The loads are
@@ -399,28 +412,37 @@ __device__ inline void relax_candidates(uint64_t* t, const bool (&active)[kILP],
     for (uint32_t q = 0; q < kILP; ++q) jj[q] = active[q] ? W::bucket(cand[q], p) : kNone;
 #pragma unroll
     for (uint32_t q = 0; q < kILP; ++q) {
-      const uint32_t tag = jj[q] <= s.bucket ? s.step + 1u : 0u;
+      const uint32_t tag = jj[q] <= s.bucket ? queued_tag(s.step + 1u) : 0u;
       old[q] = active[q] ? g_min(&t[v[q]], dist_word<W>(cand[q], tag)) : 0ull;
     }
 #pragma unroll
     for (uint32_t q = 0; q < kILP; ++q) win[q] = active[q] && cand[q] < word_dist<W>(old[q]);
   } else {
 #pragma unroll
-    for (uint32_t q = 0; q < kILP; ++q) win[q] = active[q] && cand[q] < g_min(&t[v[q]], cand[q]);
+    for (uint32_t q = 0; q < kILP; ++q) old[q] = active[q] ? g_min(&t[v[q]], cand[q]) : 0ull;
+#pragma unroll
+    for (uint32_t q = 0; q < kILP; ++q) win[q] = active[q] && cand[q] < old[q];
 #pragma unroll
     for (uint32_t q = 0; q < kILP; ++q) jj[q] = win[q] ? W::bucket(cand[q], p) : kNone;
   }
-  uint32_t slot[kILP];
+  uint32_t slot[kILP], entry[kILP];
 #pragma unroll
   for (uint32_t q = 0; q < kILP; ++q) {
     slot[q] = kNoSlot;
+    entry[q] = v[q];
     if (win[q]) {
       const uint32_t j = jj[q];
       if (j <= s.bucket) {
         bool first;
-        if constexpr (W::kPacked) first = static_cast<uint32_t>(old[q]) != s.step + 1u;
+        if constexpr (W::kPacked) first = tag_step(static_cast<uint32_t>(old[q])) != s.step + 1u;
         else first = g_exch(&p.qstamp[v[q]], s.step + 1u) != s.step + 1u;
-        if (first) slot[q] = kSlotFront;
+        if (first) {
+          slot[q] = kSlotFront;
+          // (32-bit distances: the update and the re-insertion test are one atomic, so the entry
+          // that makes the re-insertion is the one whose update saw the vertex above the bucket)
+          if constexpr (W::kPacked)
+            if (above_bucket<W>(word_dist<W>(old[q]), s, p)) entry[q] |= kFreshBit;
+        }
       } else if (j < near_end) {
         if (g_min(&p.bstamp[v[q]], j) > j) slot[q] = j & p.ring_mask;
       } else {
@@ -434,7 +456,7 @@ __device__ inline void relax_candidates(uint64_t* t, const bool (&active)[kILP],
   for (uint32_t q = 0; q < kILP; ++q) {
     nwin += static_cast<uint32_t>(__popcll(__ballot(win[q])));
     natt += static_cast<uint32_t>(__popcll(__ballot(active[q])));
-    stage_push<W>(slot[q] != kNoSlot, slot[q], v[q]);
+    stage_push<W>(slot[q] != kNoSlot, slot[q], entry[q]);
   }
   if (lane() == 0) {
     count_add(&L.st.improvements, nwin);
@@ -633,12 +655,12 @@ __device__ inline uint32_t solo_chunk(uint32_t count) {
 }
 
 // Entry threadIdx.x of a step's input list, already loaded by the leader
-// (steps it runs alone): the vertex, its tentative distance and its row.
+// (steps it runs alone): the list entry, the vertex's distance word and row.
 template <class T>
 struct Entry {
-  uint32_t u;
-  T tu;
-  T te;  // the vertex's distance at its last light expansion (light steps)
+  uint32_t u;     // as listed (with kFreshBit)
+  uint64_t word;  // t(u) (with the frontier tag for 32-bit distances)
+  T te;           // fp64: the distance at the vertex's last light expansion (light steps)
   uint4 row;
 };
 
@@ -681,41 +703,44 @@ __device__ __attribute__((always_inline)) void phase(uint64_t* t, bool solo, boo
     const uint32_t k = c * chunk + threadIdx.x;
     uint32_t beg = 0, deg = 0, u = 0;
     T tu = W::kInf;
-    T te = W::kInf;
-    bool take = false;
+    bool take = false, fresh = false;
     if (threadIdx.x < chunk && k < count) {
-      u = preloaded ? pre.u : ld_agent(&list[k]);
-      if (preloaded) {
-        tu = pre.tu;
-        te = pre.te;
-      } else {
-        tu = tload<W>(t, u);
-        if (kLight && !from_bin) te = ld_agent(&texp<W>(p)[u]);
-      }
+      const uint32_t listed = preloaded ? pre.u : ld_agent(&list[k]);
+      u = listed & ~kFreshBit;
+      const uint64_t word = preloaded ? pre.word : ld_agent(&t[u]);
+      tu = word_dist<W>(word);
       // a ring slot may hold vertices that have since moved to a lower bucket; a frontier vertex
       // whose light edges were already relaxed with its current distance has nothing new to send
-      // (a ring-slot entry is the vertex's first expansion in the bucket)
-      take = from_bin ? in_bucket<W>(tu, s, p) : (!kLight || tu != te);
+      if constexpr (W::kPacked) {
+        const uint32_t tag = static_cast<uint32_t>(word);
+        take = from_bin ? in_bucket<W>(tu, s, p) : (!kLight || !tag_expanded(tag));
+        fresh = kLight && !from_bin && (listed & kFreshBit) != 0u;
+        // updated earlier in this step, so queued for the next one at the distance expanded
+        // here: mark the word, and that entry is skipped unless a later update clears the mark
+        if (kLight && take && tag == queued_tag(s.step + 1u)) (void)g_cas(&t[u], word, word & ~uint64_t(1));
+      } else {
+        const T te = kLight && !from_bin ? (preloaded ? pre.te : ld_agent(&texp<W>(p)[u])) : W::kInf;
+        take = from_bin ? in_bucket<W>(tu, s, p) : (!kLight || tu != te);
+        // fp64 updates and re-insertions are separate atomics: a vertex's first entry in the
+        // bucket is recognised at its expansion instead (no expansion recorded in this row)
+        fresh = kLight && !from_bin && take && te == W::kInf;
+        if (kLight && take) st_agent(&texp<W>(p)[u], tu);
+      }
       if (take) {
         const uint4 row = preloaded ? pre.row : ldg(&p.rows[u]);
         beg = kLight ? row.x : row.y;
         deg = (kLight ? row.y : row.z) - beg;
-        if (kLight) st_agent(&texp<W>(p)[u], tu);
       }
     }
-    if (kLight && !p.no_heavy) {  // S = (S + t_Bi) > 0: each expanded vertex joins S once per round
+    if (kLight && !p.no_heavy) {  // S = (S + t_Bi) > 0: each vertex of the bucket joins S once per round
       bool to_s = false;
-      if (take) {
-        if (from_bin) {  // the first phase of a bucket: ring-slot entries are distinct and new to S
-          to_s = true;
-        } else if (!s.redo) {
-          // in the bucket's first round a vertex joins S at its first light expansion in the row:
-          // an earlier expansion (recorded) can only have been in this bucket, since distances
-          // only decrease and earlier buckets are settled
-          to_s = te == W::kInf;
-        } else if (ld_agent(&p.sstamp[u]) != s.round) {  // a repeated round (fp32): S starts empty
-          to_s = g_exch(&p.sstamp[u], s.round) != s.round;
-        }
+      if (!s.redo) {
+        // in the bucket's first round a vertex joins S once, at its first entry in the bucket:
+        // its ring-slot entry (the first phase), or the entry of the update that brought it
+        // into the bucket from above (distances only decrease; earlier buckets are settled)
+        to_s = from_bin ? take : fresh;
+      } else if (take && ld_agent(&p.sstamp[u]) != s.round) {  // a repeated round (fp32): S starts empty
+        to_s = g_exch(&p.sstamp[u], s.round) != s.round;
       }
       stage_push<W>(to_s, kSlotS, u);
       stage_room<W>();
@@ -1133,11 +1158,18 @@ __device__ uint32_t step_edges(const uint64_t* t, uint32_t* s_wsum, Entry<typena
   uint32_t deg = 0;
   if (threadIdx.x < s.in_count) {
     e->u = ld_agent(&list[threadIdx.x]);
-    e->tu = tload<W>(t, e->u);
-    e->te = kLight && s.in_kind != kInBin ? ld_agent(&texp<W>(p)[e->u]) : W::kInf;
-    e->row = ldg(&p.rows[e->u]);
+    const uint32_t u = e->u & ~kFreshBit;
+    e->word = ld_agent(&t[u]);
+    e->row = ldg(&p.rows[u]);
     deg = kLight ? e->row.y - e->row.x : e->row.z - e->row.y;
-    if (kLight && e->tu == e->te) deg = 0;  // nothing new to send (the phase skips it)
+    if (kLight && s.in_kind != kInBin) {  // nothing new to send: the phase skips it
+      if constexpr (W::kPacked) {
+        if (tag_expanded(static_cast<uint32_t>(e->word))) deg = 0;
+      } else {
+        e->te = ld_agent(&texp<W>(p)[u]);
+        if (e->word == e->te) deg = 0;
+      }
+    }
   }
   uint32_t total;
   (void)block_exclusive_scan<W::kWG>(deg, &total, s_wsum);
@@ -1225,7 +1257,7 @@ __global__ __launch_bounds__(W::kWG, 4) void solver_kernel(const Params* __restr
     uint64_t* t = static_cast<uint64_t*>(p.tbuf[it & 1]);
     for (uint32_t v = rank * W::kWG + threadIdx.x; v < p.n; v += size * W::kWG) {
       tstore<W>(t, v, W::kInf);
-      st_agent(&texp<W>(p)[v], W::kInf);
+      if constexpr (!W::kPacked) st_agent(&texp<W>(p)[v], W::kInf);
       st_agent(&p.bstamp[v], kNone);
       if (reset_tags) {
         st_agent(&p.qstamp[v], 0u);
