@@ -113,6 +113,11 @@ typedef struct {
                                 workgroups) */
   int32_t inline_entries;    /* tile schedule: most list entries of a phase that one workgroup runs alone
                                 inside the barrier, in [1, 512] (default: the chunk size) */
+  int32_t leader_chain;      /* 1: the workgroup running a light phase alone keeps the vertices it
+                                re-inserts in LDS and runs the bucket's next light phase from them at
+                                once while it stays within the two limits above (no list round trip
+                                and no barrier in between); 2: one phase at a time; 0 (default): 1 on
+                                graphs with at most 6 edges per vertex on average, else 2 */
 } sssp_tuning;
 
 typedef struct sssp_handle sssp_handle;

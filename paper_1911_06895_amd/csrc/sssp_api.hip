@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/sssp.h: argument checks, device
 // memory of a handle, the create-time validation and split, and the solve
 // launch with its status read-back.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -70,8 +71,9 @@ struct sssp_handle {
   int grid_groups = 0;  // workgroups of a launch of concurrent sources (kWGGroups threads, two per CU; 0: none)
   int cus = 0;
   int wallclock_khz = 100000;  // device wall-clock rate (wall_clock64 ticks per millisecond)
-  int occupancy = 0;
-  int occupancy_groups = 0;
+  int occupancy = 0;         // co-resident solver workgroups per CU (kWG; the lower of the two kernels)
+  int occupancy_groups = 0;  // the same for kWGGroups
+  bool chain = false;        // launch the solver whose leader chains its light steps
   sssp_tuning tuning{};
   sssp::Params p{};
   uint32_t* perm = nullptr;
@@ -118,6 +120,10 @@ struct sssp_handle {
 namespace {
 
 constexpr uint32_t kDefaultInlineEdges = 4096;
+// By default the leader chains its light steps on graphs of low mean out-degree
+// (meshes, road-like graphs: long runs of small light phases); on denser graphs
+// the chains are short and the plain kernel is as fast.
+constexpr int64_t kChainMaxMeanDegree = 6;
 constexpr int32_t kDefaultWaitLimitMs = 30000;
 
 // The tile schedule of the handle's tuning (0 fields: the defaults) in its launch parameters.
@@ -127,6 +133,7 @@ void apply_tile_tuning(sssp_handle* h) {
   h->p.hub_edges = t.hub_edges > 0 ? static_cast<uint32_t>(t.hub_edges) : sssp::kHub;
   h->p.chunk_entries = static_cast<uint32_t>(t.chunk_entries);
   h->p.inline_entries = static_cast<uint32_t>(t.inline_entries);
+  h->chain = t.leader_chain == 1 || (t.leader_chain == 0 && h->m <= kChainMaxMeanDegree * h->n);
 }
 
 // A barrier wait that sees no progress for longer than this aborts the schedule (wall-clock ticks).
@@ -385,8 +392,15 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device) == hipSuccess && khz > 0)
       h->wallclock_khz = khz;
   }
-  SSSP_TRY(sssp::solver_occupancy(g->wtype, sssp::kWG, &h->occupancy));
-  SSSP_TRY(sssp::solver_occupancy(g->wtype, sssp::kWGGroups, &h->occupancy_groups));
+  {  // both solver kernels (with and without chained steps) must fit the grid
+    int occ[4] = {0, 0, 0, 0};
+    SSSP_TRY(sssp::solver_occupancy(g->wtype, sssp::kWG, false, &occ[0]));
+    SSSP_TRY(sssp::solver_occupancy(g->wtype, sssp::kWG, true, &occ[1]));
+    SSSP_TRY(sssp::solver_occupancy(g->wtype, sssp::kWGGroups, false, &occ[2]));
+    SSSP_TRY(sssp::solver_occupancy(g->wtype, sssp::kWGGroups, true, &occ[3]));
+    h->occupancy = std::min(occ[0], occ[1]);
+    h->occupancy_groups = std::min(occ[2], occ[3]);
+  }
 
   const int64_t n = g->n, m = g->m;
   h->n = n;
@@ -544,7 +558,7 @@ sssp_status enqueue_solve(sssp_handle* h, const int32_t* sources_dev, int32_t k,
   const bool small = small_workgroups(h, groups, multi);
   SSSP_TRY(sssp::launch_solver(multi ? h->params_dev + sssp::kMaxGroups : h->params_dev, groups, h->p.wtype,
                                sources_dev, k, multi, static_cast<uint32_t*>(dist), small ? h->grid_groups : h->grid,
-                               small ? sssp::kWGGroups : sssp::kWG, s));
+                               small ? sssp::kWGGroups : sssp::kWG, h->chain, s));
   h->enq_groups = groups;
   return SSSP_OK;
 }
@@ -896,7 +910,8 @@ sssp_status sssp_last_stats(const sssp_handle* h, sssp_stats* out) {
 sssp_status sssp_set_tuning(sssp_handle* h, const sssp_tuning* t) {
   if (!h || !t) return SSSP_ERR_INVALID_ARGUMENT;
   if (t->workgroups_per_cu < 0 || t->ring_buckets < 0 || t->inline_edges < 0 || t->concurrent_sources < 0 ||
-      t->wait_limit_ms < 0 || t->hub_edges < 0 || t->chunk_entries < 0 || t->inline_entries < 0)
+      t->wait_limit_ms < 0 || t->hub_edges < 0 || t->chunk_entries < 0 || t->inline_entries < 0 ||
+      t->leader_chain < 0 || t->leader_chain > 2)
     return SSSP_ERR_INVALID_ARGUMENT;
   const auto pow2 = [](int32_t x) { return (x & (x - 1)) == 0; };
   if (t->hub_edges != 0 && (t->hub_edges < static_cast<int32_t>(sssp::kHubMin) || t->hub_edges > 65536 ||
@@ -951,6 +966,7 @@ sssp_status sssp_get_tuning(const sssp_handle* h, sssp_tuning* out) {
   const uint32_t chunk = h->p.chunk_entries ? h->p.chunk_entries : (size >= 128 ? sssp::kChunk / 2 : sssp::kChunk);
   t.chunk_entries = static_cast<int32_t>(chunk);
   t.inline_entries = static_cast<int32_t>(h->p.inline_entries ? h->p.inline_entries : chunk);
+  t.leader_chain = h->chain ? 1 : 2;
   *out = t;
   return SSSP_OK;
 }

@@ -4,8 +4,9 @@
 // workgroup size, the hub threshold, the chunk size, the largest step run by
 // one workgroup alone). sssp_autotune times solves of a sample of sources:
 // first over (delta, concurrent groups), then, on the fastest handle, over
-// each tile parameter in turn (coordinate search, keeping a value only when it
-// is at least 2 % faster than the current choice), and returns that handle.
+// each tile parameter and the chaining of the leader's light steps in turn
+// (coordinate search, keeping a value only when it is at least 2 % faster
+// than the current choice), and returns that handle.
 // Host code only, over the public entry points.
 #include <cmath>
 #include <cstring>
@@ -177,7 +178,8 @@ sssp_status sssp_autotune(const sssp_graph* g, const int32_t* sources, int32_t k
     std::vector<Knob> knobs = {{&sssp_tuning::hub_edges, {512, 2048, 4096}},
                                {&sssp_tuning::chunk_entries, {64, 128, 256, 512}},
                                {&sssp_tuning::inline_edges, {1024, 16384}},
-                               {&sssp_tuning::inline_entries, {64, 128}}};
+                               {&sssp_tuning::inline_entries, {64, 128}},
+                               {&sssp_tuning::leader_chain, {1, 2}}};
     if (res.concurrent_sources == 1) knobs.insert(knobs.begin(), Knob{&sssp_tuning::workgroups_per_cu, {1}});
     for (const Knob& kb : knobs) {
       int32_t keep = cur.*kb.field;

@@ -212,17 +212,18 @@ hipError_t launch_relabel_and_split(const int64_t* row_ptr, const int32_t* col, 
                                     int64_t n, int64_t m, uint32_t* scratch,
                                     uint32_t* new_id, uint32_t* off, uint32_t* split, uint64_t* edges,
                                     uint64_t* w64, uint32_t* perm, hipStream_t s);
-hipError_t solver_occupancy(int wtype, int wg, int* blocks_per_cu);
+hipError_t solver_occupancy(int wtype, int wg, bool chain, int* blocks_per_cu);
 hipError_t launch_pack_rows(const uint32_t* off, const uint32_t* split, int64_t n, uint4* rows, hipStream_t s);
 hipError_t launch_ctl_reset(Ctl* c, uint32_t groups, int reset_epochs, unsigned long long* trace, uint32_t trace_cap,
                             unsigned long long wait_ticks, hipStream_t s);
 hipError_t launch_fill(uint32_t* p, size_t count, uint32_t value, hipStream_t s);
 // `params` is a device array of one Params per group; grid must be a multiple of
-// groups; wg (kWG or kWGGroups) is the workgroup size. multi = 0: row r of dist
-// holds the distances from sources[r]; multi = 1: one row, the distances from
-// the nearest of the k sources.
+// groups; wg (kWG or kWGGroups) is the workgroup size; chain: the kernel whose
+// leader chains its light steps. multi = 0: row r of dist holds the distances
+// from sources[r]; multi = 1: one row, the distances from the nearest of the k
+// sources.
 hipError_t launch_solver(const Params* params, uint32_t groups, uint32_t wtype, const int32_t* sources, int k,
-                         int multi, void* dist, int grid, int wg, hipStream_t s);
+                         int multi, void* dist, int grid, int wg, bool chain, hipStream_t s);
 
 // validation status bits
 enum : uint32_t {

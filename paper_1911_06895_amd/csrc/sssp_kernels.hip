@@ -81,10 +81,12 @@ struct Queue {
 // default is 512-thread workgroups, two per CU, whose independent schedules
 // overlap each other's latency-bound steps (faster on every workload measured);
 // 1024-thread workgroups, one per CU, can be requested for one source or one
-// multi-source row.
-template <class Wt, uint32_t WG>
+// multi-source row. Chain: the leader chains its light steps (light_chain), a
+// kernel of its own so that the other kernels' code is not changed by it.
+template <class Wt, uint32_t WG, bool Chain = false>
 struct Cfg : Wt {
   static constexpr uint32_t kWG = WG;
+  static constexpr bool kChain = Chain;
   static constexpr uint32_t kPiece = WG * kILP;  // edges of one hub piece (one round of a workgroup)
   static constexpr uint32_t kQueue = WG;         // LDS candidates (one per thread); drained once a quarter full
   // LDS staging for list appends: room for a round and a drain above the flush threshold
@@ -127,6 +129,17 @@ __device__ __attribute__((always_inline)) inline BarrierState& lds_barrier() {
 template <class W>
 __device__ __attribute__((always_inline)) inline Queue<W::kQueue>& lds_queue() {
   __shared__ Queue<W::kQueue> x;
+  return x;
+}
+
+// The frontier of the leader's chained light steps (see light_chain).
+struct ChainList {
+  uint32_t v[kChunk];
+  uint32_t n;  // may pass kChunk: the excess went to the global list
+};
+template <class W>
+__device__ __attribute__((always_inline)) inline ChainList& lds_chain() {
+  __shared__ ChainList x;
   return x;
 }
 
@@ -383,6 +396,25 @@ __device__ void stage_flush_now(uint32_t n) {
   __syncthreads();
 }
 
+// Chained leader steps: append a re-inserted vertex to the LDS frontier;
+// returns true when it was kept there (false: it did not fit, and goes to the
+// global list instead).
+template <class W>
+__device__ inline bool chain_push(bool push, uint32_t v) {
+  ChainList& ch = lds_chain<W>();
+  const uint64_t mask = __ballot(push);
+  if (mask == 0) return false;
+  const int leader = first_lane(mask);
+  uint32_t b = 0;
+  if (static_cast<int>(lane()) == leader) b = atomicAdd(&ch.n, static_cast<uint32_t>(__popcll(mask)));
+  b = __shfl(b, leader);
+  if (!push) return false;
+  const uint32_t i = b + lanes_below(mask);
+  if (i >= kChunk) return false;
+  ch.v[i] = v;
+  return true;
+}
+
 // A relaxation of (v, t(u) (+) w): t(v) = min(t(v), request) (Sec. III-C relax;
 // Sec. IV-C/IV-D t = min(t, t_Req)), then v is filed by the bucket of its new
 // tentative distance: back into the current bucket's frontier (the
@@ -396,7 +428,8 @@ __device__ void stage_flush_now(uint32_t n) {
 // then shared by many requests instead of stalling every round.
 
 // The atomic part for kILP candidates per lane (their atomics overlap in flight).
-template <class W>
+// kChain: the leader's chained light steps keep the re-inserted vertices in LDS.
+template <class W, bool kChain = false>
 __device__ inline void relax_candidates(uint64_t* t, const bool (&active)[kILP],
                                         const typename W::T (&cand)[kILP], const uint32_t (&v)[kILP],
                                         uint64_t near_end) {
@@ -456,7 +489,9 @@ __device__ inline void relax_candidates(uint64_t* t, const bool (&active)[kILP],
   for (uint32_t q = 0; q < kILP; ++q) {
     nwin += static_cast<uint32_t>(__popcll(__ballot(win[q])));
     natt += static_cast<uint32_t>(__popcll(__ballot(active[q])));
-    stage_push<W>(slot[q] != kNoSlot, slot[q], entry[q]);
+    bool kept = false;
+    if constexpr (kChain) kept = chain_push<W>(slot[q] == kSlotFront, entry[q]);
+    stage_push<W>(slot[q] != kNoSlot && !kept, slot[q], entry[q]);
   }
   if (lane() == 0) {
     count_add(&L.st.improvements, nwin);
@@ -485,7 +520,7 @@ __device__ inline bool queue_push(bool pass, uint32_t v, uint64_t c) {
 }
 
 // The prefilter for kILP requests (v, t(u) (+) w) per lane.
-template <class W>
+template <class W, bool kChain = false>
 __device__ inline void relax_batch(uint64_t* t, const bool (&active)[kILP], const typename W::T (&tu)[kILP],
                                    const uint32_t (&v)[kILP], const typename W::Wt (&w)[kILP], uint64_t near_end) {
   const Lds<W> L = lds<W>();
@@ -511,7 +546,7 @@ __device__ inline void relax_batch(uint64_t* t, const bool (&active)[kILP], cons
     direct[q] = queue_push<W>(ok[q] && cand[q] < tv[q], v[q], static_cast<uint64_t>(cand[q]));
     any |= direct[q];
   }
-  if (__ballot(any)) relax_candidates<W>(t, direct, cand, v, near_end);
+  if (__ballot(any)) relax_candidates<W, kChain>(t, direct, cand, v, near_end);
 }
 
 // The staged-append and queue counts as every thread sees them: read between
@@ -535,7 +570,7 @@ __device__ inline void stage_room() {
 
 // Relax the `queued` candidates (read with read_counts) and empty the queue.
 // All threads call it; the staging has room for W::kQueue appends.
-template <class W>
+template <class W, bool kChain = false>
 __device__ void drain_queue(uint64_t* t, uint64_t near_end, uint32_t queued) {
   const Lds<W> L = lds<W>();
   using T = typename W::T;
@@ -552,7 +587,7 @@ __device__ void drain_queue(uint64_t* t, uint64_t near_end, uint32_t queued) {
       v[q] = active[q] ? L.q.v[i] : 0u;
       cand[q] = active[q] ? static_cast<T>(L.q.c[i]) : T(0);
     }
-    relax_candidates<W>(t, active, cand, v, near_end);
+    relax_candidates<W, kChain>(t, active, cand, v, near_end);
   }
   __syncthreads();
   if (threadIdx.x == 0) L.q.n = 0;
@@ -562,8 +597,9 @@ __device__ void drain_queue(uint64_t* t, uint64_t near_end, uint32_t queued) {
 // After a round of relax_batch: make room in the staging for another round,
 // drain the queue once it is a quarter full (an early drain lowers t sooner,
 // so fewer later requests pass the prefilter only to lose), and with `force`
-// (the end of a step) drain and flush everything.
-template <class W>
+// (the end of a step) drain and flush everything (a chain of the leader's
+// steps keeps its appends staged until it ends).
+template <class W, bool kChain = false>
 __device__ inline void round_end(uint64_t* t, uint64_t near_end, bool force) {
   uint32_t staged, queued;
   read_counts<W>(&staged, &queued);
@@ -572,10 +608,10 @@ __device__ inline void round_end(uint64_t* t, uint64_t near_end, bool force) {
     staged = 0;
   }
   if (queued >= (force ? 1u : W::kQueue / 4)) {
-    drain_queue<W>(t, near_end, queued);
+    drain_queue<W, kChain>(t, near_end, queued);
     if (force) read_counts<W>(&staged, &queued);
   }
-  if (force && staged > 0) stage_flush_now<W>(staged);
+  if (force && staged > 0 && !kChain) stage_flush_now<W>(staged);  // a chain defers its appends
 }
 
 // The prefilter's cached loads of t rely on every cached copy being from the
@@ -675,7 +711,7 @@ __device__ void hub_pieces(uint64_t* t, bool light);
 // are prefix-summed in LDS and the lanes walk the concatenated edge ranges, so
 // consecutive lanes read consecutive edges of a row. Vertices with hub_edges
 // or more edges are queued as pieces for a grid-wide hub step instead.
-template <class W, bool kLight>
+template <class W, bool kLight, bool kChain = false>
 __device__ __attribute__((always_inline)) void phase(uint64_t* t, bool solo, bool preloaded = false,
                                                      Entry<typename W::T> pre = Entry<typename W::T>{}) {
   using T = typename W::T;
@@ -799,21 +835,25 @@ __device__ __attribute__((always_inline)) void phase(uint64_t* t, bool solo, boo
           tw[q] = s_tu[at[q]];
         }
       }
-      relax_batch<W>(t, active, tw, v, w, near_end);
-      round_end<W>(t, near_end, false);
+      relax_batch<W, kChain>(t, active, tw, v, w, near_end);
+      round_end<W, kChain>(t, near_end, false);
     }
     __syncthreads();
   }
-  round_end<W>(t, near_end, true);
+  round_end<W, kChain>(t, near_end, true);
 }
+
+template <class W>
+__device__ void light_chain(uint64_t* t, Entry<typename W::T> e);
 
 // The leader's steps run alone (inside the barrier) call this out-of-line
 // copy; the group-wide steps of the kernel's loop have the phase inlined, so
 // that their workgroups do not save and restore registers around a call at
-// every step.
+// every step. With W::kChain a light step starts a chain of them (light_chain).
 template <class W, bool kLight>
 __device__ __attribute__((noinline)) void phase_solo(uint64_t* t, Entry<typename W::T> pre) {
-  phase<W, kLight>(t, true, true, pre);
+  if constexpr (kLight && W::kChain) light_chain<W>(t, pre);
+  else phase<W, kLight>(t, true, true, pre);
 }
 
 // Hub pieces: W::kPiece consecutive edges of the high-degree vertices queued by
@@ -1176,6 +1216,88 @@ __device__ uint32_t step_edges(const uint64_t* t, uint32_t* s_wsum, Entry<typena
   return total;
 }
 
+// The leader's chained light steps. A light step the leader runs alone keeps
+// the vertices it re-inserts in LDS; while they are few enough for another
+// step of its own (the limits of the steps the leader runs alone), the next
+// light phase of the bucket starts from them at once: no list append and
+// read-back, no counter round trip, no schedule publication in between. The
+// schedule in LDS advances as after_step would advance it, and the other
+// appends (S, the ring, the far list) stay staged until the chain ends. Then
+// the LDS frontier goes to the global list as the last step's output, and
+// after_step takes over. Repeated rounds (fp32) run one step at a time.
+constexpr uint32_t kChainMax = 4096;  // steps per chain at most
+template <class W>
+__device__ __attribute__((always_inline)) void light_chain(uint64_t* t, Entry<typename W::T> e) {
+  using T = typename W::T;
+  const Lds<W> L = lds<W>();
+  const Params& p = L.p;
+  Sched& s = L.s;
+  ChainList& ch = lds_chain<W>();
+  Ctl* c = p.ctl;
+  __shared__ uint32_t s_wsum[W::kWG / 64];
+  if (s.redo) {
+    phase<W, true>(t, true, true, e);
+    return;
+  }
+  for (uint32_t k = 0;; ++k) {
+    if (threadIdx.x == 0) ch.n = 0;
+    __syncthreads();
+    phase<W, true, true>(t, true, true, e);
+    __syncthreads();
+    const uint32_t n = ch.n;
+    bool go = false;
+    if (n > 0 && n <= inline_cap(p, grp_size(p)) && k + 1 < kChainMax) {
+      // the next step's entries, one per thread: vertex, distance word, row
+      e = Entry<T>{};
+      uint32_t deg = 0, total;
+      if (threadIdx.x < n) {
+        e.u = ch.v[threadIdx.x];
+        const uint32_t u = e.u & ~kFreshBit;
+        e.word = ld_agent(&t[u]);
+        e.row = ldg(&p.rows[u]);
+        deg = e.row.y - e.row.x;
+        if constexpr (W::kPacked) {
+          if (tag_expanded(static_cast<uint32_t>(e.word))) deg = 0;  // nothing new to send
+        } else {
+          e.te = ld_agent(&texp<W>(p)[u]);
+          if (e.word == e.te) deg = 0;
+        }
+      }
+      (void)block_exclusive_scan<W::kWG>(deg, &total, s_wsum);
+      go = total <= p.inline_edges;
+    }
+    if (!go) {  // the LDS frontier becomes the last step's output list
+      stage_room<W>();
+      const uint32_t kept = min(n, kChunk);
+      stage_push<W>(threadIdx.x < kept, kSlotFront, threadIdx.x < kept ? ch.v[threadIdx.x] : 0u);
+      uint32_t staged, queued;
+      read_counts<W>(&staged, &queued);
+      if (staged > 0) stage_flush_now<W>(staged);
+      return;
+    }
+    // the schedule of the next step, as after_step would set it
+    trace_step_counts<W>(c);
+    if (threadIdx.x == 0) {
+      g_add(&c->light_phases, 1ull);
+      if (k == 0) {  // the first step's input was a global list, now consumed
+        if (s.in_kind == kInBin) st_agent(&c->bincount[s.bucket & p.ring_mask][0], 0u);
+        else st_agent(&c->fcount[s.in_kind], 0u);
+      }
+      s.step += 1u;
+      s.in_kind = s.out_buf;
+      s.in_count = n;
+      s.out_buf = 1u - s.out_buf;
+      if (L.bar.trace) publish_sched(c, s);
+      g_add(&c->heartbeat, 1u);  // the waiting workgroups see progress
+    }
+    // the count reset lands before any later append to that list; fp64: the expansion
+    // records are read back by the next step
+    if (k == 0 || L.bar.trace || !W::kPacked) drain_stores();
+    __syncthreads();
+    if (threadIdx.x == 0) record_trace(c, L.bar.trace, 0x80u);
+  }
+}
+
 // The leader's part of a barrier: schedule the step after `s`; while that step
 // is a small light or heavy phase, run it on this workgroup alone and schedule again.
 template <class W>
@@ -1359,26 +1481,30 @@ hipError_t launch_fill(uint32_t* p, size_t count, uint32_t value, hipStream_t s)
 }
 
 namespace {
-// the solver kernel of a weight type and workgroup size
-template <uint32_t WG>
+// the solver kernel of a weight type, workgroup size and step chaining
+template <uint32_t WG, bool Chain>
 const void* solver_fn(uint32_t wtype) {
-  return wtype == kWU32   ? reinterpret_cast<const void*>(solver_kernel<Cfg<WeightU32, WG>>)
-         : wtype == kWF32 ? reinterpret_cast<const void*>(solver_kernel<Cfg<WeightF32, WG>>)
-                          : reinterpret_cast<const void*>(solver_kernel<Cfg<WeightF64, WG>>);
+  return wtype == kWU32   ? reinterpret_cast<const void*>(solver_kernel<Cfg<WeightU32, WG, Chain>>)
+         : wtype == kWF32 ? reinterpret_cast<const void*>(solver_kernel<Cfg<WeightF32, WG, Chain>>)
+                          : reinterpret_cast<const void*>(solver_kernel<Cfg<WeightF64, WG, Chain>>);
 }
-const void* solver_fn(uint32_t wtype, int wg) { return wg == kWGGroups ? solver_fn<kWGGroups>(wtype) : solver_fn<kWG>(wtype); }
+const void* solver_fn(uint32_t wtype, int wg, bool chain) {
+  if (wg == kWGGroups) return chain ? solver_fn<kWGGroups, true>(wtype) : solver_fn<kWGGroups, false>(wtype);
+  return chain ? solver_fn<kWG, true>(wtype) : solver_fn<kWG, false>(wtype);
+}
 }  // namespace
 
-hipError_t solver_occupancy(int wtype, int wg, int* blocks_per_cu) {
+hipError_t solver_occupancy(int wtype, int wg, bool chain, int* blocks_per_cu) {
   if (wg != kWG && wg != kWGGroups) return hipErrorInvalidValue;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solver_fn(static_cast<uint32_t>(wtype), wg), wg, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solver_fn(static_cast<uint32_t>(wtype), wg, chain),
+                                                      wg, 0);
 }
 
 // One cooperative launch (every workgroup co-resident, which the barriers
 // need). While the stream is being captured into a graph, the launch-attribute
 // form records a cooperative kernel node.
 hipError_t launch_solver(const Params* params, uint32_t groups, uint32_t wtype, const int32_t* sources, int k,
-                         int multi, void* dist, int grid, int wg, hipStream_t s) {
+                         int multi, void* dist, int grid, int wg, bool chain, hipStream_t s) {
   if (groups < 1 || groups > kMaxGroups || grid < 1 || grid % static_cast<int>(groups) != 0) return hipErrorInvalidValue;
   if (wg != kWG && wg != kWGGroups) return hipErrorInvalidValue;
   const Params* pp = params;
@@ -1388,7 +1514,7 @@ hipError_t launch_solver(const Params* params, uint32_t groups, uint32_t wtype, 
   int mm = multi;
   void* d = dist;
   void* args[] = {&pp, &gg, &src, &kk, &mm, &d};
-  const void* fn = solver_fn(wtype, wg);
+  const void* fn = solver_fn(wtype, wg, chain);
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   const hipError_t e = hipStreamIsCapturing(s, &cap);
   if (e != hipSuccess) return e;

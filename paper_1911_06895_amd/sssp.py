@@ -45,7 +45,7 @@ class SsspStats(ctypes.Structure):
 
 
 TUNING_FIELDS = ("workgroups_per_cu", "ring_buckets", "inline_edges", "concurrent_sources", "wait_limit_ms",
-                 "hub_edges", "chunk_entries", "inline_entries")
+                 "hub_edges", "chunk_entries", "inline_entries", "leader_chain")
 
 
 class SsspTuning(ctypes.Structure):

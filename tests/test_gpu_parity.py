@@ -355,8 +355,9 @@ def test_tuning_fields_resolved_and_checked():
         assert t["hub_edges"] == 1024 and t["inline_edges"] == 4096 and t["wait_limit_ms"] == 30000
         assert t["chunk_entries"] in (256, 512) and t["inline_entries"] == t["chunk_entries"]
         assert t["concurrent_sources"] == 1 and t["workgroups_per_cu"] == 2
+        assert t["leader_chain"] == 2  # 8 edges per vertex: one light step at a time by default
         for bad in ({"hub_edges": 100}, {"hub_edges": 3000}, {"chunk_entries": 1024}, {"chunk_entries": 48},
-                    {"inline_entries": 513}, {"wait_limit_ms": -1}):
+                    {"inline_entries": 513}, {"wait_limit_ms": -1}, {"leader_chain": 3}, {"leader_chain": -1}):
             with pytest.raises(sssp.SsspError) as e:
                 solver.set_tuning(**bad)
             assert e.value.status == sssp.SSSP_ERR_INVALID_ARGUMENT, bad
@@ -366,6 +367,41 @@ def test_tuning_fields_resolved_and_checked():
         assert_exact(g, solver.solve_numpy([9])[0], 9)
     finally:
         solver.close()
+
+
+@pytest.mark.parametrize("chain", [1, 2])
+def test_leader_chain_exact(chain):
+    """The leader's chained light steps (leader_chain 1: the re-inserted vertices stay in LDS and the
+    bucket's next light phase starts at once) and one light step at a time (2), each forced on every
+    graph class: R-MAT u32, fp32 log-uniform (repeated rounds), fp64, ER u32 with small inline limits,
+    a grid, and concurrent sources; all equal the oracle's distances."""
+    cases = [
+        (G.rmat_graph(13, 16, cfg=61), 16.0, {}),
+        (G.rmat_graph(12, 16, cfg=62, weights="f32_loguniform", wlo=1e-2, whi=1e2), 0.37, {}),
+        (G.rmat_graph(12, 16, cfg=63, weights="f64", wlo=0.1, whi=10.0), 1.0, {}),
+        (G.er_graph(3000, 12000, cfg=64, wlo=1, whi=100), 40.0, {"inline_entries": 16, "inline_edges": 64}),
+        (G.grid_graph(80, 80, cfg=65), 400.0, {}),
+        (G.grid_graph(48, 48, cfg=66), 100.0, {"concurrent_sources": 4}),
+    ]
+    for g, delta, extra in cases:
+        srcs = G.sources_with_outedges(g, 3, cfg=60)
+        got, st = gpu_solve(g, delta, srcs, tuning={"leader_chain": chain, **extra})
+        for r, s in enumerate(srcs):
+            assert_exact(g, got[r], s, f"{g.name} chain={chain} {extra}")
+        assert st["sources"] == len(srcs)
+
+
+def test_leader_chain_default_by_degree():
+    """Chained light steps are the default on graphs of at most 6 edges per vertex (a grid: 4),
+    one light step at a time on denser ones (R-MAT edge factor 16)."""
+    for g, want in ((G.grid_graph(32, 32, cfg=67), 1), (G.rmat_graph(10, 16, cfg=67), 2)):
+        solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, 64)
+        try:
+            assert sssp.sssp_get_tuning(solver.handle)["leader_chain"] == want, g.name
+            solver.set_tuning(leader_chain=3 - want)
+            assert sssp.sssp_get_tuning(solver.handle)["leader_chain"] == 3 - want
+        finally:
+            solver.close()
 
 
 def test_tuning_variants_agree():
