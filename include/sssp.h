@@ -112,7 +112,8 @@ typedef struct {
                                 power of two in [32, 512] (default 512, 256 in groups of 128 or more
                                 workgroups) */
   int32_t inline_entries;    /* tile schedule: most list entries of a phase that one workgroup runs alone
-                                inside the barrier, in [1, 512] (default: the chunk size) */
+                                inside the barrier, in [1, 512] (default: the chunk size; 512 with
+                                leader_chain 1) */
   int32_t leader_chain;      /* 1: the workgroup running a light phase alone keeps the vertices it
                                 re-inserts in LDS and runs the bucket's next light phase from them at
                                 once while it stays within the two limits above (no list round trip
