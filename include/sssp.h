@@ -101,7 +101,8 @@ typedef struct {
                                 entries) run on one workgroup without a device-wide barrier (default 4096) */
   int32_t concurrent_sources; /* sources solved at the same time, each by its own group of workgroups
                                  (a power of two dividing the launch's workgroup counts, at most 256; default 1).
-                                 Each extra group holds its own working set, about (11 + ring) * 4 * n bytes */
+                                 Each extra group holds its own working set, about (14 + ring) * 4 * n bytes
+                                 (fp64: 2 more) plus m / 13 bytes of hub queues */
   int32_t wait_limit_ms;     /* a device-wide barrier wait that sees neither the release nor progress of the
                                 workgroup running steps alone inside the barrier for this long aborts the
                                 solve with SSSP_ERR_DEVICE instead of hanging (default 30000) */
