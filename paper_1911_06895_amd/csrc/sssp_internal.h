@@ -152,7 +152,7 @@ struct Params {
   const uint64_t* w64;    // [m] fp64 weight bits at the same positions (fp64 handles)
   uint32_t* qstamp;       // [n] frontier tag of the last push
   uint32_t* sstamp;       // [n] round tag of the last S insertion
-  uint32_t* bstamp;       // [n] lowest bucket a vertex was filed under (this solve)
+  uint32_t* bstamp;       // [n] a bucket the vertex was filed under in the ring (this solve; kNone: none)
   uint32_t* fstamp;       // [n] far epoch of the last far insertion
   uint32_t* ovf_at;       // [n] a candidate for this vertex did not fit
   uint32_t* front[2];     // [n] frontier buffers

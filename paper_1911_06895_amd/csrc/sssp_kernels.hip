@@ -477,7 +477,14 @@ __device__ inline void relax_candidates(uint64_t* t, const bool (&active)[kILP],
             if (above_bucket<W>(word_dist<W>(old[q]), s, p)) entry[q] |= kFreshBit;
         }
       } else if (j < near_end) {
-        if (g_min(&p.bstamp[v[q]], j) > j) slot[q] = j & p.ring_mask;
+        // filed under bucket j unless its previous distance was in bucket j already (every
+        // distance in a ring bucket came with a filing there); the stamp only tells the far
+        // redistribution that the vertex has reached the ring
+        const typename W::T od = word_dist<W>(old[q]);
+        if (od == W::kInf || W::bucket(od, p) > j) {
+          slot[q] = j & p.ring_mask;
+          st_agent(&p.bstamp[v[q]], j);
+        }
       } else {
         g_min(&p.ctl->far_min, j);
         if (g_exch(&p.fstamp[v[q]], s.far_epoch) != s.far_epoch) slot[q] = kSlotFar;
