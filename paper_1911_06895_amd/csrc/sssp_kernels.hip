@@ -751,6 +751,9 @@ __device__ __attribute__((always_inline)) void phase(uint64_t* t, bool solo, boo
       const uint32_t listed = preloaded ? pre.u : ld_agent(&list[k]);
       u = listed & ~kFreshBit;
       const uint64_t word = preloaded ? pre.word : ld_agent(&t[u]);
+      // the row does not depend on the distance: both loads are in flight together (a skipped
+      // entry wastes its row load, one round trip less for every other)
+      const uint4 row = preloaded ? pre.row : ldg(&p.rows[u]);
       tu = word_dist<W>(word);
       // a ring slot may hold vertices that have since moved to a lower bucket; a frontier vertex
       // whose light edges were already relaxed with its current distance has nothing new to send
@@ -770,7 +773,6 @@ __device__ __attribute__((always_inline)) void phase(uint64_t* t, bool solo, boo
         if (kLight && take) st_agent(&texp<W>(p)[u], tu);
       }
       if (take) {
-        const uint4 row = preloaded ? pre.row : ldg(&p.rows[u]);
         beg = kLight ? row.x : row.y;
         deg = (kLight ? row.y : row.z) - beg;
       }
