@@ -877,56 +877,89 @@ __device__ void hub_pieces(uint64_t* t, bool light) {
   using T = typename W::T;
   const Params& p = L.p;
   const Sched& s = L.s;
-  __shared__ uint32_t s_beg, s_end, s_claim;
-  __shared__ T s_tu;
+  constexpr uint32_t kPerMax = 2;
+  __shared__ uint32_t s_beg[kPerMax], s_end[kPerMax], s_claim;
+  __shared__ T s_tu[kPerMax];
   const uint64_t* queue = p.hub + static_cast<size_t>(s.hub_in) * p.hub_cap;
   const uint32_t count = s.hub_backlog < p.hub_cap ? s.hub_backlog : p.hub_cap;
   const uint64_t near_end = static_cast<uint64_t>(s.bucket) + p.ring;  // no wrap near 2^32
   const uint32_t size = grp_size(p);
-  // Workgroup b takes piece b, then claims further pieces from a counter.
-  // Thread 0 works one piece ahead: while a piece is relaxed, the next one is
-  // already claimed and its queue record is in flight, so a piece boundary
-  // waits only for the row and t(u) of the next vertex.
+  // A claim takes two consecutive pieces when there are at least eight per
+  // workgroup (their rows and distances then come in one round trip), else
+  // one (the step lasts as long as its busiest workgroup). Workgroup b takes
+  // claim b, then claims further ones from a counter. Thread 0 works one claim
+  // ahead: while a claim is relaxed, the next one is already claimed and its
+  // queue records are in flight, so a claim boundary waits only for the rows
+  // and t(u) of its vertices.
+  const uint32_t per = count >= 8u * size ? 2u : 1u;
+  const uint32_t claims = (count + per - 1) / per;
   uint32_t c = grp_rank(p);
-  uint64_t rec = 0;  // thread 0: queue record of piece c
-  if (threadIdx.x == 0 && c < count) rec = ld_agent(&queue[c]);
-  while (c < count) {
+  uint64_t rec[kPerMax] = {0ull, 0ull};  // thread 0: queue records of claim c
+  if (threadIdx.x == 0 && c < claims) {
+#pragma unroll
+    for (uint32_t q = 0; q < kPerMax; ++q)
+      if (q < per && c * per + q < count) rec[q] = ld_agent(&queue[c * per + q]);
+  }
+  while (c < claims) {
     if (threadIdx.x == 0) {
-      const uint32_t nc = count <= size ? count : size + g_add(&p.ctl->hub_next, 1u);
-      const uint32_t u = static_cast<uint32_t>(rec);
-      const uint32_t piece = static_cast<uint32_t>(rec >> 32);
-      const uint4 row = ldg(&p.rows[u]);
-      const T tu = tload<W>(t, u);
-      rec = nc < count ? ld_agent(&queue[nc]) : 0ull;
-      const uint32_t b = light ? row.x : row.y;
-      const uint32_t e = light ? row.y : row.z;
-      const uint32_t pb = b + piece * W::kPiece;
-      s_beg = pb;
-      s_end = e - pb > W::kPiece ? pb + W::kPiece : e;
-      s_tu = tu;
+      const uint32_t nc = claims <= size ? claims : size + g_add(&p.ctl->hub_next, 1u);
+      uint4 row[kPerMax];
+      T tu[kPerMax];
+      uint32_t piece[kPerMax];
+      bool valid[kPerMax];
+#pragma unroll
+      for (uint32_t q = 0; q < kPerMax; ++q) {
+        valid[q] = q < per && c * per + q < count;
+        const uint32_t u = static_cast<uint32_t>(rec[q]);
+        piece[q] = static_cast<uint32_t>(rec[q] >> 32);
+        if (valid[q]) {
+          row[q] = ldg(&p.rows[u]);
+          tu[q] = tload<W>(t, u);
+        }
+      }
+#pragma unroll
+      for (uint32_t q = 0; q < kPerMax; ++q)
+        rec[q] = q < per && nc < claims && nc * per + q < count ? ld_agent(&queue[nc * per + q]) : 0ull;
+#pragma unroll
+      for (uint32_t q = 0; q < kPerMax; ++q) {
+        s_beg[q] = s_end[q] = 0;
+        if (valid[q]) {
+          const uint32_t b = light ? row[q].x : row[q].y;
+          const uint32_t e = light ? row[q].y : row[q].z;
+          const uint32_t pb = b + piece[q] * W::kPiece;
+          s_beg[q] = pb;
+          s_end[q] = e - pb > W::kPiece ? pb + W::kPiece : e;
+          s_tu[q] = tu[q];
+        }
+      }
       s_claim = nc;
     }
     __syncthreads();
     c = s_claim;
-    bool active[kILP];
-    uint32_t v[kILP];
-    typename W::Wt w[kILP];
-    T tw[kILP];
+    for (uint32_t q = 0; q < per; ++q) {
+      const uint32_t pbeg = s_beg[q], pend = s_end[q];
+      if (pbeg >= pend) continue;  // the last claim's missing second piece
+      bool active[kILP];
+      uint32_t v[kILP];
+      typename W::Wt w[kILP];
+      T tw[kILP];
 #pragma unroll
-    for (uint32_t q = 0; q < kILP; ++q) {
-      const uint32_t e = s_beg + q * W::kWG + threadIdx.x;
-      active[q] = e < s_end;
-      v[q] = 0;
-      w[q] = 0;
-      tw[q] = s_tu;
-      if (active[q]) {
-        const uint64_t ed = ldg(&p.edges[e]);
-        v[q] = static_cast<uint32_t>(ed);
-        w[q] = W::weight(p, ed, e);
+      for (uint32_t i = 0; i < kILP; ++i) {
+        const uint32_t e = pbeg + i * W::kWG + threadIdx.x;
+        active[i] = e < pend;
+        v[i] = 0;
+        w[i] = 0;
+        tw[i] = s_tu[q];
+        if (active[i]) {
+          const uint64_t ed = ldg(&p.edges[e]);
+          v[i] = static_cast<uint32_t>(ed);
+          w[i] = W::weight(p, ed, e);
+        }
       }
+      relax_batch<W>(t, active, tw, v, w, near_end);
+      round_end<W>(t, near_end, false);
     }
-    relax_batch<W>(t, active, tw, v, w, near_end);
-    round_end<W>(t, near_end, false);
+    __syncthreads();  // every thread has read this claim's pieces before thread 0 writes the next
   }
   round_end<W>(t, near_end, true);
 }
