@@ -123,11 +123,13 @@ def test_rmat_s14(delta):
     assert st["light_edges"] >= light
 
 
-def _heavy_phase_records(g, delta, src):
+def _heavy_phase_records(g, delta, src, tuning=None):
     """(bucket, input entries) of every heavy phase of one traced solve: the input of bucket i's
     heavy phase is S_i, the vertices expanded in bucket i (Sec. IV-D)."""
     solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, delta)
     try:
+        if tuning:
+            solver.set_tuning(**tuning)
         cap = 1 << 16
         buf = torch.zeros(4 * cap, dtype=torch.int64, device="cuda")
         sssp.sssp_set_trace(solver.handle, buf, cap)
@@ -146,11 +148,13 @@ def _heavy_phase_records(g, delta, src):
     return d, bucket[heavy], entries[heavy]
 
 
-@pytest.mark.parametrize("kind,delta", [("rmat", 8), ("rmat", 32), ("rmat", 128), ("grid", 50), ("er", 16)])
-def test_bucket_schedule_matches_oracle_trace(kind, delta):
+@pytest.mark.parametrize("kind,delta,chain", [("rmat", 8, 0), ("rmat", 32, 0), ("rmat", 128, 0), ("grid", 50, 0),
+                                              ("er", 16, 0), ("rmat", 32, 1), ("er", 16, 1), ("grid", 50, 2)])
+def test_bucket_schedule_matches_oracle_trace(kind, delta, chain):
     """Schedule invariants of Fig. 1 on the GPU (integer weights, where no bucket is repeated):
     the non-empty buckets and each |S_i| equal those of the oracle's literal linear-algebra run,
-    and S_i = {v : floor(d(v) / delta) = i}."""
+    and S_i = {v : floor(d(v) / delta) = i}; with the library's default for the graph (chain 0),
+    and with the leader's chained light steps forced on (1) or off (2)."""
     if kind == "rmat":
         g = G.rmat_graph(14, 16, cfg=2)
     elif kind == "grid":
@@ -158,7 +162,7 @@ def test_bucket_schedule_matches_oracle_trace(kind, delta):
     else:
         g = G.workload("er_n1024_m8192")
     src = int(G.sources_with_outedges(g, 1, cfg=7)[0])
-    d, buckets, sizes = _heavy_phase_records(g, delta, src)
+    d, buckets, sizes = _heavy_phase_records(g, delta, src, {"leader_chain": chain} if chain else None)
     want_d, rc, tr = oracle.delta_stepping_la(g, delta, src)
     assert rc == oracle.OK and np.array_equal(d, want_d)
     nz = sizes > 0  # a bucket whose ring slot held only vertices that had moved lower expands nothing
