@@ -613,6 +613,7 @@ def main():
     torch.cuda.synchronize()
     ms_one_launch = e0.elapsed_time(e1) / args.steps
     st = sssp.sssp_last_stats(handle)
+    tuning_main = sssp.sssp_get_tuning(handle)  # the handle is released before the modes run
     rows = host_rows()
     m_rows = np.array([reached_edges(g, row) for row in rows], dtype=np.float64)
     b_rows = np.array([algorithmic_bytes(g, row, 0) for row in rows]) + 4.0 * st["improvements"] / len(sources)
@@ -685,7 +686,7 @@ def main():
                    "gteps_min_max": [round(float(gteps_rows.min()), 3), round(float(gteps_rows.max()), 3)],
                    "one_launch_all_sources": {"ms": round(ms_one_launch, 3),
                                               "gteps": round(float(m_rows.sum()) / ms_one_launch / 1e6, 3)},
-                   "tuning": sssp.sssp_get_tuning(handle) if handle is not None else None,
+                   "tuning": tuning_main,
                    "delta_sweep": sweep, "oracle_checked_sources": checked},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
