@@ -145,6 +145,7 @@ struct Params {
   double delta_d;       // f32: (double)(float)delta; f64: delta
   double inv_delta_d;   // 1 / delta_d (an estimate; bucket indices are corrected exactly)
   const uint32_t* vid;    // [n] solver id of each caller vertex (decreasing in-degree order)
+  uint32_t zero_from;     // solver ids from here on have no in-edges (reachable only as a seed)
   void* tbuf[2];          // [n] 64-bit tentative-distance words in solver ids (alternating between sources)
   void* texp;             // fp64: [n] distance of each vertex at its last light expansion in the current row
   const uint4* rows;      // [n] row u of the split copy: (start, end of light edges, end, 0)
@@ -208,6 +209,9 @@ hipError_t launch_validate_weights(const void* w, int wtype, int64_t m, uint32_t
 hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, const void* w, int wtype, int64_t n,
                            int64_t m, uint32_t* status, unsigned long long* wmax_bits, double* wsum, hipStream_t s);
 size_t build_scratch_words(int64_t n);
+// After launch_relabel_and_split, this word of its scratch holds the number of vertices with at
+// least one in-edge (their solver ids come first).
+inline size_t relabel_positive_count_word(int64_t n) { return static_cast<size_t>(n) + kDegClasses; }
 hipError_t launch_relabel_and_split(const int64_t* row_ptr, const int32_t* col, const void* w, const Threshold& th,
                                     int64_t n, int64_t m, uint32_t* scratch,
                                     uint32_t* new_id, uint32_t* off, uint32_t* split, uint64_t* edges,

@@ -1450,8 +1450,27 @@ __global__ __launch_bounds__(W::kWG, 4) void solver_kernel(const Params* __restr
     }
     if (alive) {  // the source's row of the output, in the caller's vertex numbering
       T* out = static_cast<T*>(dist) + static_cast<size_t>(row) * p.n;
-      for (uint32_t v = rank * W::kWG + threadIdx.x; v < p.n; v += size * W::kWG)
-        *gp(&out[v]) = tload<W>(t, ldg(&p.vid[v]));
+      // a vertex without in-edges is reached only as a seed: a one-source row gives the others
+      // infinity without reading t (about half the vertices of an R-MAT graph); four vertices per
+      // thread are read before any is written, so their round trips overlap
+      const uint32_t src = multi ? kNone : static_cast<uint32_t>(ldg(&sources[row]));
+      const uint32_t zf = multi ? p.n : p.zero_from;
+      const uint32_t stride = size * W::kWG;
+      uint32_t v = rank * W::kWG + threadIdx.x;
+      for (; v + 3u * stride < p.n; v += 4u * stride) {
+        uint32_t id[4];
+        T d[4];
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) id[q] = ldg(&p.vid[v + q * stride]);
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) d[q] = id[q] < zf || v + q * stride == src ? tload<W>(t, id[q]) : W::kInf;
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) *gp(&out[v + q * stride]) = d[q];
+      }
+      for (; v < p.n; v += stride) {
+        const uint32_t id = ldg(&p.vid[v]);
+        *gp(&out[v]) = id < zf || v == src ? tload<W>(t, id) : W::kInf;
+      }
     }
   }
   // add this workgroup's counters to the group's control block

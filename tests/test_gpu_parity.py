@@ -81,6 +81,42 @@ def test_multi_source_rows():
     assert st["sources"] == len(srcs)
 
 
+@pytest.mark.parametrize("wkind", ["u32", "f32", "f64"])
+def test_sources_without_in_edges(wkind):
+    """Vertices without in-edges are reached only as seeds (the output copy gives the others
+    infinity without reading their distance): a source with no in-edges, a row whose source has
+    in-edges, rows of invalid sources, and a nearest-source solve whose seeds have no in-edges."""
+    r = G.rng_for(77, G.S_STRUCT)
+    n, m = 3000, 9000
+    src = r.integers(0, n // 2, size=m)          # in-edges only into the upper half, out-edges from
+    dst = r.integers(n // 3, n, size=m)          # the lower half: many vertices have no in-edges
+    w = {"u32": r.integers(1, 100, size=m).astype(np.uint32),
+         "f32": r.uniform(0.5, 4.0, size=m).astype(np.float32),
+         "f64": r.uniform(0.5, 4.0, size=m)}[wkind]
+    g = G.csr_from_edges(n, src, dst, w)
+    indeg = np.bincount(g.col, minlength=n)
+    outdeg = np.diff(g.row_ptr)
+    no_in = np.nonzero((indeg == 0) & (outdeg > 0))[0]
+    with_in = np.nonzero((indeg > 0) & (outdeg > 0))[0]
+    assert no_in.size > 10 and with_in.size > 10
+    srcs = [int(no_in[0]), int(with_in[0]), int(no_in[-1])]
+    got, _ = gpu_solve(g, 8.0, srcs)
+    for row, s0 in enumerate(srcs):
+        assert_exact(g, got[row], s0, f"{wkind} no-in-edges")
+        assert got[row][s0] == 0
+    solver = sssp.DeltaStepping(g.row_ptr, g.col, g.w, 8.0)
+    try:
+        seeds = [int(x) for x in no_in[:5]]
+        d = solver.solve_multi(seeds).cpu().numpy()
+        if d.dtype == np.int32:  # u32 distances come back in an int32 tensor
+            d = d.view(np.uint32)
+        want = np.stack([oracle.dijkstra(g, x)[0] for x in seeds]).min(axis=0)
+        assert np.array_equal(_bits(d), _bits(want))
+        assert all(d[x] == 0 for x in seeds)
+    finally:
+        solver.close()
+
+
 @pytest.mark.parametrize("seed", range(12))
 def test_random_graphs_ragged(seed):
     """Sizes that span several 256-entry tiles with a ragged tail, raw CSR (parallel
