@@ -508,11 +508,10 @@ sssp_status create_impl(const sssp_graph* g, double delta, hipStream_t stream, s
     h->adj_grid = occ >= 1 ? h->cus : 0;
   }
   if (be == hipSuccess) be = hipStreamSynchronize(stream);
-  uint32_t with_in_edges = static_cast<uint32_t>(n);
+  uint32_t no_in_edges = 0;
   if (be == hipSuccess)
-    be = hipMemcpy(&with_in_edges, build + sssp::relabel_positive_count_word(n), sizeof(uint32_t),
-                   hipMemcpyDeviceToHost);
-  p.zero_from = with_in_edges <= static_cast<uint32_t>(n) ? with_in_edges : static_cast<uint32_t>(n);
+    be = hipMemcpy(&no_in_edges, build + sssp::relabel_no_in_edges_word(n), sizeof(uint32_t), hipMemcpyDeviceToHost);
+  p.zero_from = static_cast<uint32_t>(n) - (no_in_edges <= static_cast<uint32_t>(n) ? no_in_edges : 0u);
   (void)hipFree(build);
   SSSP_TRY(be);
   const sssp_status st = configure_grid(h);

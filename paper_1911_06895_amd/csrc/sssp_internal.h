@@ -209,9 +209,9 @@ hipError_t launch_validate_weights(const void* w, int wtype, int64_t m, uint32_t
 hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, const void* w, int wtype, int64_t n,
                            int64_t m, uint32_t* status, unsigned long long* wmax_bits, double* wsum, hipStream_t s);
 size_t build_scratch_words(int64_t n);
-// After launch_relabel_and_split, this word of its scratch holds the number of vertices with at
-// least one in-edge (their solver ids come first).
-inline size_t relabel_positive_count_word(int64_t n) { return static_cast<size_t>(n) + kDegClasses; }
+// After launch_relabel_and_split, this word of its scratch holds the number of vertices without
+// in-edges (the in-degree histogram's first class; their solver ids come last).
+inline size_t relabel_no_in_edges_word(int64_t n) { return static_cast<size_t>(n); }
 hipError_t launch_relabel_and_split(const int64_t* row_ptr, const int32_t* col, const void* w, const Threshold& th,
                                     int64_t n, int64_t m, uint32_t* scratch,
                                     uint32_t* new_id, uint32_t* off, uint32_t* split, uint64_t* edges,
