@@ -42,7 +42,7 @@ typedef enum {
                                     without progress past its limit, or an internal queue over capacity) */
   SSSP_ERR_OVERFLOW = 5,         /* a reachable vertex's distance is not representable */
   SSSP_ERR_NO_FORWARD = 6,       /* sssp_backward before any successful sssp_solve */
-  SSSP_ERR_UNSUPPORTED = 7,      /* a size or type outside what this build handles */
+  SSSP_ERR_UNSUPPORTED = 7,      /* a size or type outside what the library handles */
 } sssp_status;
 
 typedef enum {

@@ -1,5 +1,5 @@
 // Schedule autotuner: the method has one knob, delta (the bucket width, which
-// also decides which edges are light, Sec. III-A/IV-A); this build adds its
+// also decides which edges are light, Sec. III-A/IV-A); the library adds its
 // own: the number of sources solved concurrently and the tile schedule (the
 // workgroup size, the hub threshold, the chunk size, the largest step run by
 // one workgroup alone). sssp_autotune times solves of a sample of sources:
